@@ -1,0 +1,145 @@
+"""Seeded synthetic inputs shared by the oracle side and the HIP side.
+
+This module holds no arithmetic of the lattice Boltzmann method. It draws the
+initial density fields, builds the per-column external force tables the step
+takes as input, looks up the stencil parameters of the paper's Table 1, and
+names the benchmark workloads. Both the tests of the oracle and the tests of
+the HIP library import it; it imports neither of them.
+
+Conventions (lattice units unless noted):
+* density n is the paper's reduced density n / n_c; a van der Waals fluid
+  with parameters (a, b) maps onto it by n = 3 b rho, so rho = 1/(3b) is n = 1;
+* the external force table fext[x] is a force density in the paper's units,
+  one value per column x = 0 .. Lx-1;
+* T is T / T_c; tau and kappa are in the paper's units.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, asdict
+from typing import List, Optional
+
+import numpy as np
+
+# Table 1 of the paper: optimal (N, Q) for kappa = 0.3, per temperature.
+TABLE1_OVC = {0.83: (0.3, 2.1), 0.85: (0.3, 2.3), 0.87: (0.3, 2.5), 0.89: (0.3, 2.6),
+              0.91: (0.3, 2.5), 0.93: (0.3, 1.9), 0.95: (0.3, 2.0), 0.97: (0.3, 0.0),
+              0.98: (0.3, 3.9), 0.99: (0.5, 2.1)}
+TABLE1_ODC = {0.83: (0.3, 2.1), 0.85: (0.3, 2.3), 0.87: (0.3, 2.5), 0.89: (0.3, 2.7),
+              0.91: (0.4, 1.7), 0.93: (0.4, 1.9), 0.95: (0.4, 2.1), 0.97: (0.0, 0.0),
+              0.98: (0.3, 3.9), 0.99: (1.0, 1.0)}
+STANDARD_CHOICE = (0.5, 1.0)  # central differences: M = 0, R = 0
+
+
+def table1_nq(T: float, choice: str = "OVC"):
+    """(N, Q) of Table 1 at the tabulated temperature nearest to T; a tie goes
+    to the lower temperature (so 0.90 -> 0.89)."""
+    tab = TABLE1_OVC if choice.upper() == "OVC" else TABLE1_ODC
+    keys = sorted(tab)
+    best = min(keys, key=lambda t: (round(abs(t - T), 12), t))
+    return tab[best]
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def noisy_density(Lx: int, Ly: int, seed: int, mean: float = 1.0, amp: float = 0.01) -> np.ndarray:
+    """n0[y, x] = mean + U(-amp, amp), drawn from PCG64(seed) in row order."""
+    return mean + rng(seed).uniform(-amp, amp, size=(Ly, Lx))
+
+
+def potential_force(Lx: int, V0: float, k: int) -> np.ndarray:
+    """Force table of the periodic potential V(x) = V0 sin(2 pi k x / Lx):
+    fext[x] = -dV/dx = -(2 pi k V0 / Lx) cos(2 pi k x / Lx)."""
+    x = np.arange(Lx, dtype=np.float64)
+    return -(2.0 * math.pi * k * V0 / Lx) * np.cos(2.0 * math.pi * k * x / Lx)
+
+
+def sine_force(Lx: int, A0: float, lam: float) -> np.ndarray:
+    """The paper's literal form F_ext,x = A0 sin(2 pi x / lambda) (Sec. II)."""
+    x = np.arange(Lx, dtype=np.float64)
+    return A0 * np.sin(2.0 * math.pi * x / lam)
+
+
+def flat_interface(Lx: int, Ly: int, n_lo: float, n_hi: float, axis: str = "x",
+                   width: float = 2.0) -> np.ndarray:
+    """Two smooth planar interfaces (periodic): the middle half holds n_hi,
+    the rest n_lo. axis='x' varies along x, axis='y' along y."""
+    L = Lx if axis == "x" else Ly
+    s = np.arange(L, dtype=np.float64)
+    prof = n_lo + 0.5 * (n_hi - n_lo) * (np.tanh((s - L / 4) / width) - np.tanh((s - 3 * L / 4) / width))
+    return np.tile(prof, (Ly, 1)) if axis == "x" else np.tile(prof[:, None], (1, Lx))
+
+
+def droplet(Lx: int, Ly: int, R: float, n_in: float, n_out: float, width: float = 1.0) -> np.ndarray:
+    """Disc of radius R centred in a periodic box, tanh edge."""
+    y, x = np.mgrid[0:Ly, 0:Lx].astype(np.float64)
+    r = np.hypot(x - (Lx - 1) / 2, y - (Ly - 1) / 2)
+    return n_out + 0.5 * (n_in - n_out) * (1.0 - np.tanh((r - R) / width))
+
+
+@dataclass
+class Workload:
+    """One lattice: sizes, physics parameters and the input recipe."""
+    name: str
+    Lx: int
+    Ly: int
+    T: float = 0.95
+    tau: float = 1.0
+    kappa: float = 0.3
+    V0: float = 0.0
+    k: int = 1
+    U: float = 0.0
+    y_periodic: bool = False
+    seed: int = 1307
+    steps: int = 100
+    fp32: bool = False
+    N: Optional[float] = None
+    Q: Optional[float] = None
+
+    def __post_init__(self):
+        if self.N is None or self.Q is None:
+            self.N, self.Q = table1_nq(self.T)
+
+    def n0(self) -> np.ndarray:
+        return noisy_density(self.Lx, self.Ly, self.seed)
+
+    def fext(self) -> np.ndarray:
+        return potential_force(self.Lx, self.V0, self.k)
+
+    @property
+    def nodes(self) -> int:
+        return self.Lx * self.Ly
+
+    def as_dict(self):
+        return asdict(self)
+
+
+# The five workloads. Small parity case first; the single-GPU roofline case
+# is the large lattice.
+PARITY_FP64 = Workload("lb-fp64-128x64-walls", 128, 64, T=0.95, V0=0.05, k=4, U=0.01,
+                       steps=2000, seed=1307)
+FP32_VS_FP64 = [Workload(f"lb-fp32-1024x256-T{T}-U{U}-s{s}", 1024, 256, T=T, V0=0.1, k=8,
+                         U=U, steps=50000, seed=s, fp32=True)
+                for T in (0.90, 0.95) for U in (0.005, 0.05) for s in (1, 2, 3, 4)]
+ROOFLINE = Workload("lb-fp32-8192x2048-walls", 8192, 2048, T=0.90, V0=0.1, k=32, U=0.08,
+                    steps=10000, seed=1307, fp32=True)
+
+
+def batch_draws(count: int = 96, seed: int = 1307) -> List[Workload]:
+    """Instances of the batched sweep. Draw order per instance: Lx, Ly, T, V0,
+    k, U, noise seed."""
+    g = rng(seed)
+    out = []
+    for i in range(count):
+        Lx = int(g.choice([128, 256, 512, 1024]))
+        Ly = int(g.choice([64, 128, 256]))
+        T = float(g.uniform(0.85, 0.98))
+        V0 = float(g.uniform(0.0, 0.2))
+        k = int(g.choice([2, 4, 8]))
+        U = float(g.uniform(0.0, 0.08))
+        s = int(g.integers(0, 2**31 - 1))
+        out.append(Workload(f"batch-{i}", Lx, Ly, T=T, V0=V0, k=k, U=U, seed=s,
+                            steps=20000, fp32=True))
+    return out

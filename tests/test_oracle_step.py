@@ -1,0 +1,270 @@
+"""Pins of the oracle's whole time step against what the paper and the
+mathematics fix: conservation, closed-form flows, the wall rule, exact
+properties of the discrete steady state, symmetries, and the paper's printed
+numbers."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import lbsynth as ls
+from oracle import closed_forms as cf
+from oracle.lb_oracle import CX, CY, OracleLB, Params
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _noisy(Lx, Ly, seed=11):
+    return ls.noisy_density(Lx, Ly, seed)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_mass_is_conserved(periodic):
+    # The wall rule keeps the mass exactly (n-hat, Sec. II) and collisions
+    # conserve it (A = 0 in Eq.(coeff)).
+    p = Params(48, 24, T=0.95, N=0.3, Q=2.0, U=0.03, y_periodic=periodic)
+    o = OracleLB(p, _noisy(48, 24), fext=ls.potential_force(48, 0.1, 2))
+    m0 = o.mass()
+    o.run(400, threads=2)
+    assert abs(o.mass() - m0) / m0 < 1e-13
+    # the moments of the last step integrate to the same mass
+    assert abs(o.n.sum() - m0) / m0 < 1e-13
+
+
+def _stream_known(S, y):
+    """Populations arriving at row y of a wall lattice (pull streaming)."""
+    out = {}
+    Ly = S.shape[1]
+    for i in range(9):
+        sy = y - CY[i]
+        if 0 <= sy < Ly:
+            out[i] = np.roll(S[i, sy], CX[i])
+    return out
+
+
+def test_wall_nodes_take_wall_density_and_velocity():
+    # Sec. II: after the wall rule, the lower-wall node has density n-hat =
+    # f0 + f4 + f7 + f8 (its own, previous step, not streamed) + f1 + f3 + f4 +
+    # f7 + f8 (streamed), and moves with the wall: u*_x = -U, u*_y = 0. The
+    # upper wall is the mirror image (+U).
+    Lx, Ly, U = 20, 12, 0.04
+    p = Params(Lx, Ly, T=0.95, N=0.3, Q=2.0, U=U)
+    o = OracleLB(p, _noisy(Lx, Ly), fext=ls.potential_force(Lx, 0.1, 1))
+    o.run(7)
+    S = o.S.copy()
+    o.run(1)
+    lo_in, hi_in = _stream_known(S, 0), _stream_known(S, Ly - 1)
+    nhat_lo = S[0, 0] + S[4, 0] + S[7, 0] + S[8, 0] + sum(lo_in[i] for i in (1, 3, 4, 7, 8))
+    nhat_hi = S[0, -1] + S[2, -1] + S[5, -1] + S[6, -1] + sum(hi_in[i] for i in (1, 3, 2, 5, 6))
+    assert np.allclose(o.n[0], nhat_lo, atol=1e-14)
+    assert np.allclose(o.n[-1], nhat_hi, atol=1e-14)
+    assert np.allclose(o.ux[0], -U, atol=1e-15) and np.allclose(o.ux[-1], U, atol=1e-15)
+    assert np.allclose(o.uy[0], 0, atol=1e-15) and np.allclose(o.uy[-1], 0, atol=1e-15)
+    # bulk rows: n is the plain sum of streamed populations
+    mid = _stream_known(S, Ly // 2)
+    assert np.allclose(o.n[Ly // 2], sum(mid.values()), atol=1e-14)
+
+
+def test_couette_profile():
+    # Sec. IV: a homogeneous fluid between the moving walls relaxes to the
+    # linear Couette profile; lattice units, wall nodes at rows 0 and Ly-1.
+    Ly, U = 16, 0.01
+    p = Params(3, Ly, T=0.95, N=0.3, Q=2.0, U=U)
+    o = OracleLB(p, np.full((Ly, 3), 0.5))
+    tS = (Ly - 1) ** 2 / (cf.kinematic_viscosity(1.0) * math.pi**2)
+    o.run(int(40 * tS))
+    assert np.abs(o.ux - cf.couette(Ly, U)[:, None]).max() < 1e-10
+    assert np.abs(o.uy).max() < 1e-12
+
+
+def _shear_wave_rate(L, tau):
+    p = Params(1, L, T=0.95, tau=tau, N=0.3, Q=2.0, y_periodic=True)
+    y = np.arange(L)
+    s = np.sin(2 * math.pi * y / L)
+    o = OracleLB(p, np.full((L, 1), 0.5), ux0=1e-5 * s[:, None])
+    o.run(40)
+    a1 = o.ux[:, 0] @ s
+    o.run(200)
+    a2 = o.ux[:, 0] @ s
+    return math.log(a1 / a2) / 200
+
+
+@pytest.mark.parametrize("tau", [1.0, 2.0])
+def test_shear_wave_viscosity(tau):
+    # Sec. II: eta = n (tau - dt/2), i.e. nu_l = (tau_l - 1/2)/3 per step in
+    # lattice units. The discrete rate approaches nu k^2 with an O(k^2)
+    # relative error: check the limit and the order.
+    r128, r256 = _shear_wave_rate(128, tau), _shear_wave_rate(256, tau)
+    e128 = r128 / cf.shear_wave_rate(tau, 128) - 1
+    e256 = r256 / cf.shear_wave_rate(tau, 256) - 1
+    assert abs(e256) < 2e-3
+    assert 3.5 < e128 / e256 < 4.5            # second-order convergence
+    extrap = (4 * r256 - r128 / 4) / 3 / cf.shear_wave_rate(tau, 256) - 1
+    assert abs(extrap) < 5e-5
+
+
+def _flat(T, N, Q, tau=1.0, Lx=96, steps=24000):
+    nl, nv, _ = cf.maxwell(T)
+    p = Params(Lx, 4, T=T, tau=tau, N=N, Q=Q, y_periodic=True)
+    o = OracleLB(p, ls.flat_interface(Lx, 4, nv, nl, axis="x"))
+    o.run(steps)
+    return o
+
+
+def test_discrete_steady_state_identity():
+    # Consequence of Eq.(evoleq), Eq.(eqfunc), Eq.(forceterm) and
+    # Eq.(newvel) for a steady state at rest that varies along x only: summing
+    # the populations by c_x, the collision and streaming leave
+    #   T (n(x+1) - n(x)) = (F_p(x+1) + F_p(x)) / 2,
+    # where F_p is the force density of Eq.(force2) in paper units; the
+    # relaxation time drops out.
+    T, kappa = 0.95, 0.3
+    o = _flat(T, 0.3, 2.0)
+    n = o.n[0]
+    assert np.abs(o.ux).max() < 1e-12
+    P = n * T - cf.p_vdw(n, T)
+    L = np.roll(n, -1) + np.roll(n, 1) - 2 * n
+    Fp = 0.5 * (np.roll(P, -1) - np.roll(P, 1)) + kappa * n * 0.5 * (np.roll(L, -1) - np.roll(L, 1))
+    lhs = T * (np.roll(n, -1) - n)
+    rhs = 0.5 * (np.roll(Fp, -1) + Fp)
+    assert np.abs(lhs - rhs).max() < 1e-12
+
+
+def test_flat_interface_independent_of_tau_and_stencil():
+    # Sec. III: the phase diagram does not depend on tau. For a planar
+    # interface along a lattice axis the (N, Q) choice folds away too.
+    ref = _flat(0.95, 0.3, 2.0).n
+    assert np.abs(_flat(0.95, 0.3, 2.0, tau=2.0).n - ref).max() < 1e-11
+    assert np.abs(_flat(0.95, 0.4, 2.1).n - ref).max() < 1e-11
+    assert np.abs(_flat(0.95, 0.5, 1.0).n - ref).max() < 1e-11
+
+
+def test_flat_interface_approaches_maxwell():
+    # Sec. III: bulk densities of a relaxed planar interface approach the
+    # Maxwell construction. The scheme's discretisation error shrinks as the
+    # interface widens toward the critical point.
+    rel = []
+    for T in (0.95, 0.97, 0.99):
+        o = _flat(T, *ls.table1_nq(T), Lx=160, steps=60000)
+        nl, nv, _ = cf.maxwell(T)
+        dl, dv = o.n[0, 80] - nl, o.n[0, 0] - nv
+        if T == 0.95:
+            assert abs(dl) < 1.2e-2 and abs(dv) < 2.0e-2
+        rel.append(max(abs(dl), abs(dv)) / (nl - nv))
+    assert rel[0] > rel[1] > rel[2]
+    assert rel[2] < 1e-2
+
+
+def test_maxwell_matches_printed_values():
+    # Caption of Fig. 4: n_L_th = 1.461727, n_V_th = 0.579015 at T = 0.95.
+    rows = np.loadtxt(os.path.join(GOLDEN, "maxwell_T095.txt"))
+    T, nl_p, nv_p = rows
+    nl, nv, _ = cf.maxwell(T)
+    assert abs(nl - nl_p) < 5e-7 and abs(nv - nv_p) < 5e-7
+
+
+@pytest.mark.slow
+def test_droplet_matches_printed_densities():
+    # Sec. III, Figs. 3-4 and 12: droplet of radius 15 at T = 0.95, OVC
+    # stencil; printed bulk densities 1.462721 / 0.580015 and spurious
+    # velocities of about 0.002. The paper gives no box size (80 x 80 here).
+    T, R, nl_p, nv_p, umax_p = np.loadtxt(os.path.join(GOLDEN, "droplet_T095.txt"))
+    nl, nv, _ = cf.maxwell(T)
+    L = 80
+    N, Q = ls.table1_nq(T)
+    p = Params(L, L, T=T, N=N, Q=Q, y_periodic=True)
+    o = OracleLB(p, ls.droplet(L, L, R, nl, nv))
+    o.run(3000, threads=8)
+    c = L // 2
+    assert abs(o.n[c, c] - nl_p) < 5e-3
+    assert abs(o.n[0, 0] - nv_p) < 5e-3
+    umax = np.hypot(o.ux, o.uy).max()
+    assert umax_p / 2 < umax < umax_p * 2
+
+
+@pytest.mark.slow
+def test_laplace_pressure_decreases_with_radius():
+    # Laplace law in d = 2: the pressure jump across a droplet falls as 1/R.
+    # The slope is the scheme's surface tension; at T = 0.95 and kappa = 0.3
+    # the interface spans only a few nodes, so only a loose bound on it holds.
+    T = 0.95
+    nl, nv, _ = cf.maxwell(T)
+    sig = cf.surface_tension(T, 0.3)
+    Rs, dps = [16, 24, 32], []
+    for R in Rs:
+        L = 4 * R
+        p = Params(L, L, T=T, N=0.3, Q=2.0, y_periodic=True)
+        o = OracleLB(p, ls.droplet(L, L, R, nl, nv))
+        o.run(5000, threads=8)
+        c = L // 2
+        dps.append(cf.p_vdw(o.n[c, c], T) - cf.p_vdw(o.n[0, 0], T))
+    assert dps[0] > dps[1] > dps[2] > 0
+    slope = np.polyfit(1.0 / np.array(Rs), dps, 1)[0]
+    assert 0.3 * sig < slope < 1.5 * sig
+
+
+def _run(p, n0, fext, steps, ux0=None, uy0=None):
+    o = OracleLB(p, n0, ux0=ux0, uy0=uy0, fext=fext)
+    o.run(steps)
+    return o
+
+
+def test_mirror_symmetry_x():
+    # Reflecting x maps a solution onto a solution: n(x) -> n(-x), u_x -> -u_x,
+    # external force -> -F(-x), wall speed -> -U.
+    Lx, Ly = 24, 16
+    n0 = _noisy(Lx, Ly, 3)
+    fx = ls.potential_force(Lx, 0.1, 2)
+    a = _run(Params(Lx, Ly, U=0.02), n0, fx, 60)
+    mirror = lambda a2: np.roll(a2[..., ::-1], 1, axis=-1)  # x -> Lx-1-x then shift: x -> -x mod Lx
+    b = _run(Params(Lx, Ly, U=-0.02), mirror(n0), -mirror(fx), 60)
+    assert np.abs(b.n - mirror(a.n)).max() < 1e-12
+    assert np.abs(b.ux + mirror(a.ux)).max() < 1e-12
+    assert np.abs(b.uy - mirror(a.uy)).max() < 1e-12
+
+
+def test_mirror_symmetry_y_walls():
+    # Reflecting y swaps the walls: with U -> -U the lower wall keeps speed
+    # -U. This pins the upper-wall rule (the paper gives the lower one).
+    Lx, Ly = 24, 16
+    n0 = _noisy(Lx, Ly, 4)
+    fx = ls.potential_force(Lx, 0.1, 2)
+    a = _run(Params(Lx, Ly, U=0.02), n0, fx, 60)
+    b = _run(Params(Lx, Ly, U=-0.02), n0[::-1].copy(), fx, 60)
+    assert np.abs(b.n - a.n[::-1]).max() < 1e-12
+    assert np.abs(b.ux - a.ux[::-1]).max() < 1e-12
+    assert np.abs(b.uy + a.uy[::-1]).max() < 1e-12
+
+
+def test_transpose_symmetry_periodic():
+    # On a square periodic lattice without external force, swapping x and y
+    # maps solutions onto solutions: the y stencil is the x stencil turned.
+    L = 20
+    n0 = _noisy(L, L, 5)
+    a = _run(Params(L, L, N=0.3, Q=2.0, y_periodic=True), n0, None, 80)
+    b = _run(Params(L, L, N=0.3, Q=2.0, y_periodic=True), n0.T.copy(), None, 80)
+    assert np.abs(b.n - a.n.T).max() < 1e-12
+    assert np.abs(b.ux - a.uy.T).max() < 1e-12
+
+
+def test_uniform_force_accelerates_uniformly():
+    # A uniform fluid under a uniform force gains F per step of post-collision
+    # momentum; the physical velocity of Eq.(newvel) after k steps is
+    # (k - 1/2) F / n in lattice units (F = F_p / 3).
+    Lx, Ly, n, Fp = 6, 5, 0.8, 3e-5
+    p = Params(Lx, Ly, T=0.95, y_periodic=True)
+    o = _run(p, np.full((Ly, Lx), n), np.full(Lx, Fp), 25)
+    assert np.allclose(o.n, n, atol=1e-14)
+    assert np.allclose(o.ux, (25 - 0.5) * (Fp / 3) / n, rtol=1e-12)
+    assert np.allclose(o.uy, 0, atol=1e-16)
+
+
+def test_rest_state_is_stationary():
+    Lx, Ly = 8, 6
+    p = Params(Lx, Ly, T=0.9, y_periodic=False)
+    o = OracleLB(p, np.full((Ly, Lx), 1.3))
+    S0 = o.S.copy()
+    o.run(10)
+    assert np.abs(o.S - S0).max() < 1e-15

@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Throughput of the fused lattice Boltzmann step on one MI355X.
+
+Workload (synthetic, seeded): 8192 x 2048 lattice between walls moving at
++-0.08, T = 0.9 T_c, periodic potential V0 = 0.1 with 32 stripes, density noise
++-0.01 around n = 1, FP32 deviation storage, FP64 mass/momentum check with
+drift correction every 100 steps. One step = one full time step of the lattice
+(stream, density, stencils, force, walls, collision, store) plus its share of
+the checks.
+
+Prints one JSON line: MLUPS (million lattice-node updates per second), the
+roofline of the step kernel against the HBM peak, and the FP64 CPU oracle
+timed on the host cores on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES_PER_UPDATE_FP32 = 72     # 9 populations read + 9 written, 4 B each
+BYTES_PER_UPDATE_FP64 = 144
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1307_6703_amd", "csrc", "lb_device.hip")
+TUNED = os.path.join(ROOT, "paper_1307_6703_amd", "tuned_launch.json")
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def tuned_launch(key: str):
+    try:
+        return json.load(open(TUNED)).get(key)
+    except (OSError, ValueError):
+        return None
+
+
+def measured_traffic(nodes: int):
+    """HBM bytes per launch from committed rocprofv3 counters, if they were
+    taken on the current kernel source."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_hash() or t.get("nodes") != nodes:
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(w, n0, fext, seconds: float):
+    """The FP64 oracle as it stands, on the full lattice, for as many whole
+    steps as fit in about `seconds` (at least one)."""
+    from oracle.lb_oracle import OracleLB, Params
+    o = OracleLB(Params(w.Lx, w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, U=w.U,
+                        y_periodic=w.y_periodic), n0, fext=fext)
+    t0 = time.perf_counter()
+    used = o.run(1)
+    t1 = time.perf_counter()
+    steps = max(0, int(seconds / max(t1 - t0, 1e-9)) - 1)
+    if steps:
+        o.run(steps)
+    dt = time.perf_counter() - t0
+    total = steps + 1
+    return {"value": round(w.nodes * total / dt / 1e6, 3), "unit": "MLUPS", "cores": used,
+            "kind": "oracle",
+            "sample": f"{total} FP64 steps of the full {w.Lx}x{w.Ly} lattice ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--launch", default=None, help="threads,rows of the step kernel")
+    ap.add_argument("--autotune", action="store_true", help="autotune the launch shape first")
+    ap.add_argument("--check-every", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one MI355X: the lattice fits one GPU's HBM and this build "
+              "has no multi-GPU path; run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import lbsynth as ls
+    from paper_1307_6703_amd import Lattice
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = ls.ROOFLINE
+    n0, fext = w.n0(), w.fext()
+    lat = Lattice(w.Lx, w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, U=w.U, fext=fext,
+                  y_periodic=w.y_periodic, fp32=True, check_every=args.check_every,
+                  drift_correct=True)
+    lat.init(n0)
+    key = f"{w.Lx}x{w.Ly}-fp32-gfx950"
+    if args.launch:
+        th, rw = (int(v) for v in args.launch.split(","))
+        lat.set_launch(th, rw)
+    elif args.autotune:
+        lat.autotune(nsteps=10)
+    elif tuned_launch(key):
+        lat.set_launch(*tuned_launch(key))
+    threads, rows, blocks = lat.get_launch()
+    print(f"[bench] {w.name}: {w.nodes} nodes, launch {threads} threads x {rows} rows, "
+          f"{blocks} workgroups", file=sys.stderr, flush=True)
+
+    m0 = lat.reduce()["mass"]
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    # whole-job timing: steps plus their checks, on the lattice's stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    lat.step(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    mlups = w.nodes * args.steps / (ms * 1e-3) / 1e6
+    print(f"[bench] timed {args.steps} steps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms)",
+          file=sys.stderr, flush=True)
+    red = lat.reduce()
+
+    # the step kernel alone (checks off), same stream, for the roofline
+    lat.set_checks(0, False)
+    k_steps = max(50, args.steps // 2)
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e2.record()
+    lat.step(k_steps)
+    e3.record()
+    torch.cuda.synchronize()
+    k_ms = e2.elapsed_time(e3) / k_steps
+    alg_bytes = BYTES_PER_UPDATE_FP32 * w.nodes
+    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    print(f"[bench] step kernel {k_ms * 1e3:.1f} us/launch, {achieved:.0f} GB/s algorithmic",
+          file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "MLUPS",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "Lx": w.Lx, "Ly": w.Ly, "walls": not w.y_periodic,
+                   "T": w.T, "tau": w.tau, "kappa": w.kappa, "N": w.N, "Q": w.Q, "U": w.U,
+                   "V0": w.V0, "stripes": w.k, "seed": w.seed, "storage": "fp32-deviation",
+                   "checks": f"fp64 every {args.check_every} steps + drift correction",
+                   "launch": {"threads": threads, "rows": rows, "workgroups": blocks}},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(w.nodes),
+                     "kernel": "step_kernel<float,%d>" % threads,
+                     "us_per_launch": round(k_ms * 1e3, 2),
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "hbm_frac_of_peak": round(mlups * 1e6 * BYTES_PER_UPDATE_FP32 / 1e9 / HBM_PEAK_GBS, 4),
+        "mass_drift": abs(red["mass"] - m0) / m0,
+        "gpu": torch.cuda.get_device_name(0),
+    }
+    assert red["nonfinite"] == 0 and 0 < red["nmin"] and red["nmax"] < 3, red
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, n0, fext, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

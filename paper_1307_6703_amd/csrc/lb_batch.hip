@@ -1,0 +1,461 @@
+// Host side of the batched C ABI (include/lbvdw.h): many independent
+// lattices of uneven size advance together. One step of the batch is one
+// launch of the step kernel over the tiles of every instance (the tile table
+// names the instance; each instance has its own descriptor, populations,
+// force table and checks). Runs of steps are recorded once into a HIP graph
+// and replayed.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <numeric>
+
+#include "lb_host.h"
+
+using namespace lbh;
+
+namespace {
+
+struct Inst {
+  lb_params p{};
+  size_t base = 0;  // offset of the instance's region in the workspace
+  Layout L{};
+  bool has_state = false;
+  bool moments_valid = false;
+};
+
+// Shared part of the batch workspace.
+struct BatchLayout {
+  size_t descs, reds, tiles, part, inst0, total;
+  int max_tiles;
+};
+
+BatchLayout batch_layout(int count, const lb_params* p, std::vector<Inst>* insts) {
+  BatchLayout B;
+  int max_tiles = 0, max_red = 1;
+  for (int i = 0; i < count; ++i) {
+    const int strips = (p[i].Lx + 57) / 58;
+    const int chunks = (p[i].Ly + 7) / 8;
+    max_tiles += strips * chunks;
+    max_red = std::max(max_red, lbk::reduce_blocks((int64_t)p[i].Lx * p[i].Ly));
+  }
+  size_t o = 0;
+  B.descs = o; o = align_up(o + sizeof(Desc) * count);
+  B.reds = o; o = align_up(o + sizeof(ReduceOut) * count);
+  B.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)max_tiles);
+  B.part = o; o = align_up(o + sizeof(double) * 6 * (size_t)max_red);
+  B.inst0 = o;
+  for (int i = 0; i < count; ++i) {
+    Layout L = layout_for(&p[i], o);
+    if (insts) {
+      (*insts)[i].base = o;
+      (*insts)[i].L = L;
+    }
+    o += L.total;
+  }
+  B.total = o;
+  B.max_tiles = max_tiles;
+  return B;
+}
+
+constexpr int kGraphSteps = 64;
+
+}  // namespace
+
+struct lb_batch {
+  int count = 0;
+  bool fp32 = false;
+  int check_every = 0, drift = 0;
+  char* ws = nullptr;
+  hipStream_t st = nullptr;
+  BatchLayout B{};
+  std::vector<Inst> inst;
+  std::vector<Desc> hdesc;
+  Desc* ddesc = nullptr;
+  ReduceOut* dred = nullptr;
+  Tile* dtiles = nullptr;
+  double* dpart = nullptr;
+  int threads = 256, rows = 64, ntiles = 0;
+  int parity = 0;
+  int64_t step = 0;
+  bool pending_shift = false;
+  bool unstable_any = false;
+  std::vector<int> unstable;
+  // graphs of kGraphSteps steps, keyed by the pending-shift state at entry
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  int exec_threads = 0, exec_rows = 0;
+};
+
+namespace {
+
+int64_t inst_nodes(const lb_batch* b, int i) { return (int64_t)b->inst[i].p.Lx * b->inst[i].p.Ly; }
+
+void drop_graphs(lb_batch* b) {
+  for (auto& e : b->exec)
+    if (e) {
+      (void)hipGraphExecDestroy(e);
+      e = nullptr;
+    }
+}
+
+lb_status batch_tiles(lb_batch* b, int threads, int rows) {
+  if (threads != 64 && threads != 128 && threads != 256)
+    return fail(LB_EINVAL, "threads must be 64, 128 or 256 (got %d)", threads);
+  if (rows < 1) return fail(LB_EINVAL, "rows must be >= 1");
+  // largest instances first: the dispatcher hands out tiles in order, so the
+  // long-running ones start early
+  std::vector<int> order(b->count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return inst_nodes(b, x) > inst_nodes(b, y); });
+  std::vector<Tile> all;
+  for (int i : order) {
+    const int r = std::max(std::min(rows, b->inst[i].p.Ly), std::min(8, b->inst[i].p.Ly));
+    std::vector<Tile> t = make_tiles(i, b->inst[i].p.Lx, b->inst[i].p.Ly, threads, r);
+    all.insert(all.end(), t.begin(), t.end());
+  }
+  if ((int)all.size() > b->B.max_tiles) return fail(LB_EINVAL, "too many tiles for the workspace");
+  HIPCHK(hipMemcpyAsync(b->dtiles, all.data(), all.size() * sizeof(Tile), hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipStreamSynchronize(b->st));
+  b->threads = threads;
+  b->rows = rows;
+  b->ntiles = (int)all.size();
+  drop_graphs(b);
+  return LB_OK;
+}
+
+lb_status enqueue_checks(lb_batch* b, int mode, int only = -1) {
+  for (int i = 0; i < b->count; ++i) {
+    if (only >= 0 && i != only) continue;
+    if (!b->inst[i].has_state) continue;
+    const int64_t nn = inst_nodes(b, i);
+    HIPCHK(lbk::launch_reduce(b->fp32, b->ddesc + i, b->parity, nn, b->dpart,
+                              (mode == 2 && b->pending_shift) ? 1 : 0, b->st));
+    HIPCHK(lbk::launch_reduce_final(b->dpart, lbk::reduce_blocks(nn), nn, b->dred + i, mode,
+                                    mode == 0 ? b->drift : 0, b->st));
+  }
+  return LB_OK;
+}
+
+// Enqueue `n` steps eagerly (also used while recording a graph).
+lb_status enqueue_steps(lb_batch* b, int64_t n, bool moments_last) {
+  for (int64_t s = 0; s < n; ++s) {
+    int flags = 0;
+    if (moments_last && s == n - 1) flags |= lbk::kWriteMoments;
+    if (b->pending_shift) flags |= lbk::kApplyShift;
+    HIPCHK(lbk::launch_step(b->fp32, b->threads, b->ddesc, b->dtiles, b->ntiles, b->parity, flags,
+                            b->st));
+    b->pending_shift = false;
+    b->parity ^= 1;
+    b->step += 1;
+    if (b->check_every > 0 && b->step % b->check_every == 0) {
+      lb_status r = enqueue_checks(b, 0);
+      if (r != LB_OK) return r;
+      b->pending_shift = b->drift != 0;
+    }
+  }
+  return LB_OK;
+}
+
+// A graph run must start where its recording started: even parity, a step
+// count on the check grid, and the same pending-shift state.
+bool graph_aligned(const lb_batch* b) {
+  if (b->parity != 0) return false;
+  if (b->check_every > 0 && b->step % b->check_every != 0) return false;
+  return true;
+}
+
+lb_status replay(lb_batch* b) {
+  const int key = b->pending_shift ? 1 : 0;
+  if (!b->exec[key]) {
+    hipGraph_t g;
+    const int par0 = b->parity;
+    const int64_t step0 = b->step;
+    const bool pend0 = b->pending_shift;
+    HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+    lb_status r = enqueue_steps(b, kGraphSteps, false);
+    hipError_t e = hipStreamEndCapture(b->st, &g);
+    // recording did not run anything: restore the counters
+    b->parity = par0;
+    b->step = step0;
+    b->pending_shift = pend0;
+    if (r != LB_OK) return r;
+    if (e != hipSuccess) return fail(LB_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->exec[key], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+  }
+  HIPCHK(hipGraphLaunch(b->exec[key], b->st));
+  // advance the counters exactly as the recorded steps do
+  for (int s = 0; s < kGraphSteps; ++s) {
+    b->pending_shift = false;
+    b->parity ^= 1;
+    b->step += 1;
+    if (b->check_every > 0 && b->step % b->check_every == 0) b->pending_shift = b->drift != 0;
+  }
+  return LB_OK;
+}
+
+lb_status read_batch_status(lb_batch* b) {
+  std::vector<ReduceOut> r(b->count);
+  HIPCHK(hipMemcpyAsync(r.data(), b->dred, sizeof(ReduceOut) * b->count, hipMemcpyDeviceToHost, b->st));
+  HIPCHK(hipStreamSynchronize(b->st));
+  for (int i = 0; i < b->count; ++i)
+    if (r[i].status & 1u) {
+      b->unstable[i] = 1;
+      b->unstable_any = true;
+    }
+  return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lb_batch_workspace_bytes(int32_t count, const lb_params* p, size_t* bytes) {
+  if (count < 1) return fail(LB_EINVAL, "count must be >= 1");
+  if (!p || !bytes) return fail(LB_EINVAL, "NULL argument");
+  for (int i = 0; i < count; ++i) {
+    lb_status s = validate(&p[i]);
+    if (s != LB_OK) return s;
+  }
+  *bytes = batch_layout(count, p, nullptr).total;
+  return LB_OK;
+}
+
+lb_status lb_batch_create(int32_t count, const lb_params* p, void* dev_ws, size_t ws_bytes,
+                          void* hip_stream, lb_batch** out) {
+  if (count < 1) return fail(LB_EINVAL, "count must be >= 1");
+  if (!p || !out || !dev_ws) return fail(LB_EINVAL, "NULL argument");
+  if ((uintptr_t)dev_ws % kAlign) return fail(LB_EINVAL, "workspace must be 256-byte aligned");
+  for (int i = 0; i < count; ++i) {
+    lb_status s = validate(&p[i]);
+    if (s != LB_OK) return s;
+    if (p[i].fp32 != p[0].fp32) return fail(LB_EINVAL, "all instances must share fp32");
+    if (p[i].check_every != p[0].check_every || p[i].drift_correct != p[0].drift_correct)
+      return fail(LB_EINVAL, "all instances must share check_every and drift_correct");
+  }
+  lb_batch* b = new lb_batch();
+  b->count = count;
+  b->fp32 = p[0].fp32 != 0;
+  b->check_every = p[0].check_every;
+  b->drift = p[0].drift_correct;
+  b->inst.resize(count);
+  b->B = batch_layout(count, p, &b->inst);
+  if (ws_bytes < b->B.total) {
+    size_t need = b->B.total;
+    delete b;
+    return fail(LB_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  }
+  b->ws = (char*)dev_ws;
+  b->st = (hipStream_t)hip_stream;
+  b->ddesc = (Desc*)(b->ws + b->B.descs);
+  b->dred = (ReduceOut*)(b->ws + b->B.reds);
+  b->dtiles = (Tile*)(b->ws + b->B.tiles);
+  b->dpart = (double*)(b->ws + b->B.part);
+  b->hdesc.resize(count);
+  b->unstable.assign(count, 0);
+  auto cleanup = [&](lb_status e) { delete b; return e; };
+  for (int i = 0; i < count; ++i) {
+    Inst& I = b->inst[i];
+    I.p = p[i];
+    I.p.fext_x = nullptr;
+    Desc& d = b->hdesc[i];
+    d.S[0] = b->ws + I.L.S0;
+    d.S[1] = b->ws + I.L.S1;
+    d.fext3 = b->ws + I.L.fext;
+    d.mom = (double*)(b->ws + I.L.mom);
+    d.shift = &b->dred[i].shift;
+    d.Lx = p[i].Lx;
+    d.Ly = p[i].Ly;
+    d.periodic = p[i].y_periodic;
+    d.nbar = 0.0;
+    d.T = p[i].T;
+    d.omega = 1.0 / (std::sqrt(3.0) * p[i].tau);
+    d.kappa3 = p[i].kappa / 3.0;
+    d.N = p[i].N;
+    d.M = (1.0 - 2.0 * p[i].N) / 4.0;
+    d.Q = p[i].Q;
+    d.R = (1.0 - p[i].Q) / 2.0;
+    d.U = p[i].U;
+    std::vector<double> f(p[i].Lx, 0.0);
+    if (p[i].fext_x)
+      for (int x = 0; x < p[i].Lx; ++x) f[x] = p[i].fext_x[x] / 3.0;
+    hipError_t e;
+    if (b->fp32) {
+      std::vector<float> f32(f.begin(), f.end());
+      e = hipMemcpyAsync(b->ws + I.L.fext, f32.data(), f32.size() * 4, hipMemcpyHostToDevice, b->st);
+      if (e == hipSuccess) e = hipStreamSynchronize(b->st);
+    } else {
+      e = hipMemcpyAsync(b->ws + I.L.fext, f.data(), f.size() * 8, hipMemcpyHostToDevice, b->st);
+      if (e == hipSuccess) e = hipStreamSynchronize(b->st);
+    }
+    if (e != hipSuccess) return cleanup(fail(LB_EDEVICE, "uploading a force table failed"));
+  }
+  std::vector<ReduceOut> z(count);
+  std::memset(z.data(), 0, sizeof(ReduceOut) * count);
+  if (hipMemcpyAsync(b->dred, z.data(), sizeof(ReduceOut) * count, hipMemcpyHostToDevice, b->st) != hipSuccess ||
+      hipMemcpyAsync(b->ddesc, b->hdesc.data(), sizeof(Desc) * count, hipMemcpyHostToDevice, b->st) != hipSuccess ||
+      hipStreamSynchronize(b->st) != hipSuccess)
+    return cleanup(fail(LB_EDEVICE, "uploading descriptors failed"));
+  lb_status r = batch_tiles(b, b->fp32 ? 256 : 128, 64);
+  if (r != LB_OK) return cleanup(r);
+  *out = b;
+  return LB_OK;
+}
+
+lb_status lb_batch_init(lb_batch* b, int32_t idx, const double* n0, const double* ux0,
+                        const double* uy0) {
+  if (!b) return fail(LB_EINVAL, "batch is NULL");
+  if (idx < 0 || idx >= b->count) return fail(LB_EINVAL, "index %d out of range", idx);
+  if (!n0) return fail(LB_EINVAL, "n0 is NULL");
+  if (b->step != 0 || b->parity != 0)
+    return fail(LB_ESTATE, "instances can only be initialised before the batch steps");
+  Inst& I = b->inst[idx];
+  const int64_t nn = inst_nodes(b, idx);
+  double sum = 0.0;
+  for (int64_t k = 0; k < nn; ++k) {
+    if (!(n0[k] > 0.0 && n0[k] < 3.0))
+      return fail(LB_EINVAL, "n0[%lld] = %g is outside (0, 3)", (long long)k, n0[k]);
+    sum += n0[k];
+  }
+  double* mom = (double*)(b->ws + I.L.mom);
+  HIPCHK(hipMemcpyAsync(mom, n0, nn * 8, hipMemcpyHostToDevice, b->st));
+  if (ux0) HIPCHK(hipMemcpyAsync(mom + nn, ux0, nn * 8, hipMemcpyHostToDevice, b->st));
+  if (uy0) HIPCHK(hipMemcpyAsync(mom + 2 * nn, uy0, nn * 8, hipMemcpyHostToDevice, b->st));
+  b->hdesc[idx].nbar = b->fp32 ? sum / (double)nn : 0.0;
+  HIPCHK(hipMemcpyAsync(b->ddesc + idx, &b->hdesc[idx], sizeof(Desc), hipMemcpyHostToDevice, b->st));
+  HIPCHK(lbk::launch_init(b->fp32, b->ddesc + idx, 0, mom, ux0 ? mom + nn : nullptr,
+                          uy0 ? mom + 2 * nn : nullptr, nn, b->st));
+  I.has_state = true;
+  lb_status r = enqueue_checks(b, 1, idx);
+  if (r != LB_OK) return r;
+  if ((r = read_batch_status(b)) != LB_OK) return r;
+  if (b->unstable[idx]) return fail(LB_EUNSTABLE, "initial state of instance %d is invalid", idx);
+  I.moments_valid = true;
+  return LB_OK;
+}
+
+lb_status lb_batch_step_n(lb_batch* b, int64_t nsteps) {
+  if (!b) return fail(LB_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
+  for (int i = 0; i < b->count; ++i)
+    if (!b->inst[i].has_state) return fail(LB_ESTATE, "instance %d has no state", i);
+  if (b->unstable_any) return fail(LB_ESTATE, "an instance was flagged unstable");
+  if (nsteps == 0) return LB_OK;
+  int64_t left = nsteps;
+  lb_status r;
+  // eager steps up to a point where a recorded run can start
+  while (left > 1 && !graph_aligned(b)) {
+    if ((r = enqueue_steps(b, 1, false)) != LB_OK) return r;
+    --left;
+  }
+  while (left > kGraphSteps) {  // keep the last step eager: it writes the moments
+    if ((r = replay(b)) != LB_OK) return r;
+    left -= kGraphSteps;
+  }
+  if ((r = enqueue_steps(b, left, true)) != LB_OK) return r;
+  for (auto& I : b->inst) I.moments_valid = true;
+  return LB_OK;
+}
+
+lb_status lb_batch_get_moments(lb_batch* b, int32_t idx, double* n, double* ux, double* uy) {
+  if (!b) return fail(LB_EINVAL, "batch is NULL");
+  if (idx < 0 || idx >= b->count) return fail(LB_EINVAL, "index %d out of range", idx);
+  if (!b->inst[idx].moments_valid) return fail(LB_ESTATE, "instance %d has no moments", idx);
+  const int64_t nn = inst_nodes(b, idx);
+  const double* mom = (const double*)(b->ws + b->inst[idx].L.mom);
+  if (n) HIPCHK(hipMemcpyAsync(n, mom, nn * 8, hipMemcpyDeviceToHost, b->st));
+  if (ux) HIPCHK(hipMemcpyAsync(ux, mom + nn, nn * 8, hipMemcpyDeviceToHost, b->st));
+  if (uy) HIPCHK(hipMemcpyAsync(uy, mom + 2 * nn, nn * 8, hipMemcpyDeviceToHost, b->st));
+  HIPCHK(hipStreamSynchronize(b->st));
+  lb_status r = read_batch_status(b);
+  if (r != LB_OK) return r;
+  if (b->unstable[idx]) return fail(LB_EUNSTABLE, "instance %d failed a stability check", idx);
+  return LB_OK;
+}
+
+lb_status lb_batch_reduce(lb_batch* b, int32_t idx, double out[6]) {
+  if (!b) return fail(LB_EINVAL, "batch is NULL");
+  if (idx < 0 || idx >= b->count) return fail(LB_EINVAL, "index %d out of range", idx);
+  if (!out) return fail(LB_EINVAL, "out is NULL");
+  if (!b->inst[idx].has_state) return fail(LB_ESTATE, "instance %d has no state", idx);
+  lb_status r = enqueue_checks(b, 2, idx);
+  if (r != LB_OK) return r;
+  ReduceOut ro;
+  HIPCHK(hipMemcpyAsync(&ro, b->dred + idx, sizeof ro, hipMemcpyDeviceToHost, b->st));
+  HIPCHK(hipStreamSynchronize(b->st));
+  out[0] = ro.mass; out[1] = ro.jx; out[2] = ro.jy;
+  out[3] = ro.nmin; out[4] = ro.nmax; out[5] = ro.nonfinite;
+  if (ro.status & 1u) {
+    b->unstable[idx] = 1;
+    b->unstable_any = true;
+    return fail(LB_EUNSTABLE, "instance %d failed a stability check", idx);
+  }
+  return LB_OK;
+}
+
+lb_status lb_batch_status(lb_batch* b, int32_t* per_instance) {
+  if (!b || !per_instance) return fail(LB_EINVAL, "NULL argument");
+  lb_status r = read_batch_status(b);
+  if (r != LB_OK) return r;
+  for (int i = 0; i < b->count; ++i) per_instance[i] = b->unstable[i] ? LB_EUNSTABLE : LB_OK;
+  return LB_OK;
+}
+
+lb_status lb_batch_set_launch(lb_batch* b, int32_t threads, int32_t rows) {
+  if (!b) return fail(LB_EINVAL, "batch is NULL");
+  if (threads == 0) threads = b->fp32 ? 256 : 128;
+  if (rows == 0) rows = 64;
+  return batch_tiles(b, threads, rows);
+}
+
+lb_status lb_batch_autotune(lb_batch* b, int32_t nsteps, int32_t* threads, int32_t* rows,
+                            double* ms_per_step) {
+  if (!b) return fail(LB_EINVAL, "batch is NULL");
+  if (nsteps < 1) return fail(LB_EINVAL, "nsteps must be >= 1");
+  for (int i = 0; i < b->count; ++i)
+    if (!b->inst[i].has_state) return fail(LB_ESTATE, "instance %d has no state", i);
+  if (b->unstable_any) return fail(LB_ESTATE, "an instance was flagged unstable");
+  const int cand_t[] = {128, 256};
+  const int cand_r[] = {16, 32, 64, 128, 256};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double best = 1e300;
+  int bt = b->threads, br = b->rows;
+  lb_status r = LB_OK;
+  for (int t : cand_t)
+    for (int rw : cand_r) {
+      if (r != LB_OK) break;
+      if ((r = batch_tiles(b, t, rw)) != LB_OK) break;
+      if ((r = enqueue_steps(b, 1, false)) != LB_OK) break;
+      if (hipEventRecord(e0, b->st) != hipSuccess) { r = fail(LB_EDEVICE, "event record failed"); break; }
+      if ((r = enqueue_steps(b, nsteps, false)) != LB_OK) break;
+      if (hipEventRecord(e1, b->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        r = fail(LB_EDEVICE, "event sync failed");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms / nsteps < best) { best = ms / nsteps; bt = t; br = rw; }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (r != LB_OK) return r;
+  for (auto& I : b->inst) I.moments_valid = false;
+  if ((r = batch_tiles(b, bt, br)) != LB_OK) return r;
+  if (threads) *threads = bt;
+  if (rows) *rows = br;
+  if (ms_per_step) *ms_per_step = best;
+  return LB_OK;
+}
+
+lb_status lb_batch_destroy(lb_batch* b) {
+  if (!b) return LB_OK;
+  (void)hipStreamSynchronize(b->st);
+  drop_graphs(b);
+  delete b;
+  return LB_OK;
+}
+
+}  // extern "C"

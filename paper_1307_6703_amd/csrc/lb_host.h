@@ -1,0 +1,119 @@
+// Host-side helpers shared by the single-lattice and batched C ABI code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "lb_internal.h"
+#include "lbvdw.h"
+
+using lbk::Desc;
+using lbk::ReduceOut;
+using lbk::Tile;
+
+namespace lbh {
+
+extern thread_local std::string g_err;
+
+inline lb_status fail(lb_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return lbh::fail(LB_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+inline lb_status validate(const lb_params* p) {
+  if (!p) return fail(LB_EINVAL, "params is NULL");
+  if (p->Lx < 1) return fail(LB_EINVAL, "Lx must be >= 1 (got %d)", p->Lx);
+  if (p->Ly < 4) return fail(LB_EINVAL, "Ly must be >= 4 (got %d)", p->Ly);
+  if ((int64_t)p->Lx * p->Ly > (int64_t)1 << 30)
+    return fail(LB_EINVAL, "Lx*Ly must be <= 2^30 nodes");
+  if (p->y_periodic != 0 && p->y_periodic != 1) return fail(LB_EINVAL, "y_periodic must be 0 or 1");
+  if (p->fp32 != 0 && p->fp32 != 1) return fail(LB_EINVAL, "fp32 must be 0 or 1");
+  if (!(p->T > 0.0 && p->T <= 1.5)) return fail(LB_EINVAL, "T must be in (0, 1.5] (got %g)", p->T);
+  if (!(std::sqrt(3.0) * p->tau > 0.5) || !std::isfinite(p->tau))
+    return fail(LB_EINVAL, "need sqrt(3)*tau > 1/2 (got tau=%g)", p->tau);
+  if (!(p->kappa >= 0.0) || !std::isfinite(p->kappa)) return fail(LB_EINVAL, "kappa must be >= 0");
+  if (!std::isfinite(p->N) || !std::isfinite(p->Q)) return fail(LB_EINVAL, "N, Q must be finite");
+  if (!(std::fabs(p->U) < 0.3)) return fail(LB_EINVAL, "|U| must be < 0.3 (got %g)", p->U);
+  if (p->check_every < 0) return fail(LB_EINVAL, "check_every must be >= 0");
+  if (p->drift_correct != 0 && p->drift_correct != 1) return fail(LB_EINVAL, "drift_correct must be 0 or 1");
+  if (p->fext_x)
+    for (int x = 0; x < p->Lx; ++x)
+      if (!std::isfinite(p->fext_x[x])) return fail(LB_EINVAL, "fext_x[%d] is not finite", x);
+  return LB_OK;
+}
+
+// Workspace layout of one lattice, all offsets 256-byte aligned.
+struct Layout {
+  size_t desc, red, tiles, fext, part, mom, stage, S0, S1, total;
+  int max_tiles;
+};
+
+constexpr int kMinRows = 8;
+
+inline Layout layout_for(const lb_params* p, size_t base = 0) {
+  const size_t nn = (size_t)p->Lx * p->Ly;
+  const size_t rs = p->fp32 ? sizeof(float) : sizeof(double);
+  Layout L;
+  const int strips = (p->Lx + 57) / 58;  // narrowest strip: 64 threads
+  const int chunks = (p->Ly + kMinRows - 1) / kMinRows;
+  L.max_tiles = strips * chunks;
+  size_t o = base;
+  L.desc = o; o = align_up(o + sizeof(Desc));
+  L.red = o; o = align_up(o + sizeof(ReduceOut));
+  L.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)L.max_tiles);
+  L.fext = o; o = align_up(o + rs * (size_t)p->Lx);
+  L.part = o; o = align_up(o + sizeof(double) * 6 * (size_t)lbk::reduce_blocks((int64_t)nn));
+  L.mom = o; o = align_up(o + sizeof(double) * 3 * nn);
+  L.stage = o; o = align_up(o + sizeof(double) * nn);
+  L.S0 = o; o = align_up(o + rs * 9 * nn);
+  L.S1 = o; o = align_up(o + rs * 9 * nn);
+  L.total = o - base;
+  return L;
+}
+
+inline int default_threads(const lb_params* p) {
+  const int w = p->fp32 ? 256 : 128;
+  return std::min(w, std::max(64, ((p->Lx + 6 + 63) / 64) * 64));
+}
+
+// Rows per chunk: aim for about 1024 workgroups, at least 16 rows a chunk.
+inline int default_rows(const lb_params* p, int threads) {
+  const int strips = (p->Lx + threads - 7) / (threads - 6);
+  const int chunks = std::max(1, 1024 / strips);
+  int rows = (p->Ly + chunks - 1) / chunks;
+  rows = std::max(rows, 16);
+  return std::min(rows, p->Ly);
+}
+
+inline std::vector<Tile> make_tiles(int inst, int Lx, int Ly, int threads, int rows) {
+  std::vector<Tile> t;
+  const int w = threads - 6;
+  // strip-major then chunk: consecutive tiles are vertical neighbours
+  for (int x0 = 0; x0 < Lx; x0 += w)
+    for (int y0 = 0; y0 < Ly; y0 += rows) t.push_back({inst, x0, y0, std::min(Ly, y0 + rows)});
+  return t;
+}
+
+}  // namespace lbh
+

@@ -1,0 +1,63 @@
+// Internal interface between the host-side C ABI (lb_api.hip) and the device
+// code (lb_device.hip). Not installed; not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lbk {
+
+// One lattice as the kernels see it. Lives in device memory (an array of
+// these for a batch, one for a single lattice).
+struct Desc {
+  void* S[2];            // population planes [9][Ly][Lx], buffers 0 and 1
+  const void* fext3;     // per-column F_ext,x / 3 (lattice units), Lx values
+  double* mom;           // n, ux, uy planes (FP64) of the last step, or null
+  const double* shift;   // pending uniform density shift, or null
+  int32_t Lx, Ly, periodic, pad;
+  double nbar;           // reference density subtracted in storage (0 in FP64)
+  double T, omega, kappa3, N, M, Q, R, U;
+};
+
+// A tile: instance, first column, first and one-past-last row.
+struct Tile {
+  int32_t inst, x0, y0, y1;
+};
+
+enum StepFlags : int { kWriteMoments = 1, kApplyShift = 2 };
+
+// Reduction results per lattice (FP64), laid out in device memory.
+struct ReduceOut {
+  double mass, jx, jy, nmin, nmax, nonfinite;
+  double mass_ref;   // reference mass (set at init / restore)
+  double shift;      // shift to apply at the next step (drift correction)
+  uint32_t status;   // sticky: bit 0 set once a check failed
+  uint32_t has_ref;  // mass_ref valid
+  uint32_t pad[2];
+};
+
+// Launchers (all asynchronous on `stream`). fp32 selects the storage type.
+hipError_t launch_step(bool fp32, int threads, const Desc* d_descs, const Tile* d_tiles,
+                       int ntiles, int parity, int flags, hipStream_t stream);
+hipError_t launch_init(bool fp32, const Desc* d_desc, int parity, const double* d_n0,
+                       const double* d_ux, const double* d_uy, int64_t nn, hipStream_t stream);
+// Per-block partial sums over S[parity] (nb = reduce_blocks(nn) blocks).
+int reduce_blocks(int64_t nn);
+hipError_t launch_reduce(bool fp32, const Desc* d_desc, int parity, int64_t nn, double* d_part,
+                         int add_shift, hipStream_t stream);
+// Fixed-order final reduction of `nb` partials; mode: 0 check (sticky status,
+// drift shift), 1 set the reference mass, 2 report only.
+hipError_t launch_reduce_final(const double* d_part, int nb, int64_t nn, ReduceOut* d_out,
+                               int mode, int drift, hipStream_t stream);
+// Full FP64 populations planes [p0, p1) of S[parity] into d_f (plane-major),
+// adding the pending shift when add_shift != 0.
+hipError_t launch_get_pops(bool fp32, const Desc* d_desc, int parity, int p0, int p1,
+                           int64_t nn, double* d_f, int add_shift, hipStream_t stream);
+hipError_t launch_set_pops(bool fp32, const Desc* d_desc, int parity, int p0, int p1,
+                           int64_t nn, const double* d_f, hipStream_t stream);
+// Rest-state weight w^_i at temperature T.
+double rest_weight(int i, double T);
+
+}  // namespace lbk

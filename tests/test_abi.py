@@ -1,0 +1,114 @@
+"""The C ABI on the CPU: the library loads, exports every symbol the header
+declares, and rejects bad parameters before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1307_6703_amd import lbvdw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbvdw.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(?:lb_status|const char\*)\s+(lb_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lbvdw.LIB_PATH):
+        from paper_1307_6703_amd import build
+        build.build()
+    return lbvdw.load_library()
+
+
+def test_header_declares_the_documented_calls():
+    names = _declared()
+    for must in ("lb_create", "lb_init_lattice", "lb_step_n", "lb_get_moments", "lb_reduce",
+                 "lb_batch_create", "lb_batch_init", "lb_batch_step_n", "lb_batch_get_moments",
+                 "lb_batch_status", "lb_destroy", "lb_batch_destroy", "lb_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = _declared()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding covers exactly the declared calls
+    assert sorted(lbvdw.SIGNATURES) == names
+
+
+def _bytes(lib, **kw):
+    p, fx = lbvdw.make_params(**kw)
+    n = ctypes.c_size_t()
+    st = lib.lb_workspace_bytes(ctypes.byref(p), ctypes.byref(n))
+    return st, n.value, lib.lb_last_error().decode()
+
+
+def test_workspace_size_scales_with_precision(lib):
+    st32, n32, _ = _bytes(lib, Lx=512, Ly=256, fp32=True)
+    st64, n64, _ = _bytes(lib, Lx=512, Ly=256, fp32=False)
+    assert st32 == 0 and st64 == 0
+    nn = 512 * 256
+    # two population buffers dominate: 2 x 9 x nn x (4 | 8) bytes
+    assert n32 >= 2 * 9 * nn * 4 and n64 >= 2 * 9 * nn * 8
+    assert n64 - n32 == pytest.approx(2 * 9 * nn * 4 + 512 * 4, rel=0.01)
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(Lx=0, Ly=16), "Lx"),
+    (dict(Lx=16, Ly=3), "Ly"),
+    (dict(Lx=16, Ly=16, tau=0.2), "tau"),
+    (dict(Lx=16, Ly=16, T=0.0), "T"),
+    (dict(Lx=16, Ly=16, U=0.3), "U"),
+    (dict(Lx=16, Ly=16, kappa=-1.0), "kappa"),
+    (dict(Lx=16, Ly=16, check_every=-1), "check_every"),
+    (dict(Lx=4, Ly=16, fext=[0.0, float("nan"), 0.0, 0.0]), "fext"),
+    (dict(Lx=16, Ly=16, N=float("inf")), "N, Q"),
+])
+def test_invalid_parameters_are_rejected(lib, kw, needle):
+    st, _, msg = _bytes(lib, **kw)
+    assert st == lbvdw.LB_EINVAL
+    assert needle in msg
+
+
+def test_create_rejects_small_or_misaligned_workspace(lib):
+    p, _ = lbvdw.make_params(Lx=32, Ly=16)
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: the checks come first
+    st = lib.lb_create(ctypes.byref(p), fake, 1024, None, ctypes.byref(h))
+    assert st == lbvdw.LB_ENOMEM and "needs" in lib.lb_last_error().decode()
+    st = lib.lb_create(ctypes.byref(p), ctypes.c_void_p((1 << 20) + 8), 1 << 30, None, ctypes.byref(h))
+    assert st == lbvdw.LB_EINVAL and "aligned" in lib.lb_last_error().decode()
+
+
+def test_null_handles_are_rejected(lib):
+    assert lib.lb_step_n(None, 1) == lbvdw.LB_EINVAL
+    assert lib.lb_get_moments(None, None, None, None) == lbvdw.LB_EINVAL
+    assert lib.lb_destroy(None) == lbvdw.LB_OK
+    assert lib.lb_batch_step_n(None, 1) == lbvdw.LB_EINVAL
+
+
+def test_batch_rejects_mixed_precision(lib):
+    arr = (lbvdw.lb_params * 2)()
+    arr[0], _ = lbvdw.make_params(Lx=32, Ly=16, fp32=True)
+    arr[1], _ = lbvdw.make_params(Lx=32, Ly=16, fp32=False)
+    h = ctypes.c_void_p()
+    st = lib.lb_batch_create(2, arr, ctypes.c_void_p(1 << 20), 1 << 40, None, ctypes.byref(h))
+    assert st == lbvdw.LB_EINVAL and "fp32" in lib.lb_last_error().decode()
+    n = ctypes.c_size_t()
+    assert lib.lb_batch_workspace_bytes(2, arr, ctypes.byref(n)) == 0
+    assert lib.lb_batch_workspace_bytes(0, arr, ctypes.byref(n)) == lbvdw.LB_EINVAL
+
+
+def test_product_package_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1307_6703_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in txt.lower(), f

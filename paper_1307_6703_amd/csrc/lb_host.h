@@ -93,8 +93,10 @@ inline Layout layout_for(const lb_params* p, size_t base = 0) {
 }
 
 inline int default_threads(const lb_params* p) {
-  const int w = p->fp32 ? 256 : 128;
-  return std::min(w, std::max(64, ((p->Lx + 6 + 63) / 64) * 64));
+  const int cap = p->fp32 ? 256 : 128;
+  if (p->Lx + 6 <= 64) return 64;
+  if (p->Lx + 6 <= 128 || cap == 128) return 128;
+  return 256;
 }
 
 // Rows per chunk: aim for about 1024 workgroups, at least 16 rows a chunk.

@@ -203,7 +203,7 @@ def test_fp32_drift_correction_holds_mass(torch_cuda):
     _say("fp32 drift")
     res = {}
     for drift in (False, True):
-        g, _ = _pair(512, 128, T=0.9, U=0.05, V0=0.1, k=4, fp32=True, check_every=50,
+        g, _ = _pair(512, 128, T=0.95, U=0.05, V0=0.01, k=4, fp32=True, check_every=50,
                      drift_correct=drift)
         m0 = g.reduce()["mass"]
         g.step(5000)

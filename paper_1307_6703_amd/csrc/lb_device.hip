@@ -91,58 +91,73 @@ __device__ __forceinline__ R restw(const Par<R>& p, int i) {
 //   geq_i = w^_i dn + w_i n [3 c.u + 9/2 (c.u)^2 - 3/2 u^2],
 //   F_i   = w_i s [3 c.F + X:(3 c c - I)/2],  s = 1 - omega/2,
 //   X = 3 (u F + F u) + (1 - T)(u grad n + grad n u + D I).
+// Opposite directions share the even part (sym) and flip the odd part
+// (asym); omega n (c.u) is written omega (c.j) with j = n u.
 template <typename R>
-__device__ __forceinline__ void collide(R g[9], const Par<R>& p, R n, R dn, R ux, R uy, R Fx,
-                                        R Fy, R dnx, R dny, R D) {
-  const R one = (R)1, w0 = (R)(4.0 / 9.0), wa = (R)(1.0 / 9.0), wd = (R)(1.0 / 36.0);
-  const R oneT = one - p.T;
-  const R Xxx = (R)6 * ux * Fx + oneT * ((R)2 * ux * dnx + D);
-  const R Xyy = (R)6 * uy * Fy + oneT * ((R)2 * uy * dny + D);
-  const R Xxy = (R)3 * (ux * Fy + Fx * uy) + oneT * (ux * dny + dnx * uy);
+struct Coll {
+  R keep, om, oneT, s3;      // 1 - omega, omega, 1 - T, 3 s
+  R owr0, owra, owrd;        // omega w^_i
+  R w0, wa, wd;              // w_i
+  R w0s, was, wds;           // w_i s
+};
+
+template <typename R>
+__device__ __forceinline__ Coll<R> make_coll(const Desc& d) {
+  Coll<R> c;
+  const double om = d.omega, s = 1.0 - 0.5 * d.omega;
+  c.keep = (R)(1.0 - om);
+  c.om = (R)om;
+  c.oneT = (R)(1.0 - d.T);
+  c.s3 = (R)(3.0 * s);
+  c.owr0 = (R)(om * rest_weight_hd(0, d.T));
+  c.owra = (R)(om * rest_weight_hd(1, d.T));
+  c.owrd = (R)(om * rest_weight_hd(5, d.T));
+  c.w0 = (R)(4.0 / 9.0);
+  c.wa = (R)(1.0 / 9.0);
+  c.wd = (R)(1.0 / 36.0);
+  c.w0s = (R)(4.0 / 9.0 * s);
+  c.was = (R)(1.0 / 9.0 * s);
+  c.wds = (R)(1.0 / 36.0 * s);
+  return c;
+}
+
+template <typename R>
+__device__ __forceinline__ void collide(R g[9], const Coll<R>& c, R n, R dn, R jx, R jy, R rn,
+                                        R Fx, R Fy, R dnx, R dny, R D) {
+  const R ux = jx * rn, uy = jy * rn;
   const R usq = (R)1.5 * (ux * ux + uy * uy);
-  const R om = p.omega, keep = one - om;
-  const R ns = n, sf = p.sF;
-  // rest
+  const R Xxx = (R)6 * ux * Fx + c.oneT * ((R)2 * ux * dnx + D);
+  const R Xyy = (R)6 * uy * Fy + c.oneT * ((R)2 * uy * dny + D);
+  const R Xxy = (R)3 * (ux * Fy + uy * Fx) + c.oneT * (ux * dny + uy * dnx);
+  const R on = c.om * n;
+  const R ojx = c.om * jx, ojy = c.om * jy;
+  const R trX = Xxx + Xyy;
+  g[0] = c.keep * g[0] + (c.owr0 * dn - c.w0 * (on * usq) - c.w0s * ((R)0.5 * trX));
   {
-    R geq = p.wr0 * dn + w0 * ns * (-usq);
-    R fo = w0 * sf * ((R)(-0.5) * (Xxx + Xyy));
-    g[0] = keep * g[0] + om * geq + fo;
-  }
-  // axis pairs: (1,3) along x, (2,4) along y
-  {
-    R qx = (R)0.5 * ((R)2 * Xxx - Xyy);
-    R sym = p.wra * dn + wa * ns * ((R)4.5 * ux * ux - usq);
-    R asym = wa * ns * (R)3 * ux;
-    R fsym = wa * sf * qx, fasym = wa * sf * (R)3 * Fx;
-    g[1] = keep * g[1] + om * (sym + asym) + (fsym + fasym);
-    g[3] = keep * g[3] + om * (sym - asym) + (fsym - fasym);
+    const R es = c.owra * dn + c.wa * (on * ((R)4.5 * ux * ux - usq)) + c.was * (Xxx - (R)0.5 * Xyy);
+    const R ea = (R)3 * c.wa * ojx + c.wa * c.s3 * Fx;
+    g[1] = c.keep * g[1] + (es + ea);
+    g[3] = c.keep * g[3] + (es - ea);
   }
   {
-    R qy = (R)0.5 * ((R)2 * Xyy - Xxx);
-    R sym = p.wra * dn + wa * ns * ((R)4.5 * uy * uy - usq);
-    R asym = wa * ns * (R)3 * uy;
-    R fsym = wa * sf * qy, fasym = wa * sf * (R)3 * Fy;
-    g[2] = keep * g[2] + om * (sym + asym) + (fsym + fasym);
-    g[4] = keep * g[4] + om * (sym - asym) + (fsym - fasym);
-  }
-  // diagonals: (5,7) along (1,1), (6,8) along (-1,1)
-  {
-    R cu = ux + uy, cF = Fx + Fy;
-    R q = (R)0.5 * ((R)2 * (Xxx + Xyy) + (R)6 * Xxy);
-    R sym = p.wrd * dn + wd * ns * ((R)4.5 * cu * cu - usq);
-    R asym = wd * ns * (R)3 * cu;
-    R fsym = wd * sf * q, fasym = wd * sf * (R)3 * cF;
-    g[5] = keep * g[5] + om * (sym + asym) + (fsym + fasym);
-    g[7] = keep * g[7] + om * (sym - asym) + (fsym - fasym);
+    const R es = c.owra * dn + c.wa * (on * ((R)4.5 * uy * uy - usq)) + c.was * (Xyy - (R)0.5 * Xxx);
+    const R ea = (R)3 * c.wa * ojy + c.wa * c.s3 * Fy;
+    g[2] = c.keep * g[2] + (es + ea);
+    g[4] = c.keep * g[4] + (es - ea);
   }
   {
-    R cu = uy - ux, cF = Fy - Fx;
-    R q = (R)0.5 * ((R)2 * (Xxx + Xyy) - (R)6 * Xxy);
-    R sym = p.wrd * dn + wd * ns * ((R)4.5 * cu * cu - usq);
-    R asym = wd * ns * (R)3 * cu;
-    R fsym = wd * sf * q, fasym = wd * sf * (R)3 * cF;
-    g[6] = keep * g[6] + om * (sym + asym) + (fsym + fasym);
-    g[8] = keep * g[8] + om * (sym - asym) + (fsym - fasym);
+    const R cu = ux + uy;
+    const R es = c.owrd * dn + c.wd * (on * ((R)4.5 * cu * cu - usq)) + c.wds * (trX + (R)3 * Xxy);
+    const R ea = (R)3 * c.wd * (ojx + ojy) + c.wd * c.s3 * (Fx + Fy);
+    g[5] = c.keep * g[5] + (es + ea);
+    g[7] = c.keep * g[7] + (es - ea);
+  }
+  {
+    const R cu = uy - ux;
+    const R es = c.owrd * dn + c.wd * (on * ((R)4.5 * cu * cu - usq)) + c.wds * (trX - (R)3 * Xxy);
+    const R ea = (R)3 * c.wd * (ojy - ojx) + c.wd * c.s3 * (Fy - Fx);
+    g[6] = c.keep * g[6] + (es + ea);
+    g[8] = c.keep * g[8] + (es - ea);
   }
 }
 
@@ -171,34 +186,107 @@ __device__ __forceinline__ RowMap map_row(int a, int Ly, int periodic) {
   return m;
 }
 
+// Buffer loads and stores: one buffer resource per population array
+// (uniform); the plane and row as a scalar byte offset and the column as a
+// per-lane byte offset, so no per-lane 64-bit address arithmetic is needed.
+// The range check of a raw buffer access covers the per-lane offset only, so
+// num_records = one row's bytes bounds every access to its row; a lane or a
+// row that must not touch memory uses an offset at that bound (or a resource
+// with num_records = 0) and the hardware drops the store / returns 0. All
+// nine planes of an array lie within 4 GiB (checked on the host).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int num_records) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, num_records,
+                                           0x00020000);
+}
+__device__ __forceinline__ float buf_ld(float*, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ double buf_ld(double*, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_st(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, 0);
+}
+
+template <typename R>
+__device__ __forceinline__ R fast_rcp(R x) { return (R)1 / x; }
+template <>
+__device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Pull the nine values a node of physical row `m.phys` needs (Eq.(evoleq)):
 // slot i holds S_i(x - c_i). At a wall node the three slots whose source lies
 // outside the lattice hold instead the node's own post-collision populations
 // that would leave it (lower wall: S4, S7, S8 in slots 2, 5, 6; upper wall:
 // S2, S5, S6 in slots 4, 7, 8), so that the sum of the slots is n-hat.
 template <typename R>
-__device__ __forceinline__ void pull_row(R v[9], const R* __restrict__ S, int64_t nn, int Lx,
-                                         int Ly, int periodic, const RowMap& m, int xc, int xm,
-                                         int xp) {
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    int plane = i, sr = m.phys - cy(i);
-    int sc = cx(i) == 0 ? xc : (cx(i) > 0 ? xm : xp);
-    if (periodic) {
-      sr = sr < 0 ? sr + Ly : (sr >= Ly ? sr - Ly : sr);
-    } else if ((m.wall == 1 && cy(i) == 1) || (m.wall == 2 && cy(i) == -1)) {
-      plane = opp(i);
-      sr = m.phys;
-      sc = xc;
-    }
-    v[i] = S[(int64_t)plane * nn + (int64_t)sr * Lx + sc];
-  }
+struct Pair {
+  R x, y;
+};
+
+template <typename R>
+struct Quad {
+  R jx, jy, Fx, Fy;
+};
+
+// Pull the nine values a node of physical row `m.phys` needs (Eq.(evoleq)):
+// slot i holds S_i(x - c_i). At a wall node the three slots whose source lies
+// outside the lattice hold instead the node's own post-collision populations
+// that would leave it (lower wall: S4, S7, S8 in slots 2, 5, 6; upper wall:
+// S2, S5, S6 in slots 4, 7, 8), so that the sum of the slots is n-hat.
+// Full reflection for rows beyond the tile's ghost range (rows that are
+// loaded but never stored), so every row index maps into the lattice.
+__device__ __forceinline__ RowMap map_row_any(int a, int Ly, int periodic) {
+  if (periodic || (a >= -3 && a <= Ly + 2)) return map_row(a, Ly, periodic);
+  RowMap m;
+  const int P = 2 * (Ly - 1);
+  int r = a % P;
+  if (r < 0) r += P;
+  m.ysgn = 1;
+  if (r > Ly - 1) r = P - r;
+  m.phys = r;
+  m.wall = (r == 0) ? 1 : (r == Ly - 1 ? 2 : 0);
+  return m;
 }
 
-template <typename R, int NT>
-__global__ __launch_bounds__(NT) void step_kernel(const Desc* __restrict__ descs,
-                                                  const Tile* __restrict__ tiles, int ntiles,
-                                                  int parity, int flags) {
+template <typename R>
+__device__ __forceinline__ void pull_row(R v[9], __amdgpu_buffer_rsrc_t S, uint32_t pbytes, int Lx,
+                                         int Ly, int periodic, const RowMap& m, int vc, int vm,
+                                         int vp) {
+  // source rows y - c_y (wrapped when periodic); at a wall node the slots
+  // whose source lies outside take the node's own outgoing populations
+  const uint32_t rb = (uint32_t)Lx * (uint32_t)sizeof(R);
+  int rs = m.phys - 1, rn = m.phys + 1;
+  if (periodic) {
+    rs = rs < 0 ? rs + Ly : rs;
+    rn = rn >= Ly ? rn - Ly : rn;
+  }
+  const bool lo = m.wall == 1, hi = m.wall == 2;
+  const uint32_t o_s = (uint32_t)(lo ? m.phys : rs) * rb;  // row of c_y = +1 sources
+  const uint32_t o_0 = (uint32_t)m.phys * rb;
+  const uint32_t o_n = (uint32_t)(hi ? m.phys : rn) * rb;  // row of c_y = -1 sources
+  // lower wall: slots 2, 5, 6 read own S4, S7, S8; upper: 4, 7, 8 read own S2, S5, S6
+  const int v5 = lo ? vc : vm, v6 = lo ? vc : vp, v7 = hi ? vc : vp, v8 = hi ? vc : vm;
+  const uint32_t p2 = lo ? 4u : 2u, p5 = lo ? 7u : 5u, p6 = lo ? 8u : 6u;
+  const uint32_t p4 = hi ? 2u : 4u, p7 = hi ? 5u : 7u, p8 = hi ? 6u : 8u;
+  v[0] = buf_ld((R*)nullptr, S, vc, (int)(0u * pbytes + o_0));
+  v[1] = buf_ld((R*)nullptr, S, vm, (int)(1u * pbytes + o_0));
+  v[2] = buf_ld((R*)nullptr, S, vc, (int)(p2 * pbytes + o_s));
+  v[3] = buf_ld((R*)nullptr, S, vp, (int)(3u * pbytes + o_0));
+  v[4] = buf_ld((R*)nullptr, S, vc, (int)(p4 * pbytes + o_n));
+  v[5] = buf_ld((R*)nullptr, S, v5, (int)(p5 * pbytes + o_s));
+  v[6] = buf_ld((R*)nullptr, S, v6, (int)(p6 * pbytes + o_s));
+  v[7] = buf_ld((R*)nullptr, S, v7, (int)(p7 * pbytes + o_n));
+  v[8] = buf_ld((R*)nullptr, S, v8, (int)(p8 * pbytes + o_n));
+}
+
+template <typename R, int NT, bool MOM>
+__global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void step_kernel(
+    const Desc* __restrict__ descs, const Tile* __restrict__ tiles, int ntiles, int parity,
+    int flags) {
   // Workgroups are dealt round-robin over the 8 XCDs; give each XCD a
   // contiguous run of tiles so vertically adjacent chunks share its L2.
   const int nb = gridDim.x, b = blockIdx.x;
@@ -206,181 +294,210 @@ __global__ __launch_bounds__(NT) void step_kernel(const Desc* __restrict__ descs
   const int logical = xcd * q + (xcd < rm ? xcd : rm) + (b >> 3);
   if (logical >= ntiles) return;  // uniform per block
   const Tile tile = tiles[logical];
-  const Desc& d = descs[tile.inst];
+  const int inst = tile.inst & 0x7fffffff;
+  const int dir = (tile.inst < 0) ? -1 : 1;  // march direction along y
+  const Desc& d = descs[inst];
   const int Lx = d.Lx, Ly = d.Ly, periodic = d.periodic;
   const int64_t nn = (int64_t)Lx * Ly;
-  const R* __restrict__ Sin = (const R*)d.S[parity];
-  R* __restrict__ Sout = (R*)d.S[parity ^ 1];
+  const int rowb = Lx * (int)sizeof(R);  // bytes of one row = num_records
+  const __amdgpu_buffer_rsrc_t Sin = make_rsrc(d.S[parity], rowb);
+  const __amdgpu_buffer_rsrc_t Sout = make_rsrc(d.S[parity ^ 1], rowb);
+  const __amdgpu_buffer_rsrc_t Snone = make_rsrc(d.S[parity ^ 1], 0);  // drops every access
   const R* __restrict__ fext3 = (const R*)d.fext3;
-  const Par<R> p = load_par<R>(d, flags);
+  const Coll<R> cl = make_coll<R>(d);
+  const R nbar = (R)d.nbar, T = (R)d.T, kap3 = (R)d.kappa3, third = (R)(1.0 / 3.0);
+  const R N = (R)d.N, M = (R)d.M, Q = (R)d.Q, Rw = (R)d.R, Q4R = (R)(4.0 * (d.Q + d.R));
+  // y stencils are taken along the march ("ahead" minus "behind"); the sign
+  // of the march turns them into d/dy
+  const R Ny = (R)(dir * d.N), My = (R)(dir * d.M);
+  const R Ub = (R)(-d.U), Ut = (R)d.U;
+  R shift = (R)0;
+  if ((flags & kApplyShift) && d.shift) shift = (R)(*d.shift);
+  const R sh0 = shift * (R)rest_weight_hd(0, d.T), sha = shift * (R)rest_weight_hd(1, d.T),
+          shd = shift * (R)rest_weight_hd(5, d.T);
 
   const int t = threadIdx.x;
   const int W = min(NT - 6, Lx - tile.x0);  // columns this strip updates
   int xc = (tile.x0 - 3 + t) % Lx;
   if (xc < 0) xc += Lx;
-  const int xm = xc == 0 ? Lx - 1 : xc - 1;       // source of c_x = +1
-  const int xp = xc == Lx - 1 ? 0 : xc + 1;       // source of c_x = -1
+  const int xm = xc == 0 ? Lx - 1 : xc - 1;  // source of c_x = +1
+  const int xp = xc == Lx - 1 ? 0 : xc + 1;  // source of c_x = -1
   const bool actA = t < W + 6;
   const bool actB = t >= 1 && t < W + 5;
   const bool actC = t >= 2 && t < W + 4;
   const bool actD = t >= 3 && t < W + 3;
+  // per-lane byte offsets; lanes outside the strip use the row bound (dropped)
+  const int vc = actA ? xc * (int)sizeof(R) : rowb;
+  const int vm = actA ? xm * (int)sizeof(R) : rowb;
+  const int vp = actA ? xp * (int)sizeof(R) : rowb;
   const R fx3 = actC ? fext3[xc] : (R)0;
+  const uint32_t pbytes = (uint32_t)(nn * (int64_t)sizeof(R));
 
-  __shared__ R nR[8][NT];   // density deviation dn, rows a & 7
-  __shared__ R LR[4][NT];   // Laplacian of n
-  __shared__ R PR[4][NT];   // p^i - p^w (paper units)
-  __shared__ R jxR[4][NT];  // j*_x
-  __shared__ R jyR[4][NT];  // j*_y
+  // LDS rings indexed by pipeline row j (row a_j = a_0 + dir j): slot j % 8
+  // for n, j % 4 for the others. With the loop unrolled by 8 every slot is a
+  // compile-time offset. One padding entry on each side keeps the stencil
+  // reads of edge lanes inside the arrays.
+  __shared__ R nR[8][NT + 2];          // density deviation dn
+  __shared__ Pair<R> LP[4][NT + 2];    // (Laplacian of n, p^i - p^w)
+  __shared__ Quad<R> JR[4][NT + 2];    // (j*_x, j*_y, F_x, F_y)
+  const int u = t + 1;                 // padded column index
 
-  R f[4][9];      // pulled populations, by row (a & 3)
-  R jr[4][2];     // raw momentum sum f c, by row (a & 3)
-  R Fr[2][2];     // force, by row (c & 1)
+  R f[4][9];     // pulled populations, slot j % 4
+  R pf[9];       // next row's pulled populations, in flight
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
+  for (int s = 0; s < 4; ++s)
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[s][i] = (R)0;
-    jr[s][0] = jr[s][1] = (R)0;
-  }
-  Fr[0][0] = Fr[0][1] = Fr[1][0] = Fr[1][1] = (R)0;
 
   const int y0 = tile.y0, y1 = tile.y1;
-  const int K = (y1 - y0) + 6;  // iterations: rows a = y0-3 .. y1+2
-  const bool wantMom = (flags & kWriteMoments) && d.mom;
+  // Pipeline rows j = 0 .. K-1 are rows y0-3 .. y1+2 in march order. At
+  // iteration k: A on row j = k, B on k-1, C on k-2, D on k-3. Valid: A for
+  // k < K, B for 2 <= k < K, C for 4 <= k < K, D for 6 <= k < K. Iterations
+  // past K (at most 7, only when the chunk height is not 2 mod 8) run with
+  // their memory accesses dropped. Every load and store is issued on every
+  // iteration, outside branches, so the compiler can count them exactly
+  // when it waits for the prefetched row.
+  const int K = (y1 - y0) + 6;
+  const int a0 = dir > 0 ? y0 - 3 : y1 + 2;
 
-  for (int kb = 0; kb < K; kb += 4) {
+  pull_row<R>(pf, Sin, pbytes, Lx, Ly, periodic, map_row_any(a0, Ly, periodic), vc, vm, vp);
+
+  for (int kb = 0; kb < K; kb += 8) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < 8; ++s) {
       const int k = kb + s;
-      if (k < K) {  // uniform
-        const int a = y0 - 3 + k;
-        // ---- stage A: row a ------------------------------------------------
-        {
-          const RowMap m = map_row(a, Ly, periodic);
-          if (actA) {
-            R v[9];
-            pull_row<R>(v, Sin, nn, Lx, Ly, periodic, m, xc, xm, xp);
-            R dn = (R)0;
+      const int a = a0 + dir * k;
+      // ---- stage A: row a (its loads were issued one iteration ago) ----------
+      if (k < K) {
+        R* v = f[s & 3];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-              v[i] += p.shift * restw(p, i);
-              dn += v[i];
-            }
+        for (int i = 0; i < 9; ++i) v[i] = pf[i];
+        if (shift != (R)0) {
+          v[0] += sh0;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) f[s][i] = v[i];
-            jr[s][0] = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
-            jr[s][1] = (R)m.ysgn * ((v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]));
-            nR[a & 7][t] = dn;
-          }
+          for (int i = 1; i <= 4; ++i) v[i] += sha;
+#pragma unroll
+          for (int i = 5; i <= 8; ++i) v[i] += shd;
         }
-        __syncthreads();
-        // ---- stage B: row b = a-1 --------------------------------------------
-        {
-          const int bb = a - 1;
-          if (bb >= y0 - 2 && bb <= y1 + 1 && actB) {
-            const R* nm = nR[(bb - 1) & 7];
-            const R* n0 = nR[bb & 7];
-            const R* np = nR[(bb + 1) & 7];
-            const R c = n0[t];
-            const R L = p.Q * ((n0[t + 1] + n0[t - 1]) + (np[t] + nm[t])) +
-                        p.Rw * ((np[t + 1] + np[t - 1]) + (nm[t + 1] + nm[t - 1])) -
-                        (R)4 * (p.Q + p.Rw) * c;
-            const R n = p.nbar + c;
-            const R P = n * p.T - (R)3 * n * p.T / ((R)3 - n) + (R)1.125 * n * n;
-            LR[bb & 3][t] = L;
-            PR[bb & 3][t] = P;
-          }
+        const R dn = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])) + v[8];
+        nR[s][u] = dn;
+      }
+      // prefetch row a + dir (dropped past the last pipeline row)
+      pull_row<R>(pf, (k + 1 < K) ? Sin : Snone, pbytes, Lx, Ly, periodic,
+                  map_row_any(a + dir, Ly, periodic), vc, vm, vp);
+      __syncthreads();
+      // ---- stage B: row a - dir: Laplacian and pressure term -----------------
+      if (k >= 2 && k < K && actB) {
+        const R* nb_ = nR[(s + 6) & 7];  // behind
+        const R* n0 = nR[(s + 7) & 7];
+        const R* na_ = nR[s];            // ahead
+        const R c = n0[u];
+        const R L = Q * ((n0[u + 1] + n0[u - 1]) + (na_[u] + nb_[u])) +
+                    Rw * ((na_[u + 1] + na_[u - 1]) + (nb_[u + 1] + nb_[u - 1])) - Q4R * c;
+        const R n = nbar + c;
+        // p^i - p^w = n T - 3 n T / (3 - n) + 9 n^2 / 8 = n^2 (9/8 - T / (3 - n))
+        const R P = n * n * ((R)1.125 - T * fast_rcp<R>((R)3 - n));
+        LP[(s + 3) & 3][u] = Pair<R>{L, P};
+      }
+      __syncthreads();
+      // ---- stage C: row a - 2 dir: force and j* ------------------------------
+      if (k >= 4 && k < K && actC) {
+        const Pair<R>* Bk = LP[(s + 1) & 3];  // behind
+        const Pair<R>* Md = LP[(s + 2) & 3];
+        const Pair<R>* Ah = LP[(s + 3) & 3];  // ahead
+        const Pair<R> aE = Ah[u + 1], aW = Ah[u - 1], aC = Ah[u];
+        const Pair<R> bE = Bk[u + 1], bW = Bk[u - 1], bC = Bk[u];
+        const Pair<R> mE = Md[u + 1], mW = Md[u - 1];
+        // gradient: d/dx = N (E - W) + M (d1 + d2), d/dy = dir [N (A - B) + M (d1 - d2)],
+        // d1 = AE - BW, d2 = BE - AW (A ahead, B behind in the march)
+        const R Ld1 = aE.x - bW.x, Ld2 = bE.x - aW.x;
+        const R Pd1 = aE.y - bW.y, Pd2 = bE.y - aW.y;
+        const R gLx = N * (mE.x - mW.x) + M * (Ld1 + Ld2);
+        const R gLy = Ny * (aC.x - bC.x) + My * (Ld1 - Ld2);
+        const R gPx = N * (mE.y - mW.y) + M * (Pd1 + Pd2);
+        const R gPy = Ny * (aC.y - bC.y) + My * (Pd1 - Pd2);
+        const R n = nbar + nR[(s + 6) & 7][u];
+        const R kn = kap3 * n;
+        const R Fx = third * gPx + kn * gLx + fx3;
+        const R Fy = third * gPy + kn * gLy;
+        const RowMap m = map_row(a - 2 * dir, Ly, periodic);
+        R jx, jy;
+        if (m.wall) {
+          jx = n * (m.wall == 1 ? Ub : Ut);
+          jy = (R)0;
+        } else {
+          // momentum of the pulled populations of this row, still in the ring
+          const R* v = f[(s + 2) & 3];
+          jx = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]) + (R)0.5 * Fx;
+          R py = (v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]);
+          if (m.ysgn < 0) py = -py;  // mirrored ghost row: y-components odd
+          jy = py + (R)0.5 * Fy;
         }
-        __syncthreads();
-        // ---- stage C: row c = a-2 --------------------------------------------
-        {
-          const int cc = a - 2;
-          if (cc >= y0 - 1 && cc <= y1 && actC) {
-            const R* Pm = PR[(cc - 1) & 3];
-            const R* P0 = PR[cc & 3];
-            const R* Pp = PR[(cc + 1) & 3];
-            const R* Lm = LR[(cc - 1) & 3];
-            const R* L0 = LR[cc & 3];
-            const R* Lp = LR[(cc + 1) & 3];
-            const R gPx = p.N * (P0[t + 1] - P0[t - 1]) +
-                          p.M * ((Pp[t + 1] - Pp[t - 1]) + (Pm[t + 1] - Pm[t - 1]));
-            const R gPy = p.N * (Pp[t] - Pm[t]) +
-                          p.M * ((Pp[t + 1] - Pm[t + 1]) + (Pp[t - 1] - Pm[t - 1]));
-            const R gLx = p.N * (L0[t + 1] - L0[t - 1]) +
-                          p.M * ((Lp[t + 1] - Lp[t - 1]) + (Lm[t + 1] - Lm[t - 1]));
-            const R gLy = p.N * (Lp[t] - Lm[t]) +
-                          p.M * ((Lp[t + 1] - Lm[t + 1]) + (Lp[t - 1] - Lm[t - 1]));
-            const R n = p.nbar + nR[cc & 7][t];
-            const R Fx = p.third * gPx + p.kappa3 * n * gLx + fx3;
-            const R Fy = p.third * gPy + p.kappa3 * n * gLy;
-            const RowMap m = map_row(cc, Ly, periodic);
-            R jx, jy;
-            if (m.wall) {
-              jx = n * (m.wall == 1 ? p.Ub : p.Ut);
-              jy = (R)0;
-            } else {
-              jx = jr[(s + 2) & 3][0] + (R)0.5 * Fx;
-              jy = jr[(s + 2) & 3][1] + (R)0.5 * Fy;
-            }
-            jxR[cc & 3][t] = jx;
-            jyR[cc & 3][t] = jy;
-            Fr[s & 1][0] = Fx;
-            Fr[s & 1][1] = Fy;
-          }
+        JR[(s + 2) & 3][u] = Quad<R>{jx, jy, Fx, Fy};
+      }
+      __syncthreads();
+      // ---- stage D: row a - 3 dir: walls, collision, store -------------------
+      const int dd = a - 3 * dir;
+      const bool validD = k >= 6 && k < K;
+      // rows without a valid D stage store nothing (their stores are dropped)
+      R g[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) g[i] = f[(s + 1) & 3][i];
+      R n = (R)1, ux = (R)0, uy = (R)0;
+      if (validD) {
+        const R* nb_ = nR[(s + 4) & 7];  // behind
+        const R* n0 = nR[(s + 5) & 7];
+        const R* na_ = nR[(s + 6) & 7];  // ahead
+        const R nd1 = na_[u + 1] - nb_[u - 1], nd2 = nb_[u + 1] - na_[u - 1];
+        const R dnx = N * (n0[u + 1] - n0[u - 1]) + M * (nd1 + nd2);
+        const R dny = Ny * (na_[u] - nb_[u]) + My * (nd1 - nd2);
+        const Quad<R>* Jb = JR[s & 3];
+        const Quad<R>* J0 = JR[(s + 1) & 3];
+        const Quad<R>* Ja = JR[(s + 2) & 3];
+        const Pair<R> aE = {Ja[u + 1].jx, Ja[u + 1].jy}, aW = {Ja[u - 1].jx, Ja[u - 1].jy};
+        const Pair<R> bE = {Jb[u + 1].jx, Jb[u + 1].jy}, bW = {Jb[u - 1].jx, Jb[u - 1].jy};
+        const R aCy = Ja[u].jy, bCy = Jb[u].jy;
+        const R mEx = J0[u + 1].jx, mWx = J0[u - 1].jx;
+        const Quad<R> mC = J0[u];
+        // D = d/dx j*_x + d/dy j*_y
+        const R D = N * (mEx - mWx) + M * ((aE.x - aW.x) + (bE.x - bW.x)) +
+                    Ny * (aCy - bCy) + My * ((aE.y - bE.y) + (aW.y - bW.y));
+        const R dn = n0[u];
+        n = nbar + dn;
+        const R rn = fast_rcp<R>(n);
+        const R jx = mC.jx, jy = mC.jy;
+        ux = jx * rn;
+        uy = jy * rn;
+        const R Fx = mC.Fx, Fy = mC.Fy;
+        const int wall = periodic ? 0 : (dd == 0 ? 1 : (dd == Ly - 1 ? 2 : 0));
+        if (wall == 1) {  // lower wall, speed Ub (Sec. II)
+          const R h = (R)0.5 * (g[1] - g[3]);
+          g[2] = g[4];
+          g[5] = g[7] - h - (R)0.25 * (Fx + Fy) + (R)0.5 * n * Ub;
+          g[6] = g[8] + h + (R)0.25 * (Fx - Fy) - (R)0.5 * n * Ub;
+          g[0] = dn - (g[1] + g[3]) - (R)2 * (g[4] + g[7] + g[8]) + (R)0.5 * Fy;
+        } else if (wall == 2) {  // upper wall: mirror image, speed Ut
+          const R h = (R)0.5 * (g[1] - g[3]);
+          g[4] = g[2];
+          g[7] = g[5] + h + (R)0.25 * (Fx + Fy) - (R)0.5 * n * Ut;
+          g[8] = g[6] - h - (R)0.25 * (Fx - Fy) + (R)0.5 * n * Ut;
+          g[0] = dn - (g[1] + g[3]) - (R)2 * (g[2] + g[5] + g[6]) - (R)0.5 * Fy;
         }
-        __syncthreads();
-        // ---- stage D: row d = a-3 --------------------------------------------
-        {
-          const int dd = a - 3;
-          if (dd >= y0 && dd <= y1 - 1 && actD) {
-            const R* nm = nR[(dd - 1) & 7];
-            const R* n0 = nR[dd & 7];
-            const R* np = nR[(dd + 1) & 7];
-            const R dnx = p.N * (n0[t + 1] - n0[t - 1]) +
-                          p.M * ((np[t + 1] - np[t - 1]) + (nm[t + 1] - nm[t - 1]));
-            const R dny = p.N * (np[t] - nm[t]) +
-                          p.M * ((np[t + 1] - nm[t + 1]) + (np[t - 1] - nm[t - 1]));
-            const R* xm_ = jxR[(dd - 1) & 3];
-            const R* x0_ = jxR[dd & 3];
-            const R* xp_ = jxR[(dd + 1) & 3];
-            const R* ym_ = jyR[(dd - 1) & 3];
-            const R* y0_ = jyR[dd & 3];
-            const R* yp_ = jyR[(dd + 1) & 3];
-            const R D = p.N * (x0_[t + 1] - x0_[t - 1]) +
-                        p.M * ((xp_[t + 1] - xp_[t - 1]) + (xm_[t + 1] - xm_[t - 1])) +
-                        p.N * (yp_[t] - ym_[t]) +
-                        p.M * ((yp_[t + 1] - ym_[t + 1]) + (yp_[t - 1] - ym_[t - 1]));
-            const R dn = n0[t];
-            const R n = p.nbar + dn;
-            const R inv = (R)1 / n;
-            const R ux = x0_[t] * inv, uy = y0_[t] * inv;
-            const R Fx = Fr[(s + 1) & 1][0], Fy = Fr[(s + 1) & 1][1];
-            R g[9];
+        collide<R>(g, cl, n, dn, jx, jy, rn, Fx, Fy, dnx, dny, D);
+      }
+      {
+        const __amdgpu_buffer_rsrc_t so = validD ? Sout : Snone;
+        const uint32_t roff = validD ? (uint32_t)dd * (uint32_t)rowb : 0u;
+        const int vst = actD ? vc : rowb;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) g[i] = f[(s + 1) & 3][i];
-            const int wall = periodic ? 0 : (dd == 0 ? 1 : (dd == Ly - 1 ? 2 : 0));
-            if (wall == 1) {  // lower wall, speed Ub (Sec. II)
-              const R h = (R)0.5 * (g[1] - g[3]);
-              g[2] = g[4];
-              g[5] = g[7] - h - (R)0.25 * (Fx + Fy) + (R)0.5 * n * p.Ub;
-              g[6] = g[8] + h + (R)0.25 * (Fx - Fy) - (R)0.5 * n * p.Ub;
-              g[0] = dn - (g[1] + g[3]) - (R)2 * (g[4] + g[7] + g[8]) + (R)0.5 * Fy;
-            } else if (wall == 2) {  // upper wall: mirror image, speed Ut
-              const R h = (R)0.5 * (g[1] - g[3]);
-              g[4] = g[2];
-              g[7] = g[5] + h + (R)0.25 * (Fx + Fy) - (R)0.5 * n * p.Ut;
-              g[8] = g[6] - h - (R)0.25 * (Fx - Fy) + (R)0.5 * n * p.Ut;
-              g[0] = dn - (g[1] + g[3]) - (R)2 * (g[2] + g[5] + g[6]) - (R)0.5 * Fy;
-            }
-            collide<R>(g, p, n, dn, ux, uy, Fx, Fy, dnx, dny, D);
-            const int64_t o = (int64_t)dd * Lx + xc;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) Sout[(int64_t)i * nn + o] = g[i];
-            if (wantMom) {
-              d.mom[o] = (double)n;
-              d.mom[nn + o] = (double)ux;
-              d.mom[2 * nn + o] = (double)uy;
-            }
-          }
+        for (int i = 0; i < 9; ++i) buf_st(g[i], so, vst, (int)((uint32_t)i * pbytes + roff));
+        if (MOM) {
+          const int64_t o = validD ? (int64_t)dd * Lx : 0;
+          const __amdgpu_buffer_rsrc_t mo = make_rsrc(d.mom + o, validD ? Lx * 8 : 0);
+          const int vo = actD ? xc * 8 : Lx * 8;
+          buf_st((double)n, mo, vo, 0);
+          buf_st((double)ux, mo, vo, (int)(nn * 8));
+          buf_st((double)uy, mo, vo, (int)(2 * nn * 8));
         }
       }
     }
@@ -390,8 +507,12 @@ __global__ __launch_bounds__(NT) void step_kernel(const Desc* __restrict__ descs
 template <typename R, int NT>
 static hipError_t launch_step_t(const Desc* dd, const Tile* dt, int ntiles, int parity, int flags,
                                 hipStream_t st) {
-  hipLaunchKernelGGL((step_kernel<R, NT>), dim3(ntiles), dim3(NT), 0, st, dd, dt, ntiles, parity,
-                     flags);
+  if (flags & kWriteMoments)
+    hipLaunchKernelGGL((step_kernel<R, NT, true>), dim3(ntiles), dim3(NT), 0, st, dd, dt, ntiles,
+                       parity, flags);
+  else
+    hipLaunchKernelGGL((step_kernel<R, NT, false>), dim3(ntiles), dim3(NT), 0, st, dd, dt, ntiles,
+                       parity, flags);
   return hipGetLastError();
 }
 

@@ -45,8 +45,10 @@ inline lb_status validate(const lb_params* p) {
   if (!p) return fail(LB_EINVAL, "params is NULL");
   if (p->Lx < 1) return fail(LB_EINVAL, "Lx must be >= 1 (got %d)", p->Lx);
   if (p->Ly < 4) return fail(LB_EINVAL, "Ly must be >= 4 (got %d)", p->Ly);
-  if ((int64_t)p->Lx * p->Ly > (int64_t)1 << 30)
-    return fail(LB_EINVAL, "Lx*Ly must be <= 2^30 nodes");
+  // the nine population planes of one buffer must stay below 4 GiB (32-bit
+  // buffer offsets in the step kernel)
+  if ((int64_t)p->Lx * p->Ly * 9 * (p->fp32 ? 4 : 8) >= ((int64_t)1 << 32))
+    return fail(LB_EINVAL, "9*Lx*Ly*(4|8) bytes must be < 4 GiB (FP32: < 119304647 nodes)");
   if (p->y_periodic != 0 && p->y_periodic != 1) return fail(LB_EINVAL, "y_periodic must be 0 or 1");
   if (p->fp32 != 0 && p->fp32 != 1) return fail(LB_EINVAL, "fp32 must be 0 or 1");
   if (!(p->T > 0.0 && p->T <= 1.5)) return fail(LB_EINVAL, "T must be in (0, 1.5] (got %g)", p->T);
@@ -99,21 +101,43 @@ inline int default_threads(const lb_params* p) {
   return 256;
 }
 
-// Rows per chunk: aim for about 1024 workgroups, at least 16 rows a chunk.
+// Workgroups of the step kernel that fit on the device at once: FP32 runs at
+// 4 waves per SIMD (128 VGPRs), FP64 at 2.
+inline int resident_slots(const lb_params* p, int threads) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  const int waves_per_cu = (p->fp32 ? 4 : 2) * 4;
+  return cus * std::max(1, waves_per_cu / (threads / 64));
+}
+
+// Rows per chunk: as few chunks as fill the resident workgroups once, and a
+// height of 2 mod 8 so the kernel's 8-row unrolled march has no idle tail.
 inline int default_rows(const lb_params* p, int threads) {
   const int strips = (p->Lx + threads - 7) / (threads - 6);
-  const int chunks = std::max(1, 1024 / strips);
+  const int chunks = std::max(1, resident_slots(p, threads) / strips);
   int rows = (p->Ly + chunks - 1) / chunks;
-  rows = std::max(rows, 16);
+  rows = ((std::max(rows, 10) - 2 + 7) / 8) * 8 + 2;
   return std::min(rows, p->Ly);
 }
 
+// Tiles of one lattice: strips of threads-6 columns, chunks of `rows` rows,
+// strip-major so consecutive tiles are vertical neighbours. Odd chunks march
+// downwards (sign bit of inst), so two neighbouring chunks reach their
+// shared boundary rows at the same time and share those loads in L2.
 inline std::vector<Tile> make_tiles(int inst, int Lx, int Ly, int threads, int rows) {
   std::vector<Tile> t;
   const int w = threads - 6;
-  // strip-major then chunk: consecutive tiles are vertical neighbours
-  for (int x0 = 0; x0 < Lx; x0 += w)
-    for (int y0 = 0; y0 < Ly; y0 += rows) t.push_back({inst, x0, y0, std::min(Ly, y0 + rows)});
+  for (int x0 = 0; x0 < Lx; x0 += w) {
+    int j = 0;
+    for (int y0 = 0; y0 < Ly; y0 += rows, ++j) {
+      const int code = (j & 1) ? (int)((unsigned)inst | 0x80000000u) : inst;
+      t.push_back({code, x0, y0, std::min(Ly, y0 + rows)});
+    }
+  }
   return t;
 }
 

@@ -21,7 +21,8 @@ struct Desc {
   double T, omega, kappa3, N, M, Q, R, U;
 };
 
-// A tile: instance, first column, first and one-past-last row.
+// A tile: instance (sign bit set: march downwards), first column, first and
+// one-past-last row.
 struct Tile {
   int32_t inst, x0, y0, y1;
 };

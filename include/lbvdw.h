@@ -72,7 +72,7 @@ typedef enum {
 
 typedef struct {
   int32_t Lx, Ly;         /* nodes; Lx >= 1, Ly >= 4; 9*Lx*Ly*(4 or 8 bytes)
-                             < 4 GiB (FP32 < 119.3M nodes, FP64 < 59.6M)      */
+                             < 2 GiB (FP32 < 59.6M nodes, FP64 < 29.8M)       */
   int32_t y_periodic;     /* 1: periodic in y; 0: moving walls at rows 0, Ly-1 */
   int32_t fp32;           /* 0: FP64 populations; 1: FP32 deviations          */
   double T;               /* reduced temperature, 0 < T <= 1.5                */

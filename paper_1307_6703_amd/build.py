@@ -1,7 +1,10 @@
 """Build the HIP library liblbvdw.so (gfx950) in-tree.
 
 Compiles csrc/lb_device.hip and csrc/lb_api.hip with hipcc for gfx950 only.
-Packed FP32 instructions are disabled for device code.
+Packed FP32 instructions are disabled for device code. Multiply-adds fuse only
+within one source expression (-ffp-contract=on), so the arithmetic of a node
+does not depend on how the compiler lays out a kernel instance: every launch
+shape gives bitwise-identical results.
 """
 import os
 import shutil
@@ -15,7 +18,7 @@ LIB = os.path.join(HERE, "liblbvdw.so")
 SOURCES = ["lb_device.hip", "lb_api.hip", "lb_batch.hip"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]

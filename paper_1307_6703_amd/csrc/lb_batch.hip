@@ -80,8 +80,11 @@ struct lb_batch {
   bool pending_shift = false;
   bool unstable_any = false;
   std::vector<int> unstable;
-  // graphs of kGraphSteps steps, keyed by the pending-shift state at entry
+  // graphs of kGraphSteps steps, keyed by the pending-shift state at entry;
+  // recorded on a private stream (the caller's may be the null stream, which
+  // cannot be captured) and replayed on the caller's
   hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipStream_t rec = nullptr;
   int exec_threads = 0, exec_rows = 0;
 };
 
@@ -171,9 +174,13 @@ lb_status replay(lb_batch* b) {
     const int par0 = b->parity;
     const int64_t step0 = b->step;
     const bool pend0 = b->pending_shift;
-    HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+    if (!b->rec) HIPCHK(hipStreamCreateWithFlags(&b->rec, hipStreamNonBlocking));
+    hipStream_t user = b->st;
+    b->st = b->rec;
+    HIPCHK(hipStreamBeginCapture(b->rec, hipStreamCaptureModeThreadLocal));
     lb_status r = enqueue_steps(b, kGraphSteps, false);
-    hipError_t e = hipStreamEndCapture(b->st, &g);
+    hipError_t e = hipStreamEndCapture(b->rec, &g);
+    b->st = user;
     // recording did not run anything: restore the counters
     b->parity = par0;
     b->step = step0;
@@ -344,14 +351,16 @@ lb_status lb_batch_step_n(lb_batch* b, int64_t nsteps) {
   if (nsteps == 0) return LB_OK;
   int64_t left = nsteps;
   lb_status r;
-  // eager steps up to a point where a recorded run can start
-  while (left > 1 && !graph_aligned(b)) {
-    if ((r = enqueue_steps(b, 1, false)) != LB_OK) return r;
-    --left;
-  }
-  while (left > kGraphSteps) {  // keep the last step eager: it writes the moments
-    if ((r = replay(b)) != LB_OK) return r;
-    left -= kGraphSteps;
+  // recorded runs where the step count is on the check grid; eager steps in
+  // between; the last step is always eager (it writes the moments)
+  while (left > 1) {
+    if (left > kGraphSteps && graph_aligned(b)) {
+      if ((r = replay(b)) != LB_OK) return r;
+      left -= kGraphSteps;
+    } else {
+      if ((r = enqueue_steps(b, 1, false)) != LB_OK) return r;
+      --left;
+    }
   }
   if ((r = enqueue_steps(b, left, true)) != LB_OK) return r;
   for (auto& I : b->inst) I.moments_valid = true;
@@ -454,6 +463,7 @@ lb_status lb_batch_destroy(lb_batch* b) {
   if (!b) return LB_OK;
   (void)hipStreamSynchronize(b->st);
   drop_graphs(b);
+  if (b->rec) (void)hipStreamDestroy(b->rec);
   delete b;
   return LB_OK;
 }

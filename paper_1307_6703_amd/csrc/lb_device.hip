@@ -189,11 +189,11 @@ __device__ __forceinline__ RowMap map_row(int a, int Ly, int periodic) {
 // Buffer loads and stores: one buffer resource per population array
 // (uniform); the plane and row as a scalar byte offset and the column as a
 // per-lane byte offset, so no per-lane 64-bit address arithmetic is needed.
-// The range check of a raw buffer access covers the per-lane offset only, so
-// num_records = one row's bytes bounds every access to its row; a lane or a
-// row that must not touch memory uses an offset at that bound (or a resource
-// with num_records = 0) and the hardware drops the store / returns 0. All
-// nine planes of an array lie within 4 GiB (checked on the host).
+// The hardware range check compares scalar + lane offset with num_records
+// (the array's size): a lane that must not touch memory uses a lane offset
+// equal to num_records, a row that must not touch memory uses a resource
+// with num_records = 0, and the hardware drops the store / returns 0. The
+// host keeps every array below 2 GiB, so the two offsets never wrap 32 bits.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int num_records) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, num_records,
                                            0x00020000);
@@ -299,9 +299,10 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void step_kernel(
   const Desc& d = descs[inst];
   const int Lx = d.Lx, Ly = d.Ly, periodic = d.periodic;
   const int64_t nn = (int64_t)Lx * Ly;
-  const int rowb = Lx * (int)sizeof(R);  // bytes of one row = num_records
-  const __amdgpu_buffer_rsrc_t Sin = make_rsrc(d.S[parity], rowb);
-  const __amdgpu_buffer_rsrc_t Sout = make_rsrc(d.S[parity ^ 1], rowb);
+  const int rowb = Lx * (int)sizeof(R);            // bytes of one row
+  const int arrb = (int)(9 * nn * (int64_t)sizeof(R));  // bytes of the nine planes (< 2 GiB)
+  const __amdgpu_buffer_rsrc_t Sin = make_rsrc(d.S[parity], arrb);
+  const __amdgpu_buffer_rsrc_t Sout = make_rsrc(d.S[parity ^ 1], arrb);
   const __amdgpu_buffer_rsrc_t Snone = make_rsrc(d.S[parity ^ 1], 0);  // drops every access
   const R* __restrict__ fext3 = (const R*)d.fext3;
   const Coll<R> cl = make_coll<R>(d);
@@ -326,10 +327,10 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void step_kernel(
   const bool actB = t >= 1 && t < W + 5;
   const bool actC = t >= 2 && t < W + 4;
   const bool actD = t >= 3 && t < W + 3;
-  // per-lane byte offsets; lanes outside the strip use the row bound (dropped)
-  const int vc = actA ? xc * (int)sizeof(R) : rowb;
-  const int vm = actA ? xm * (int)sizeof(R) : rowb;
-  const int vp = actA ? xp * (int)sizeof(R) : rowb;
+  // per-lane byte offsets; lanes outside the strip use the array bound (dropped)
+  const int vc = actA ? xc * (int)sizeof(R) : arrb;
+  const int vm = actA ? xm * (int)sizeof(R) : arrb;
+  const int vp = actA ? xp * (int)sizeof(R) : arrb;
   const R fx3 = actC ? fext3[xc] : (R)0;
   const uint32_t pbytes = (uint32_t)(nn * (int64_t)sizeof(R));
 
@@ -488,16 +489,17 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void step_kernel(
       {
         const __amdgpu_buffer_rsrc_t so = validD ? Sout : Snone;
         const uint32_t roff = validD ? (uint32_t)dd * (uint32_t)rowb : 0u;
-        const int vst = actD ? vc : rowb;
+        const int vst = actD ? vc : arrb;
 #pragma unroll
         for (int i = 0; i < 9; ++i) buf_st(g[i], so, vst, (int)((uint32_t)i * pbytes + roff));
         if (MOM) {
-          const int64_t o = validD ? (int64_t)dd * Lx : 0;
-          const __amdgpu_buffer_rsrc_t mo = make_rsrc(d.mom + o, validD ? Lx * 8 : 0);
-          const int vo = actD ? xc * 8 : Lx * 8;
-          buf_st((double)n, mo, vo, 0);
-          buf_st((double)ux, mo, vo, (int)(nn * 8));
-          buf_st((double)uy, mo, vo, (int)(2 * nn * 8));
+          const int momb = (int)(3 * nn * 8);
+          const __amdgpu_buffer_rsrc_t mo = make_rsrc(d.mom, validD ? momb : 0);
+          const int vo = actD ? xc * 8 : momb;
+          const int ro = validD ? dd * Lx * 8 : 0;
+          buf_st((double)n, mo, vo, ro);
+          buf_st((double)ux, mo, vo, (int)(nn * 8) + ro);
+          buf_st((double)uy, mo, vo, (int)(2 * nn * 8) + ro);
         }
       }
     }

@@ -45,10 +45,10 @@ inline lb_status validate(const lb_params* p) {
   if (!p) return fail(LB_EINVAL, "params is NULL");
   if (p->Lx < 1) return fail(LB_EINVAL, "Lx must be >= 1 (got %d)", p->Lx);
   if (p->Ly < 4) return fail(LB_EINVAL, "Ly must be >= 4 (got %d)", p->Ly);
-  // the nine population planes of one buffer must stay below 4 GiB (32-bit
-  // buffer offsets in the step kernel)
-  if ((int64_t)p->Lx * p->Ly * 9 * (p->fp32 ? 4 : 8) >= ((int64_t)1 << 32))
-    return fail(LB_EINVAL, "9*Lx*Ly*(4|8) bytes must be < 4 GiB (FP32: < 119304647 nodes)");
+  // the nine population planes of one buffer must stay below 2 GiB (32-bit
+  // buffer offsets in the step kernel, range-checked without wrapping)
+  if ((int64_t)p->Lx * p->Ly * 9 * (p->fp32 ? 4 : 8) >= ((int64_t)1 << 31))
+    return fail(LB_EINVAL, "9*Lx*Ly*(4|8) bytes must be < 2 GiB (FP32: < 59652323 nodes)");
   if (p->y_periodic != 0 && p->y_periodic != 1) return fail(LB_EINVAL, "y_periodic must be 0 or 1");
   if (p->fp32 != 0 && p->fp32 != 1) return fail(LB_EINVAL, "fp32 must be 0 or 1");
   if (!(p->T > 0.0 && p->T <= 1.5)) return fail(LB_EINVAL, "T must be in (0, 1.5] (got %g)", p->T);

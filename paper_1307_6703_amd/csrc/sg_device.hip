@@ -1,0 +1,497 @@
+// Learned surrogate kernels for gfx950: 3x3 convolutions as implicit GEMMs on
+// BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation), their
+// backward passes, the loss, Adam, and the packing between lattice fields and
+// network tensors.
+//
+// Tensors are NHWC bf16: [batch, rows (y), columns (x), channels], channels a
+// multiple of 8. A 3x3 convolution wraps around in x (periodic lattice) and
+// sees zeros beyond the first and last rows (walls). Weights are kept in FP32
+// as w[tap][ci][co], tap = (dy+1)*3 + (dx+1), and packed for the kernels as
+// bf16 B-matrices [co][k], k = tap*CI + ci, padded with zeros to a multiple
+// of 32 in k.
+//
+// MFMA operand layout (16x16x32): lane l holds A[m = l%16][k = 8(l/16) .. +7],
+// B[k = 8(l/16) .. +7][n = l%16]; the accumulator holds D[m = 4(l/16) + r][n = l%16],
+// r = 0..3.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sg_internal.h"
+
+namespace sg {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int TW = 64;   // output columns per conv tile
+constexpr int TR = 4;    // output rows per conv tile (one per wave)
+constexpr int NTH = 256; // threads per workgroup
+
+__device__ __forceinline__ float bf2f(bf16 v) { return (float)v; }
+__device__ __forceinline__ bf16 f2bf(float v) { return (bf16)v; }  // round to nearest even
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_grad(float z) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+template <int CI>
+__host__ __device__ constexpr int kpad() { return (9 * CI + 31) / 32 * 32; }
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution (forward, or input-gradient with flipped weights).
+// Persistent workgroups: the packed weights are staged in LDS once, then each
+// workgroup walks tiles of TR rows x TW columns of one image. Each wave owns
+// one output row: 4 M-subtiles of 16 pixels by CO/16 N-subtiles.
+// ---------------------------------------------------------------------------
+template <int CI, int CO, int MODE>
+__global__ __launch_bounds__(NTH) void conv_kernel(ConvArgs a) {
+  constexpr int K = 9 * CI, KP = kpad<CI>(), NS = CO / 16;
+  constexpr int PX = CI + 8;   // LDS pixel stride (elements): conflict-free 16-byte reads
+  constexpr int WS = KP + 8;   // LDS weight row stride
+  constexpr int TCOLS = TW + 2, TROWS = TR + 2;
+  __shared__ __attribute__((aligned(16))) bf16 sx[TROWS * TCOLS * PX];
+  __shared__ __attribute__((aligned(16))) bf16 sw[CO * WS];
+
+  const int tid = threadIdx.x;
+  for (int i = tid; i < CO * (KP / 8); i += NTH) {
+    const int co = i / (KP / 8), c = i % (KP / 8);
+    *(uint4*)&sw[co * WS + c * 8] = ((const uint4*)a.w)[i];
+  }
+
+  const int tilesX = (a.W + TW - 1) / TW, tilesY = (a.H + TR - 1) / TR;
+  const int ntiles = tilesX * tilesY * a.B;
+  const int wave = tid >> 6, lane = tid & 63, lm = lane & 15, lg = lane >> 4;
+
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int tx = tile % tilesX;
+    const int ty = (tile / tilesX) % tilesY;
+    const int img = tile / (tilesX * tilesY);
+    const int x0 = tx * TW, h0 = ty * TR;
+    __syncthreads();  // previous tile's reads of sx are done (and sw is staged)
+    {
+      constexpr int CH = CI / 8;
+      for (int i = tid; i < TROWS * TCOLS * CH; i += NTH) {
+        const int c = i % CH, pix = i / CH;
+        const int col = pix % TCOLS, row = pix / TCOLS;
+        const int h = h0 - 1 + row;
+        int xx = (x0 - 1 + col) % a.W;
+        if (xx < 0) xx += a.W;
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (h >= 0 && h < a.H)
+          v = *(const uint4*)(a.x + (((int64_t)img * a.H + h) * a.W + xx) * CI + c * 8);
+        *(uint4*)&sx[(row * TCOLS + col) * PX + c * 8] = v;
+      }
+    }
+    __syncthreads();
+
+    f32x4 acc[4][NS];
+#pragma unroll
+    for (int ms = 0; ms < 4; ++ms)
+#pragma unroll
+      for (int ns = 0; ns < NS; ++ns) acc[ms][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+    for (int kc = 0; kc < KP / 32; ++kc) {
+      const int k = kc * 32 + lg * 8;  // this lane's 8 consecutive k (one tap)
+      const bool kv = k < K;
+      const int tap = kv ? k / CI : 0, ci0 = kv ? k % CI : 0;
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      bf16x8 bfr[NS];
+#pragma unroll
+      for (int ns = 0; ns < NS; ++ns) bfr[ns] = *(const bf16x8*)&sw[(ns * 16 + lm) * WS + k];
+#pragma unroll
+      for (int ms = 0; ms < 4; ++ms) {
+        bf16x8 afr = *(const bf16x8*)&sx[((wave + 1 + dy) * TCOLS + (ms * 16 + lm + 1 + dx)) * PX + ci0];
+        if (!kv) afr = bf16x8{};
+#pragma unroll
+        for (int ns = 0; ns < NS; ++ns)
+          acc[ms][ns] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[ns], acc[ms][ns], 0, 0, 0);
+      }
+    }
+
+    // epilogue: D[m][n] -> pixel x0 + 16 ms + 4 lg + r, channel 16 ns + lm
+    const int h = h0 + wave;
+    if (h < a.H) {
+#pragma unroll
+      for (int ms = 0; ms < 4; ++ms)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int xx = x0 + ms * 16 + lg * 4 + r;
+          if (xx >= a.W) continue;
+          const int64_t p = ((int64_t)img * a.H + h) * a.W + xx;
+#pragma unroll
+          for (int ns = 0; ns < NS; ++ns) {
+            const int co = ns * 16 + lm;
+            const float v = acc[ms][ns][r] + (a.bias ? a.bias[co] : 0.f);
+            if (MODE == FWD_FIRST) {
+              a.y[p * CO + co] = f2bf(silu(v));
+              if (a.z) a.z[p * CO + co] = f2bf(v);
+            } else if (MODE == FWD_RES) {
+              a.y[p * CO + co] = f2bf(bf2f(a.res[p * CO + co]) + silu(v));
+              if (a.z) a.z[p * CO + co] = f2bf(v);
+            } else if (MODE == FWD_OUT) {
+              if (co < a.nout) a.yf[p * a.nout + co] = v;
+            } else {  // BWD: v = dL/dh of this layer's input (+ the residual path)
+              const float g = v + (a.res ? bf2f(a.res[p * CO + co]) : 0.f);
+              if (a.z) a.z[p * CO + co] = f2bf(g);
+              a.y[p * CO + co] = f2bf(g * silu_grad(bf2f(a.zprev[p * CO + co])));
+            }
+          }
+        }
+    }
+  }
+}
+
+template <int CI, int CO, int MODE>
+static hipError_t launch_conv_t(const ConvArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((conv_kernel<CI, CO, MODE>), dim3(grid), dim3(NTH), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_conv(int ci, int co, int mode, const ConvArgs& a, int grid, hipStream_t st) {
+#define SG_CONV(CI_, CO_)                                                     \
+  if (ci == CI_ && co == CO_) {                                               \
+    if (mode == FWD_FIRST) return launch_conv_t<CI_, CO_, FWD_FIRST>(a, grid, st); \
+    if (mode == FWD_RES) return launch_conv_t<CI_, CO_, FWD_RES>(a, grid, st);     \
+    if (mode == FWD_OUT) return launch_conv_t<CI_, CO_, FWD_OUT>(a, grid, st);     \
+    if (mode == BWD) return launch_conv_t<CI_, CO_, BWD>(a, grid, st);             \
+  }
+  SG_CONV(8, 48)
+  SG_CONV(48, 48)
+  SG_CONV(48, 16)
+  SG_CONV(16, 48)
+#undef SG_CONV
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: dW[tap*CI + ci][co] = sum_p x[p + tap][ci] gz[p][co], a GEMM
+// with the pixels as the contraction. A persistent workgroup walks row
+// segments of 64 pixels; it stages the nine shifted copies of the input (one
+// per tap) and the output gradient in LDS, transposed so that pixels are
+// contiguous, and accumulates its share of the 9CI x CO tiles in registers.
+// Partial sums per workgroup go to `part`; wgrad_reduce adds them in a fixed
+// order.
+// ---------------------------------------------------------------------------
+template <int CI, int CO>
+__global__ __launch_bounds__(NTH) void wgrad_kernel(WgradArgs a) {
+  constexpr int M = 9 * CI, MS = (M + 15) / 16, NS = CO / 16;
+  constexpr int SEG = 64, PS = SEG + 8;  // pixels per segment, LDS row stride
+  constexpr int MPW = (MS + 3) / 4;      // M-subtiles per wave (strided by 4)
+  __shared__ __attribute__((aligned(16))) bf16 sa[MS * 16 * PS];  // A^T[m][p]
+  __shared__ __attribute__((aligned(16))) bf16 sg[CO * PS];       // gz^T[co][p]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lm = lane & 15, lg = lane >> 4;
+
+  f32x4 acc[MPW][NS];
+#pragma unroll
+  for (int i = 0; i < MPW; ++i)
+#pragma unroll
+    for (int ns = 0; ns < NS; ++ns) acc[i][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // rows of A^T past M stay zero
+  for (int i = tid; i < (MS * 16 - M) * PS; i += NTH) sa[M * PS + i] = (bf16)0.f;
+
+  const int segX = (a.W + SEG - 1) / SEG;
+  const int nseg = segX * a.H * a.B;
+  for (int sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
+    const int sx = sgi % segX, h = (sgi / segX) % a.H, img = sgi / (segX * a.H);
+    const int x0 = sx * SEG;
+    __syncthreads();
+    // A^T[tap*CI + ci][p] = x[h + dy][x0 + p + dx][ci] (0 outside rows, or past W)
+    for (int i = tid; i < 9 * SEG * (CI / 8); i += NTH) {
+      const int c8 = i % (CI / 8), p = (i / (CI / 8)) % SEG, tap = i / ((CI / 8) * SEG);
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      const int hh = h + dy;
+      int xx = (x0 + p + dx) % a.W;
+      if (xx < 0) xx += a.W;
+      bf16x8 v = bf16x8{};
+      if (hh >= 0 && hh < a.H && x0 + p < a.W)
+        v = *(const bf16x8*)(a.x + (((int64_t)img * a.H + hh) * a.W + xx) * CI + c8 * 8);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sa[(tap * CI + c8 * 8 + j) * PS + p] = v[j];
+    }
+    for (int i = tid; i < SEG * (CO / 8); i += NTH) {
+      const int c8 = i % (CO / 8), p = i / (CO / 8);
+      bf16x8 v = bf16x8{};
+      if (x0 + p < a.W)
+        v = *(const bf16x8*)(a.gz + (((int64_t)img * a.H + h) * a.W + x0 + p) * CO + c8 * 8);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sg[(c8 * 8 + j) * PS + p] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kc = 0; kc < SEG / 32; ++kc) {
+      const int k = kc * 32 + lg * 8;
+      bf16x8 bfr[NS];
+#pragma unroll
+      for (int ns = 0; ns < NS; ++ns) bfr[ns] = *(const bf16x8*)&sg[(ns * 16 + lm) * PS + k];
+#pragma unroll
+      for (int i = 0; i < MPW; ++i) {
+        const int ms = wave + 4 * i;
+        if (ms < MS) {  // uniform per wave
+          const bf16x8 afr = *(const bf16x8*)&sa[(ms * 16 + lm) * PS + k];
+#pragma unroll
+          for (int ns = 0; ns < NS; ++ns)
+            acc[i][ns] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[ns], acc[i][ns], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // partial sums of this workgroup: part[block][m][co]
+  float* out = a.part + (int64_t)blockIdx.x * M * CO;
+#pragma unroll
+  for (int i = 0; i < MPW; ++i) {
+    const int ms = wave + 4 * i;
+    if (ms >= MS) continue;
+#pragma unroll
+    for (int ns = 0; ns < NS; ++ns)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = ms * 16 + lg * 4 + r, co = ns * 16 + lm;
+        if (m < M) out[m * CO + co] = acc[i][ns][r];
+      }
+  }
+}
+
+template <int CI, int CO>
+static hipError_t launch_wgrad_t(const WgradArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((wgrad_kernel<CI, CO>), dim3(grid), dim3(NTH), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad(int ci, int co, const WgradArgs& a, int grid, hipStream_t st) {
+  if (ci == 8 && co == 48) return launch_wgrad_t<8, 48>(a, grid, st);
+  if (ci == 48 && co == 48) return launch_wgrad_t<48, 48>(a, grid, st);
+  if (ci == 48 && co == 16) return launch_wgrad_t<48, 16>(a, grid, st);
+  return hipErrorInvalidValue;
+}
+
+// Fixed-order sum of the workgroup partials: dw[i] = scale * sum_b part[b][i].
+__global__ void wgrad_reduce_kernel(const float* __restrict__ part, int nblk, int n, float scale,
+                                    float* __restrict__ dw) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * n + i];
+  dw[i] = (float)(s * scale);
+}
+
+hipError_t launch_wgrad_reduce(const float* part, int nblk, int n, float scale, float* dw,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, st, part, nblk, n,
+                     scale, dw);
+  return hipGetLastError();
+}
+
+// Bias gradient: db[co] = scale * sum_p gz[p][co], fixed order (one thread per
+// channel, a block per channel group, partials per block then a final pass).
+__global__ void bias_grad_kernel(const bf16* __restrict__ gz, int64_t npix, int C, int ncount,
+                                 float scale, float* __restrict__ part, float* __restrict__ db,
+                                 int stage) {
+  if (stage == 0) {
+    // part[blk][c] over pixels blk, blk + nblk, ...
+    const int c = threadIdx.x;
+    if (c >= C) return;
+    double s = 0.0;
+    for (int64_t p = blockIdx.x; p < npix; p += gridDim.x) s += (double)(float)gz[p * C + c];
+    part[blockIdx.x * C + c] = (float)s;
+  } else {
+    const int c = threadIdx.x;
+    if (c >= C) return;
+    double s = 0.0;
+    for (int b = 0; b < ncount; ++b) s += part[b * C + c];
+    if (c < ncount * 0 + C) db[c] = (float)(s * scale);
+  }
+}
+
+hipError_t launch_bias_grad(const bf16* gz, int64_t npix, int C, int nreal, float scale,
+                            float* part, float* db, hipStream_t st) {
+  const int nb = 1024;
+  hipLaunchKernelGGL(bias_grad_kernel, dim3(nb), dim3(64), 0, st, gz, npix, C, nb, scale, part, db, 0);
+  hipLaunchKernelGGL(bias_grad_kernel, dim3(1), dim3(64), 0, st, gz, npix, nreal, nb, scale, part, db, 1);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Loss: mean squared error over the nout real output channels, FP32 inputs;
+// writes the gradient of the summed loss, 2 (pred - target), as bf16 with
+// CO channels (zeros past nout), and per-block FP64 partial sums.
+// ---------------------------------------------------------------------------
+__global__ void mse_kernel(const float* __restrict__ pred, const float* __restrict__ target,
+                           int64_t npix, int nout, int CO, bf16* __restrict__ gout,
+                           double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    for (int c = 0; c < CO; ++c) {
+      float g = 0.f;
+      if (c < nout) {
+        const float d = pred[p * nout + c] - target[p * nout + c];
+        s += (double)d * d;
+        g = 2.f * d;
+      }
+      gout[p * CO + c] = f2bf(g);
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void sum_partials_kernel(const double* __restrict__ part, int n, double scale,
+                                    double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *out = s * scale;
+  }
+}
+
+hipError_t launch_mse(const float* pred, const float* target, int64_t npix, int nout, int CO,
+                      bf16* gout, double* part, double* loss, hipStream_t st) {
+  const int nb = 512;
+  hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, st, pred, target, npix, nout, CO, gout, part);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, st, part, nb,
+                     1.0 / ((double)npix * nout), loss);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adam on FP32 master parameters (Kingma and Ba), step t counted from 1.
+// ---------------------------------------------------------------------------
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                            float* __restrict__ m, float* __restrict__ v, int n, float lr,
+                            float b1, float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1,
+                       float b2, float eps, int t, hipStream_t st) {
+  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, g, m, v, n, lr, b1,
+                     b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Weight packing: FP32 w[tap][ci][co] (ci < cir, co < cor real channels) into
+// bf16 B-matrices. Forward: wp[co][tap*CI + ci]. Input gradient (transposed
+// convolution, flipped taps): wp[ci][tap'*CO + co] = w[8 - tap'][ci][co].
+// ---------------------------------------------------------------------------
+__global__ void pack_kernel(const float* __restrict__ w, int cir, int cor, int CI, int CO,
+                            int transposed, bf16* __restrict__ wp) {
+  // forward: rows = CO, k over 9*CI; transposed: rows = CI, k over 9*CO
+  const int rows = transposed ? CI : CO;
+  const int kin = transposed ? CO : CI;
+  const int KPd = (9 * kin + 31) / 32 * 32;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * KPd) return;
+  const int row = i / KPd, k = i % KPd;
+  float v = 0.f;
+  if (k < 9 * kin) {
+    const int tap = k / kin, c = k % kin;
+    if (!transposed) {
+      if (c < cir && row < cor) v = w[(tap * cir + c) * cor + row];
+    } else {
+      if (row < cir && c < cor) v = w[((8 - tap) * cir + row) * cor + c];
+    }
+  }
+  wp[i] = f2bf(v);
+}
+
+hipError_t launch_pack(const float* w, int cir, int cor, int CI, int CO, int transposed, bf16* wp,
+                       hipStream_t st) {
+  const int rows = transposed ? CI : CO;
+  const int kin = transposed ? CO : CI;
+  const int n = rows * ((9 * kin + 31) / 32 * 32);
+  hipLaunchKernelGGL(pack_kernel, dim3((n + 255) / 256), dim3(256), 0, st, w, cir, cor, CI, CO,
+                     transposed, wp);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fields <-> network tensors.
+// Input channels (8, bf16): (n - 1) s_n, u_x s_u, u_y s_u, V(x) s_v, wall speed
+// s_u on the wall rows (0 elsewhere), (T - 0.9) s_t, 0, 0. Target / output
+// channels (3, FP32): change over K steps, (dn s_n, du_x s_u, du_y s_u).
+// ---------------------------------------------------------------------------
+__global__ void fields_to_input_kernel(const double* __restrict__ mom, int64_t nn, int H, int W,
+                                       const float* __restrict__ vx, float uwall, float temp,
+                                       int walls, Scales s, bf16* __restrict__ x) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nn;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int h = (int)(k / W), xx = (int)(k % W);
+    float c[8];
+    c[0] = (float)((mom[k] - 1.0) * s.n);
+    c[1] = (float)(mom[nn + k] * s.u);
+    c[2] = (float)(mom[2 * nn + k] * s.u);
+    c[3] = vx[xx] * s.v;
+    c[4] = walls ? (h == 0 ? -uwall * s.u : (h == H - 1 ? uwall * s.u : 0.f)) : 0.f;
+    c[5] = (temp - 0.9f) * s.t;
+    c[6] = 0.f;
+    c[7] = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[k * 8 + j] = f2bf(c[j]);
+  }
+}
+
+hipError_t launch_fields_to_input(const double* mom, int64_t nn, int H, int W, const float* vx,
+                                  float uwall, float temp, int walls, Scales s, bf16* x,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(fields_to_input_kernel, dim3((int)((nn + 255) / 256)), dim3(256), 0, st, mom,
+                     nn, H, W, vx, uwall, temp, walls, s, x);
+  return hipGetLastError();
+}
+
+// target[p][c] = (fields(t+K) - fields(t)) scaled, from two FP64 moment blocks
+__global__ void make_target_kernel(const double* __restrict__ m0, const double* __restrict__ m1,
+                                   int64_t nn, Scales s, float* __restrict__ target) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nn;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    target[k * 3 + 0] = (float)((m1[k] - m0[k]) * s.n);
+    target[k * 3 + 1] = (float)((m1[nn + k] - m0[nn + k]) * s.u);
+    target[k * 3 + 2] = (float)((m1[2 * nn + k] - m0[2 * nn + k]) * s.u);
+  }
+}
+
+hipError_t launch_make_target(const double* m0, const double* m1, int64_t nn, Scales s,
+                              float* target, hipStream_t st) {
+  hipLaunchKernelGGL(make_target_kernel, dim3((int)((nn + 255) / 256)), dim3(256), 0, st, m0, m1,
+                     nn, s, target);
+  return hipGetLastError();
+}
+
+// predicted fields (FP64) = fields(t) + output / scales
+__global__ void apply_output_kernel(const double* __restrict__ m0, const float* __restrict__ out,
+                                    int64_t nn, Scales s, double* __restrict__ m1) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nn;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    m1[k] = m0[k] + (double)out[k * 3 + 0] / s.n;
+    m1[nn + k] = m0[nn + k] + (double)out[k * 3 + 1] / s.u;
+    m1[2 * nn + k] = m0[2 * nn + k] + (double)out[k * 3 + 2] / s.u;
+  }
+}
+
+hipError_t launch_apply_output(const double* m0, const float* out, int64_t nn, Scales s,
+                               double* m1, hipStream_t st) {
+  hipLaunchKernelGGL(apply_output_kernel, dim3((int)((nn + 255) / 256)), dim3(256), 0, st, m0,
+                     out, nn, s, m1);
+  return hipGetLastError();
+}
+
+}  // namespace sg

@@ -72,6 +72,39 @@ def cpu_baseline(w, n0, fext, seconds: float):
             "sample": f"{total} FP64 steps of the full {w.Lx}x{w.Ly} lattice ({dt:.1f} s)"}
 
 
+def batched_bench(steps: int, seed: int = 1307):
+    """The batched sweep: 96 uneven lattices advanced together (one launch per
+    step over all their tiles, HIP-graph replay), autotuned launch shape.
+    Returns aggregate MLUPS = sum of nodes x steps / time."""
+    import torch
+    import lbsynth as ls
+    from paper_1307_6703_amd import Batch
+    draws = ls.batch_draws(96, seed=seed)
+    specs = [dict(Lx=w.Lx, Ly=w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, U=w.U,
+                  fext=w.fext()) for w in draws]
+    b = Batch(specs, fp32=True, check_every=100, drift_correct=True)
+    for i, w in enumerate(draws):
+        b.init(i, w.n0())
+    th, rw, _ = b.autotune(nsteps=4)
+    b.step(100)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    status = b.status()
+    out = {"instances": len(draws), "nodes": b.nodes, "steps": steps,
+           "MLUPS": round(b.nodes * steps / (ms * 1e-3) / 1e6, 1),
+           "ms_per_step": round(ms / steps, 4), "launch": {"threads": th, "rows": rw},
+           "unstable_instances": sum(1 for v in status if v != 0),
+           "workload": "96 draws: Lx in {128..1024}, Ly in {64,128,256}, T in [0.85,0.98], "
+                       "V0 in [0,0.02], k in {2,4,8}, U in [0,0.08], FP32"}
+    b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,7 +115,22 @@ def main():
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--batched-steps", type=int, default=2000,
+                    help="steps of the 96-lattice batched sweep reported beside the headline (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of 1 GiB (for scaling HBM counters)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                          "launches": 3}), flush=True)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the lattice fits one GPU's HBM and this build "
@@ -182,6 +230,9 @@ def main():
     lat.close()
     del lat
     torch.cuda.empty_cache()
+    if args.batched_steps > 0:
+        out["batched"] = batched_bench(args.batched_steps)
+        print(f"[bench] batched: {out['batched']['MLUPS']} MLUPS", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, n0, fext, args.cpu_seconds)
     print(json.dumps(out), flush=True)

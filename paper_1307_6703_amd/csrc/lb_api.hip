@@ -48,8 +48,9 @@ lb_status upload_desc(lb_handle* h) {
 }
 
 lb_status set_tiles(lb_handle* h, int threads, int rows) {
-  if (threads != 64 && threads != 128 && threads != 256)
-    return fail(LB_EINVAL, "threads must be 64, 128 or 256 (got %d)", threads);
+  if (threads != 64 && threads != 128 && threads != 256 && threads != 320 &&
+      !(threads == 512 && h->p.fp32))
+    return fail(LB_EINVAL, "threads must be 64, 128, 256, 320 or 512 (FP32 only) (got %d)", threads);
   if (rows < 1) return fail(LB_EINVAL, "rows must be >= 1");
   rows = std::max(std::min(rows, h->p.Ly), std::min(kMinRows, h->p.Ly));
   std::vector<Tile> t = make_tiles(0, h->p.Lx, h->p.Ly, threads, rows);

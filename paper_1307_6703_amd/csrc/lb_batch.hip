@@ -101,8 +101,9 @@ void drop_graphs(lb_batch* b) {
 }
 
 lb_status batch_tiles(lb_batch* b, int threads, int rows) {
-  if (threads != 64 && threads != 128 && threads != 256)
-    return fail(LB_EINVAL, "threads must be 64, 128 or 256 (got %d)", threads);
+  if (threads != 64 && threads != 128 && threads != 256 && threads != 320 &&
+      !(threads == 512 && b->fp32))
+    return fail(LB_EINVAL, "threads must be 64, 128, 256, 320 or 512 (FP32 only) (got %d)", threads);
   if (rows < 1) return fail(LB_EINVAL, "rows must be >= 1");
   // largest instances first: the dispatcher hands out tiles in order, so the
   // long-running ones start early

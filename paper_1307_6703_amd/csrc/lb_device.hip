@@ -525,10 +525,13 @@ hipError_t launch_step(bool fp32, int threads, const Desc* d_descs, const Tile* 
     if (threads == 64) return launch_step_t<float, 64>(d_descs, d_tiles, ntiles, parity, flags, stream);
     if (threads == 128) return launch_step_t<float, 128>(d_descs, d_tiles, ntiles, parity, flags, stream);
     if (threads == 256) return launch_step_t<float, 256>(d_descs, d_tiles, ntiles, parity, flags, stream);
+    if (threads == 320) return launch_step_t<float, 320>(d_descs, d_tiles, ntiles, parity, flags, stream);
+    if (threads == 512) return launch_step_t<float, 512>(d_descs, d_tiles, ntiles, parity, flags, stream);
   } else {
     if (threads == 64) return launch_step_t<double, 64>(d_descs, d_tiles, ntiles, parity, flags, stream);
     if (threads == 128) return launch_step_t<double, 128>(d_descs, d_tiles, ntiles, parity, flags, stream);
     if (threads == 256) return launch_step_t<double, 256>(d_descs, d_tiles, ntiles, parity, flags, stream);
+    if (threads == 320) return launch_step_t<double, 320>(d_descs, d_tiles, ntiles, parity, flags, stream);
   }
   return hipErrorInvalidValue;
 }
@@ -669,18 +672,35 @@ hipError_t launch_reduce(bool fp32, const Desc* d_desc, int parity, int64_t nn, 
   return hipGetLastError();
 }
 
-// One thread combines the partials in block order (fixed order: the same
-// state always gives the same bits). mode 0: check (update the sticky status
-// and the drift shift); 1: set the reference mass; 2: report only.
-__global__ void reduce_final_kernel(const double* __restrict__ part, int nb, int64_t nn,
-                                    ReduceOut* __restrict__ out, int mode, int drift) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Combine the partials in a fixed order (the same state always gives the
+// same bits): thread t sums partials t, t + 256, ... in order, then the
+// wavefront and workgroup reductions run in a fixed tree. mode 0: check
+// (update the sticky status and the drift shift); 1: set the reference
+// mass; 2: report only.
+__global__ __launch_bounds__(256) void reduce_final_kernel(const double* __restrict__ part, int nb,
+                                                           int64_t nn, ReduceOut* __restrict__ out,
+                                                           int mode, int drift) {
   double m = 0, jx = 0, jy = 0, mn = 1e300, mx = -1e300, bad = 0;
-  for (int b = 0; b < nb; ++b) {
+  for (int b = threadIdx.x; b < nb; b += 256) {
     const double* q = part + 6 * b;
     m += q[0]; jx += q[1]; jy += q[2];
     mn = fmin(mn, q[3]); mx = fmax(mx, q[4]); bad += q[5];
   }
+  __shared__ double red[6][4];
+  m = wave_sum(m); jx = wave_sum(jx); jy = wave_sum(jy); bad = wave_sum(bad);
+  mn = wave_min(mn); mx = wave_max(mx);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wv] = m; red[1][wv] = jx; red[2][wv] = jy; red[3][wv] = mn; red[4][wv] = mx; red[5][wv] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  m = ((red[0][0] + red[0][1]) + (red[0][2] + red[0][3]));
+  jx = ((red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
+  jy = ((red[2][0] + red[2][1]) + (red[2][2] + red[2][3]));
+  mn = fmin(fmin(red[3][0], red[3][1]), fmin(red[3][2], red[3][3]));
+  mx = fmax(fmax(red[4][0], red[4][1]), fmax(red[4][2], red[4][3]));
+  bad = ((red[5][0] + red[5][1]) + (red[5][2] + red[5][3]));
   out->mass = m; out->jx = jx; out->jy = jy; out->nmin = mn; out->nmax = mx; out->nonfinite = bad;
   const bool fail = bad > 0 || !(mn > 0.0) || !(mx < 3.0);
   if (mode == 1) {
@@ -696,7 +716,7 @@ __global__ void reduce_final_kernel(const double* __restrict__ part, int nb, int
 
 hipError_t launch_reduce_final(const double* d_part, int nb, int64_t nn, ReduceOut* d_out,
                                int mode, int drift, hipStream_t stream) {
-  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(64), 0, stream, d_part, nb, nn, d_out,
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, stream, d_part, nb, nn, d_out,
                      mode, drift);
   return hipGetLastError();
 }

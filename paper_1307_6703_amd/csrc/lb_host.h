@@ -95,9 +95,10 @@ inline Layout layout_for(const lb_params* p, size_t base = 0) {
 }
 
 inline int default_threads(const lb_params* p) {
-  const int cap = p->fp32 ? 256 : 128;
   if (p->Lx + 6 <= 64) return 64;
-  if (p->Lx + 6 <= 128 || cap == 128) return 128;
+  if (p->Lx + 6 <= 128 || !p->fp32) return 128;
+  if (p->Lx + 6 <= 256) return 256;
+  if (p->Lx + 6 <= 320) return 320;  // one strip per row (e.g. 256-wide lattices)
   return 256;
 }
 
@@ -111,7 +112,7 @@ inline int resident_slots(const lb_params* p, int threads) {
       cus = v;
   }
   const int waves_per_cu = (p->fp32 ? 4 : 2) * 4;
-  return cus * std::max(1, waves_per_cu / (threads / 64));
+  return cus * std::max(1, waves_per_cu / ((threads + 63) / 64));
 }
 
 // Rows per chunk: as few chunks as fill the resident workgroups once, and a

@@ -80,6 +80,10 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch ships its own HIP runtime with the same soname; loading torch
+    # first makes this library bind to it, so both share one runtime (one set
+    # of devices, streams and allocations).
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_1307_6703_amd/build.py "
                            "(hipcc, gfx950); there is no CPU fallback")

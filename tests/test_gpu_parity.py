@@ -98,6 +98,7 @@ RAGGED = [
     (251, 40, False, (256, 16)),
     (300, 21, True, (128, 10)),
     (513, 20, False, (256, 64)),
+    (700, 30, True, (320, 10)),
 ]
 
 
@@ -117,7 +118,10 @@ def test_launch_shape_does_not_change_results(torch_cuda, fp32):
     _say("launch shapes bitwise", fp32)
     Lx, Ly = 300, 70
     ref = None
-    for launch in ((64, 8), (128, 16), (256, 70), (256, 9), (128, 64)):
+    shapes = [(64, 8), (128, 16), (256, 70), (256, 9), (128, 64), (320, 18)]
+    if fp32:
+        shapes.append((512, 26))
+    for launch in shapes:
         g, _ = _pair(Lx, Ly, U=0.03, V0=0.1, k=3, fp32=fp32, launch=launch)
         g.step(40)
         f = g.populations()

@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--batched-steps", type=int, default=2000,
                     help="steps of the 96-lattice batched sweep reported beside the headline (0: skip)")
+    ap.add_argument("--surrogate-seconds", type=float, default=60.0,
+                    help="training time of the learned surrogate reported beside the headline "
+                         "(0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (for scaling HBM counters)")
     args = ap.parse_args()
@@ -233,6 +236,12 @@ def main():
     if args.batched_steps > 0:
         out["batched"] = batched_bench(args.batched_steps)
         print(f"[bench] batched: {out['batched']['MLUPS']} MLUPS", file=sys.stderr, flush=True)
+    if args.surrogate_seconds > 0:
+        from paper_1307_6703_amd import surrogate
+        out["surrogate"] = surrogate.experiment(
+            train_seconds=args.surrogate_seconds,
+            log=lambda m: print(f"[bench] surrogate {m}", file=sys.stderr, flush=True))
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, n0, fext, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -166,9 +166,37 @@ lb_status lb_batch_reduce(lb_batch* b, int32_t idx, double out[6]);
 lb_status lb_batch_status(lb_batch* b, int32_t* per_instance);
 lb_status lb_batch_destroy(lb_batch* b);
 
+/* ---- batch calls for a learned surrogate (all instances the same size) ----
+ * These let a caller replace the time stepping of some instances by a
+ * prediction of the fields and audit it against the lattice itself. They
+ * return LB_EINVAL when the instances differ in size. */
+
+/* The moments of every instance (as lb_get_moments: from the last step, the
+ * last init or the last re-entry) into a device FP64 block
+ * [count][3][Ly][Lx] (n, u*_x, u*_y). Asynchronous on the batch's stream. */
+lb_status lb_batch_get_moments_device(lb_batch* b, double* d_out);
+
+/* Re-entry: for each instance with mask[i] != 0 (host int32 array of count
+ * entries), replace the stored populations by the equilibrium of
+ * Eq.(eqfunc) at the fields of d_fields (device FP64 [count][3][Ly][Lx]:
+ * n, u*_x, u*_y) and make those fields the instance's moments. The step
+ * counter does not change; a pending drift shift of these instances is
+ * dropped. Synchronises the stream. */
+lb_status lb_batch_set_equilibrium_device(lb_batch* b, const double* d_fields,
+                                          const int32_t* mask);
+
+/* Advance only the instances with mask[i] != 0 by nsteps (even, so that
+ * their buffer parity stays that of the batch), with the batch's launch
+ * shape, no graph and no drift shift; the last step writes their moments;
+ * one FP64 check per instance at the end (flags instabilities as the
+ * periodic checks do). The batch step counter does not change. Launches
+ * are asynchronous; the tile upload synchronises the stream first. */
+lb_status lb_batch_step_subset(lb_batch* b, int64_t nsteps, const int32_t* mask);
+
 /* ---- launch shape ----------------------------------------------------------
  * The step kernel marches strips of columns along y. threads: columns a
- * workgroup loads (64, 128 or 256; it updates threads - 6 of them); rows:
+ * workgroup loads (64, 128, 256, 320, or 512 with FP32 populations; it
+ * updates threads - 6 of them); rows:
  * rows per y-chunk (>= 1). 0 keeps the default. Applies to the next step. */
 lb_status lb_set_launch(lb_handle* h, int32_t threads, int32_t rows);
 lb_status lb_get_launch(lb_handle* h, int32_t* threads, int32_t* rows, int32_t* blocks);

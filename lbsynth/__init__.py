@@ -150,3 +150,19 @@ def batch_draws(count: int = 96, seed: int = 1307) -> List[Workload]:
         out.append(Workload(f"batch-{i}", Lx, Ly, T=T, V0=V0, k=k, U=U, seed=s,
                             steps=20000, fp32=True))
     return out
+
+
+def surrogate_draws(count: int = 256, seed: int = 1307, Lx: int = 256, Ly: int = 128) -> List[Workload]:
+    """Instances for the learned surrogate: the batched sweep's parameter
+    ranges at one fixed size. Draw order per instance: T, V0, k, U, noise seed."""
+    g = rng(seed)
+    out = []
+    for i in range(count):
+        T = float(g.uniform(0.85, 0.98))
+        V0 = float(g.uniform(0.0, 0.2)) * V0_STABLE_SCALE
+        k = int(g.choice([2, 4, 8]))
+        U = float(g.uniform(0.0, 0.08))
+        s = int(g.integers(0, 2**31 - 1))
+        out.append(Workload(f"surrogate-{i}", Lx, Ly, T=T, V0=V0, k=k, U=U, seed=s,
+                            steps=0, fp32=True))
+    return out

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbvdw.so")
-SOURCES = ["lb_device.hip", "lb_api.hip", "lb_batch.hip"]
+SOURCES = ["lb_device.hip", "lb_api.hip", "lb_batch.hip", "sg_device.hip", "sg_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",

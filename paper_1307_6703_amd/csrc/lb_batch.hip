@@ -25,7 +25,7 @@ struct Inst {
 
 // Shared part of the batch workspace.
 struct BatchLayout {
-  size_t descs, reds, tiles, part, inst0, total;
+  size_t descs, reds, tiles, sub_tiles, part, inst0, total;
   int max_tiles;
 };
 
@@ -42,6 +42,7 @@ BatchLayout batch_layout(int count, const lb_params* p, std::vector<Inst>* insts
   B.descs = o; o = align_up(o + sizeof(Desc) * count);
   B.reds = o; o = align_up(o + sizeof(ReduceOut) * count);
   B.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)max_tiles);
+  B.sub_tiles = o; o = align_up(o + sizeof(Tile) * (size_t)max_tiles);
   B.part = o; o = align_up(o + sizeof(double) * 6 * (size_t)max_red);
   B.inst0 = o;
   for (int i = 0; i < count; ++i) {
@@ -73,6 +74,7 @@ struct lb_batch {
   Desc* ddesc = nullptr;
   ReduceOut* dred = nullptr;
   Tile* dtiles = nullptr;
+  Tile* dsub = nullptr;  // tile table of the last subset step
   double* dpart = nullptr;
   int threads = 256, rows = 64, ntiles = 0;
   int parity = 0;
@@ -100,15 +102,13 @@ void drop_graphs(lb_batch* b) {
     }
 }
 
-lb_status batch_tiles(lb_batch* b, int threads, int rows) {
-  if (threads != 64 && threads != 128 && threads != 256 && threads != 320 &&
-      !(threads == 512 && b->fp32))
-    return fail(LB_EINVAL, "threads must be 64, 128, 256, 320 or 512 (FP32 only) (got %d)", threads);
-  if (rows < 1) return fail(LB_EINVAL, "rows must be >= 1");
-  // largest instances first: the dispatcher hands out tiles in order, so the
-  // long-running ones start early
-  std::vector<int> order(b->count);
-  std::iota(order.begin(), order.end(), 0);
+// Tiles of the instances with mask[i] != 0 (all when mask is NULL), largest
+// instances first: the dispatcher hands out tiles in order, so the
+// long-running ones start early.
+std::vector<Tile> tile_list(const lb_batch* b, int threads, int rows, const int32_t* mask) {
+  std::vector<int> order;
+  for (int i = 0; i < b->count; ++i)
+    if (!mask || mask[i]) order.push_back(i);
   std::stable_sort(order.begin(), order.end(),
                    [&](int x, int y) { return inst_nodes(b, x) > inst_nodes(b, y); });
   std::vector<Tile> all;
@@ -117,6 +117,15 @@ lb_status batch_tiles(lb_batch* b, int threads, int rows) {
     std::vector<Tile> t = make_tiles(i, b->inst[i].p.Lx, b->inst[i].p.Ly, threads, r);
     all.insert(all.end(), t.begin(), t.end());
   }
+  return all;
+}
+
+lb_status batch_tiles(lb_batch* b, int threads, int rows) {
+  if (threads != 64 && threads != 128 && threads != 256 && threads != 320 &&
+      !(threads == 512 && b->fp32))
+    return fail(LB_EINVAL, "threads must be 64, 128, 256, 320 or 512 (FP32 only) (got %d)", threads);
+  if (rows < 1) return fail(LB_EINVAL, "rows must be >= 1");
+  std::vector<Tile> all = tile_list(b, threads, rows, nullptr);
   if ((int)all.size() > b->B.max_tiles) return fail(LB_EINVAL, "too many tiles for the workspace");
   HIPCHK(hipMemcpyAsync(b->dtiles, all.data(), all.size() * sizeof(Tile), hipMemcpyHostToDevice, b->st));
   HIPCHK(hipStreamSynchronize(b->st));
@@ -127,9 +136,10 @@ lb_status batch_tiles(lb_batch* b, int threads, int rows) {
   return LB_OK;
 }
 
-lb_status enqueue_checks(lb_batch* b, int mode, int only = -1) {
+lb_status enqueue_checks(lb_batch* b, int mode, int only = -1, const int32_t* mask = nullptr) {
   for (int i = 0; i < b->count; ++i) {
     if (only >= 0 && i != only) continue;
+    if (mask && !mask[i]) continue;
     if (!b->inst[i].has_state) continue;
     const int64_t nn = inst_nodes(b, i);
     HIPCHK(lbk::launch_reduce(b->fp32, b->ddesc + i, b->parity, nn, b->dpart,
@@ -259,6 +269,7 @@ lb_status lb_batch_create(int32_t count, const lb_params* p, void* dev_ws, size_
   b->ddesc = (Desc*)(b->ws + b->B.descs);
   b->dred = (ReduceOut*)(b->ws + b->B.reds);
   b->dtiles = (Tile*)(b->ws + b->B.tiles);
+  b->dsub = (Tile*)(b->ws + b->B.sub_tiles);
   b->dpart = (double*)(b->ws + b->B.part);
   b->hdesc.resize(count);
   b->unstable.assign(count, 0);
@@ -457,6 +468,77 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t nsteps, int32_t* threads, int32
   if (threads) *threads = bt;
   if (rows) *rows = br;
   if (ms_per_step) *ms_per_step = best;
+  return LB_OK;
+}
+
+static lb_status same_size(const lb_batch* b) {
+  for (int i = 1; i < b->count; ++i)
+    if (b->inst[i].p.Lx != b->inst[0].p.Lx || b->inst[i].p.Ly != b->inst[0].p.Ly)
+      return fail(LB_EINVAL, "all instances must have the same size for this call");
+  return LB_OK;
+}
+
+lb_status lb_batch_get_moments_device(lb_batch* b, double* dev_out) {
+  if (!b || !dev_out) return fail(LB_EINVAL, "NULL argument");
+  lb_status r = same_size(b);
+  if (r != LB_OK) return r;
+  for (int i = 0; i < b->count; ++i)
+    if (!b->inst[i].moments_valid) return fail(LB_ESTATE, "instance %d has no moments", i);
+  HIPCHK(lbk::launch_gather_moments(b->ddesc, b->count, inst_nodes(b, 0), dev_out, b->st));
+  return LB_OK;
+}
+
+lb_status lb_batch_set_equilibrium_device(lb_batch* b, const double* dev_fields,
+                                          const int32_t* mask) {
+  if (!b || !dev_fields || !mask) return fail(LB_EINVAL, "NULL argument");
+  lb_status r = same_size(b);
+  if (r != LB_OK) return r;
+  std::vector<int32_t> m(mask, mask + b->count);
+  bool any = false;
+  for (int i = 0; i < b->count; ++i) {
+    m[i] = m[i] ? 1 : 0;
+    if (m[i] && !b->inst[i].has_state) return fail(LB_ESTATE, "instance %d has no state", i);
+    any = any || m[i];
+  }
+  if (!any) return LB_OK;
+  // the mask travels in the sub-tile table's region (no step is in flight
+  // that reads it: stream order)
+  int32_t* dmask = (int32_t*)b->dsub;
+  if ((size_t)b->count * sizeof(int32_t) > (size_t)b->B.max_tiles * sizeof(Tile))
+    return fail(LB_EINVAL, "batch too large for the mask buffer");
+  HIPCHK(hipMemcpyAsync(dmask, m.data(), sizeof(int32_t) * b->count, hipMemcpyHostToDevice, b->st));
+  HIPCHK(lbk::launch_scatter_eq(b->fp32, b->ddesc, b->dred, b->count, b->parity, inst_nodes(b, 0),
+                                dev_fields, dmask, b->st));
+  HIPCHK(hipStreamSynchronize(b->st));  // m is a host temporary
+  for (int i = 0; i < b->count; ++i)
+    if (m[i]) b->inst[i].moments_valid = true;
+  return LB_OK;
+}
+
+lb_status lb_batch_step_subset(lb_batch* b, int64_t nsteps, const int32_t* mask) {
+  if (!b || !mask) return fail(LB_EINVAL, "NULL argument");
+  if (nsteps < 0 || nsteps % 2) return fail(LB_EINVAL, "nsteps must be even and >= 0 (got %lld)",
+                                            (long long)nsteps);
+  if (b->unstable_any) return fail(LB_ESTATE, "an instance was flagged unstable");
+  bool any = false;
+  for (int i = 0; i < b->count; ++i)
+    if (mask[i]) {
+      if (!b->inst[i].has_state) return fail(LB_ESTATE, "instance %d has no state", i);
+      any = true;
+    }
+  if (!any || nsteps == 0) return LB_OK;
+  std::vector<Tile> t = tile_list(b, b->threads, b->rows, mask);
+  HIPCHK(hipMemcpyAsync(b->dsub, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipStreamSynchronize(b->st));  // t is a host temporary
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const int flags = (s == nsteps - 1) ? lbk::kWriteMoments : 0;
+    HIPCHK(lbk::launch_step(b->fp32, b->threads, b->ddesc, b->dsub, (int)t.size(), b->parity ^ (int)(s & 1),
+                            flags, b->st));
+  }
+  lb_status r = enqueue_checks(b, 0, -1, mask);
+  if (r != LB_OK) return r;
+  for (int i = 0; i < b->count; ++i)
+    if (mask[i]) b->inst[i].moments_valid = true;
   return LB_OK;
 }
 

@@ -767,4 +767,64 @@ hipError_t launch_set_pops(bool fp32, const Desc* d_desc, int parity, int p0, in
   return hipGetLastError();
 }
 
+// ---- batch helpers for the learned surrogate --------------------------------
+// Gather the moments of every instance (all the same size) into one block
+// [count][3][Ly][Lx]; scatter fields back as equilibrium populations (the
+// re-entry of Eq.(eqfunc) at u = u*) for the instances with mask != 0.
+__global__ void gather_moments_kernel(const Desc* __restrict__ descs, int64_t nn,
+                                      double* __restrict__ out) {
+  const int i = blockIdx.y;
+  const double* mom = descs[i].mom;
+  double* o = out + (int64_t)i * 3 * nn;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < 3 * nn;
+       k += (int64_t)gridDim.x * blockDim.x)
+    o[k] = mom[k];
+}
+
+template <typename R>
+__global__ void scatter_eq_kernel(const Desc* __restrict__ descs, ReduceOut* __restrict__ red,
+                                  int parity, int64_t nn, const double* __restrict__ fields,
+                                  const int32_t* __restrict__ mask) {
+  const int i = blockIdx.y;
+  if (!mask[i]) return;  // uniform per block
+  const Desc& d = descs[i];
+  // a drift shift measured on the replaced state does not apply to the new one
+  if (blockIdx.x == 0 && threadIdx.x == 0) red[i].shift = 0.0;
+  R* S = (R*)d.S[parity];
+  const double* f = fields + (int64_t)i * 3 * nn;
+  const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nn;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const double n = f[k], ux = f[nn + k], uy = f[2 * nn + k];
+    const double usq = 1.5 * (ux * ux + uy * uy);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const double cu = cx(q) * ux + cy(q) * uy;
+      S[q * nn + k] = (R)(rest_weight_hd(q, d.T) * (n - d.nbar) + w[q] * n * (3.0 * cu + 4.5 * cu * cu - usq));
+    }
+    d.mom[k] = n;
+    d.mom[nn + k] = ux;
+    d.mom[2 * nn + k] = uy;
+  }
+}
+
+hipError_t launch_gather_moments(const Desc* d_descs, int count, int64_t nn, double* out,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(gather_moments_kernel, dim3(grid_for(3 * nn, 256), count), dim3(256), 0, st,
+                     d_descs, nn, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_eq(bool fp32, const Desc* d_descs, ReduceOut* d_red, int count,
+                             int parity, int64_t nn, const double* fields, const int32_t* d_mask,
+                             hipStream_t st) {
+  if (fp32)
+    hipLaunchKernelGGL(scatter_eq_kernel<float>, dim3(grid_for(nn, 256), count), dim3(256), 0, st,
+                       d_descs, d_red, parity, nn, fields, d_mask);
+  else
+    hipLaunchKernelGGL(scatter_eq_kernel<double>, dim3(grid_for(nn, 256), count), dim3(256), 0, st,
+                       d_descs, d_red, parity, nn, fields, d_mask);
+  return hipGetLastError();
+}
+
 }  // namespace lbk

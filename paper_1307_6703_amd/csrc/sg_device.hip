@@ -125,6 +125,7 @@ __global__ __launch_bounds__(NTH) void conv_kernel(ConvArgs a) {
 #pragma unroll
           for (int ns = 0; ns < NS; ++ns) {
             const int co = ns * 16 + lm;
+            if (MODE == FWD_OUT && co >= a.nout) continue;  // padded channels: no bias entry
             const float v = acc[ms][ns][r] + (a.bias ? a.bias[co] : 0.f);
             if (MODE == FWD_FIRST) {
               a.y[p * CO + co] = f2bf(silu(v));
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(NTH) void conv_kernel(ConvArgs a) {
               a.y[p * CO + co] = f2bf(bf2f(a.res[p * CO + co]) + silu(v));
               if (a.z) a.z[p * CO + co] = f2bf(v);
             } else if (MODE == FWD_OUT) {
-              if (co < a.nout) a.yf[p * a.nout + co] = v;
+              a.yf[p * a.nout + co] = v;
             } else {  // BWD: v = dL/dh of this layer's input (+ the residual path)
               const float g = v + (a.res ? bf2f(a.res[p * CO + co]) : 0.f);
               if (a.z) a.z[p * CO + co] = f2bf(g);
@@ -269,49 +270,54 @@ hipError_t launch_wgrad(int ci, int co, const WgradArgs& a, int grid, hipStream_
   return hipErrorInvalidValue;
 }
 
-// Fixed-order sum of the workgroup partials: dw[i] = scale * sum_b part[b][i].
-__global__ void wgrad_reduce_kernel(const float* __restrict__ part, int nblk, int n, float scale,
-                                    float* __restrict__ dw) {
+// Fixed-order sum of the workgroup partials onto the real channels:
+// dw[(tap*cir + ci)*cor + co] = scale * sum_b part[b][(tap*CI + ci)*CO + co].
+__global__ void wgrad_reduce_kernel(const float* __restrict__ part, int nblk, int CI, int CO,
+                                    int cir, int cor, float scale, float* __restrict__ dw) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= 9 * cir * cor) return;
+  const int co = i % cor, ci = (i / cor) % cir, tap = i / (cor * cir);
+  const int64_t j = (int64_t)(tap * CI + ci) * CO + co, n = 9 * CI * CO;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * n + i];
+  for (int b = 0; b < nblk; ++b) s += part[b * n + j];
   dw[i] = (float)(s * scale);
 }
 
-hipError_t launch_wgrad_reduce(const float* part, int nblk, int n, float scale, float* dw,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, st, part, nblk, n,
-                     scale, dw);
+hipError_t launch_wgrad_reduce(const float* part, int nblk, int CI, int CO, int cir, int cor,
+                               float scale, float* dw, hipStream_t st) {
+  const int n = 9 * cir * cor;
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, st, part, nblk, CI,
+                     CO, cir, cor, scale, dw);
   return hipGetLastError();
 }
 
-// Bias gradient: db[co] = scale * sum_p gz[p][co], fixed order (one thread per
-// channel, a block per channel group, partials per block then a final pass).
-__global__ void bias_grad_kernel(const bf16* __restrict__ gz, int64_t npix, int C, int ncount,
-                                 float scale, float* __restrict__ part, float* __restrict__ db,
-                                 int stage) {
-  if (stage == 0) {
-    // part[blk][c] over pixels blk, blk + nblk, ...
-    const int c = threadIdx.x;
-    if (c >= C) return;
-    double s = 0.0;
-    for (int64_t p = blockIdx.x; p < npix; p += gridDim.x) s += (double)(float)gz[p * C + c];
-    part[blockIdx.x * C + c] = (float)s;
-  } else {
-    const int c = threadIdx.x;
-    if (c >= C) return;
-    double s = 0.0;
-    for (int b = 0; b < ncount; ++b) s += part[b * C + c];
-    if (c < ncount * 0 + C) db[c] = (float)(s * scale);
-  }
+// Bias gradient: db[c] = scale * sum_p gz[p][c] in a fixed order: block b
+// sums pixels b, b + nb, ... per channel, then one pass adds the block sums.
+constexpr int kBiasBlocks = 1024;
+
+__global__ void bias_partial_kernel(const bf16* __restrict__ gz, int64_t npix, int C,
+                                    float* __restrict__ part) {
+  const int c = threadIdx.x;
+  if (c >= C) return;
+  double s = 0.0;
+  for (int64_t p = blockIdx.x; p < npix; p += gridDim.x) s += (double)bf2f(gz[p * C + c]);
+  part[blockIdx.x * C + c] = (float)s;
+}
+
+__global__ void bias_final_kernel(const float* __restrict__ part, int nb, int C, int nreal,
+                                  float scale, float* __restrict__ db) {
+  const int c = threadIdx.x;
+  if (c >= nreal) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[b * C + c];
+  db[c] = (float)(s * scale);
 }
 
 hipError_t launch_bias_grad(const bf16* gz, int64_t npix, int C, int nreal, float scale,
                             float* part, float* db, hipStream_t st) {
-  const int nb = 1024;
-  hipLaunchKernelGGL(bias_grad_kernel, dim3(nb), dim3(64), 0, st, gz, npix, C, nb, scale, part, db, 0);
-  hipLaunchKernelGGL(bias_grad_kernel, dim3(1), dim3(64), 0, st, gz, npix, nreal, nb, scale, part, db, 1);
+  hipLaunchKernelGGL(bias_partial_kernel, dim3(kBiasBlocks), dim3(64), 0, st, gz, npix, C, part);
+  hipLaunchKernelGGL(bias_final_kernel, dim3(1), dim3(64), 0, st, part, kBiasBlocks, C, nreal,
+                     scale, db);
   return hipGetLastError();
 }
 
@@ -425,72 +431,169 @@ hipError_t launch_pack(const float* w, int cir, int cor, int CI, int CO, int tra
 }
 
 // ---------------------------------------------------------------------------
-// Fields <-> network tensors.
+// Fields <-> network tensors, batched over instances of one size (nn = H*W
+// nodes). Moments are FP64 blocks [B][3][H][W] (n, u_x, u_y).
 // Input channels (8, bf16): (n - 1) s_n, u_x s_u, u_y s_u, V(x) s_v, wall speed
-// s_u on the wall rows (0 elsewhere), (T - 0.9) s_t, 0, 0. Target / output
-// channels (3, FP32): change over K steps, (dn s_n, du_x s_u, du_y s_u).
+// s_u on the wall rows (-U on row 0, +U on row H-1, 0 elsewhere), (T - 0.9) s_t,
+// 0, 0. Target / output channels (3, FP32): change over the chunk,
+// (dn s_n, du_x s_u, du_y s_u).
 // ---------------------------------------------------------------------------
-__global__ void fields_to_input_kernel(const double* __restrict__ mom, int64_t nn, int H, int W,
-                                       const float* __restrict__ vx, float uwall, float temp,
+__global__ void fields_to_input_kernel(const double* __restrict__ mom, int B, int H, int W,
+                                       const float* __restrict__ vx, const float* __restrict__ cond,
                                        int walls, Scales s, bf16* __restrict__ x) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nn;
-       k += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t nn = (int64_t)H * W;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < (int64_t)B * nn;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(g / nn);
+    const int64_t k = g - (int64_t)b * nn;
     const int h = (int)(k / W), xx = (int)(k % W);
+    const double* m = mom + (int64_t)b * 3 * nn;
+    const float uwall = cond[2 * b], temp = cond[2 * b + 1];
     float c[8];
-    c[0] = (float)((mom[k] - 1.0) * s.n);
-    c[1] = (float)(mom[nn + k] * s.u);
-    c[2] = (float)(mom[2 * nn + k] * s.u);
-    c[3] = vx[xx] * s.v;
+    c[0] = (float)((m[k] - 1.0) * s.n);
+    c[1] = (float)(m[nn + k] * s.u);
+    c[2] = (float)(m[2 * nn + k] * s.u);
+    c[3] = vx[(int64_t)b * W + xx] * s.v;
     c[4] = walls ? (h == 0 ? -uwall * s.u : (h == H - 1 ? uwall * s.u : 0.f)) : 0.f;
     c[5] = (temp - 0.9f) * s.t;
     c[6] = 0.f;
     c[7] = 0.f;
+    bf16x8 v;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) x[k * 8 + j] = f2bf(c[j]);
+    for (int j = 0; j < 8; ++j) v[j] = f2bf(c[j]);
+    *(bf16x8*)(x + g * 8) = v;
   }
 }
 
-hipError_t launch_fields_to_input(const double* mom, int64_t nn, int H, int W, const float* vx,
-                                  float uwall, float temp, int walls, Scales s, bf16* x,
-                                  hipStream_t st) {
-  hipLaunchKernelGGL(fields_to_input_kernel, dim3((int)((nn + 255) / 256)), dim3(256), 0, st, mom,
-                     nn, H, W, vx, uwall, temp, walls, s, x);
+static int grid_1d(int64_t n) {
+  const int64_t g = (n + 255) / 256;
+  return (int)(g < 65536 ? (g < 1 ? 1 : g) : 65536);
+}
+
+hipError_t launch_fields_to_input(const double* mom, int B, int H, int W, const float* vx,
+                                  const float* cond, int walls, Scales s, bf16* x, hipStream_t st) {
+  hipLaunchKernelGGL(fields_to_input_kernel, dim3(grid_1d((int64_t)B * H * W)), dim3(256), 0, st,
+                     mom, B, H, W, vx, cond, walls, s, x);
   return hipGetLastError();
 }
 
-// target[p][c] = (fields(t+K) - fields(t)) scaled, from two FP64 moment blocks
+// target[b][k][c] = (fields1 - fields0) scaled
 __global__ void make_target_kernel(const double* __restrict__ m0, const double* __restrict__ m1,
-                                   int64_t nn, Scales s, float* __restrict__ target) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nn;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    target[k * 3 + 0] = (float)((m1[k] - m0[k]) * s.n);
-    target[k * 3 + 1] = (float)((m1[nn + k] - m0[nn + k]) * s.u);
-    target[k * 3 + 2] = (float)((m1[2 * nn + k] - m0[2 * nn + k]) * s.u);
+                                   int B, int64_t nn, Scales s, float* __restrict__ target) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < (int64_t)B * nn;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = g / nn, k = g - b * nn, o = b * 3 * nn + k;
+    target[g * 3 + 0] = (float)((m1[o] - m0[o]) * s.n);
+    target[g * 3 + 1] = (float)((m1[o + nn] - m0[o + nn]) * s.u);
+    target[g * 3 + 2] = (float)((m1[o + 2 * nn] - m0[o + 2 * nn]) * s.u);
   }
 }
 
-hipError_t launch_make_target(const double* m0, const double* m1, int64_t nn, Scales s,
+hipError_t launch_make_target(const double* m0, const double* m1, int B, int64_t nn, Scales s,
                               float* target, hipStream_t st) {
-  hipLaunchKernelGGL(make_target_kernel, dim3((int)((nn + 255) / 256)), dim3(256), 0, st, m0, m1,
-                     nn, s, target);
+  hipLaunchKernelGGL(make_target_kernel, dim3(grid_1d(B * nn)), dim3(256), 0, st, m0, m1, B, nn, s,
+                     target);
   return hipGetLastError();
 }
 
-// predicted fields (FP64) = fields(t) + output / scales
+// predicted fields (FP64) = fields0 + output / scales
 __global__ void apply_output_kernel(const double* __restrict__ m0, const float* __restrict__ out,
-                                    int64_t nn, Scales s, double* __restrict__ m1) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nn;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    m1[k] = m0[k] + (double)out[k * 3 + 0] / s.n;
-    m1[nn + k] = m0[nn + k] + (double)out[k * 3 + 1] / s.u;
-    m1[2 * nn + k] = m0[2 * nn + k] + (double)out[k * 3 + 2] / s.u;
+                                    int B, int64_t nn, Scales s, double* __restrict__ m1) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < (int64_t)B * nn;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = g / nn, k = g - b * nn, o = b * 3 * nn + k;
+    m1[o] = m0[o] + (double)out[g * 3 + 0] / s.n;
+    m1[o + nn] = m0[o + nn] + (double)out[g * 3 + 1] / s.u;
+    m1[o + 2 * nn] = m0[o + 2 * nn] + (double)out[g * 3 + 2] / s.u;
   }
 }
 
-hipError_t launch_apply_output(const double* m0, const float* out, int64_t nn, Scales s,
+hipError_t launch_apply_output(const double* m0, const float* out, int B, int64_t nn, Scales s,
                                double* m1, hipStream_t st) {
-  hipLaunchKernelGGL(apply_output_kernel, dim3((int)((nn + 255) / 256)), dim3(256), 0, st, m0,
-                     out, nn, s, m1);
+  hipLaunchKernelGGL(apply_output_kernel, dim3(grid_1d(B * nn)), dim3(256), 0, st, m0, out, B, nn,
+                     s, m1);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Per-instance comparisons of two field blocks [B][3][nn], one workgroup per
+// instance, fixed reduction order (deterministic): out[b][0..5] = (sum n_a,
+// sum n_b, max |n_a - n_b| / n_b, count of nodes where n_a is not finite or
+// outside (0, 3), sum (n_a - n_b)^2, sum n_b^2).
+// ---------------------------------------------------------------------------
+constexpr int kCmpBS = 256;
+
+__global__ __launch_bounds__(kCmpBS) void compare_kernel(const double* __restrict__ a,
+                                                         const double* __restrict__ bref,
+                                                         int64_t nn, double* __restrict__ out) {
+  const int b = blockIdx.x;
+  const double* na = a + (int64_t)b * 3 * nn;
+  const double* nb = bref + (int64_t)b * 3 * nn;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t k = threadIdx.x; k < nn; k += kCmpBS) {
+    const double x = na[k], y = nb[k];
+    v[0] += x;
+    v[1] += y;
+    const double e = fabs(x - y) / y;
+    v[2] = (e > v[2] || e != e) ? e : v[2];  // NaN propagates
+    v[3] += (x > 0.0 && x < 3.0) ? 0.0 : 1.0;
+    v[4] += (x - y) * (x - y);
+    v[5] += y * y;
+  }
+  __shared__ double red[6][kCmpBS];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) red[j][threadIdx.x] = v[j];
+  __syncthreads();
+  for (int o = kCmpBS / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        const double u = red[j][threadIdx.x + o];
+        if (j == 2) {
+          if (u > red[2][threadIdx.x] || u != u) red[2][threadIdx.x] = u;
+        } else {
+          red[j][threadIdx.x] += u;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) out[6 * b + threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_compare(const double* a, const double* b, int B, int64_t nn, double* out,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(compare_kernel, dim3(B), dim3(kCmpBS), 0, st, a, b, nn, out);
+  return hipGetLastError();
+}
+
+// Mass projection: n_a += (sum n_ref - sum n_a) / nn for the instances with
+// mask[b] != 0, so that the total density of a equals that of ref (FP64,
+// fixed reduction order).
+__global__ __launch_bounds__(kCmpBS) void project_mass_kernel(double* __restrict__ a,
+                                                              const double* __restrict__ ref,
+                                                              int64_t nn,
+                                                              const int32_t* __restrict__ mask) {
+  const int b = blockIdx.x;
+  if (!mask[b]) return;
+  double* na = a + (int64_t)b * 3 * nn;
+  const double* nr = ref + (int64_t)b * 3 * nn;
+  double d = 0;
+  for (int64_t k = threadIdx.x; k < nn; k += kCmpBS) d += nr[k] - na[k];
+  __shared__ double red[kCmpBS];
+  red[threadIdx.x] = d;
+  __syncthreads();
+  for (int o = kCmpBS / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double shift = red[0] / (double)nn;
+  for (int64_t k = threadIdx.x; k < nn; k += kCmpBS) na[k] += shift;
+}
+
+hipError_t launch_project_mass(double* a, const double* ref, int B, int64_t nn, const int32_t* mask,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(project_mass_kernel, dim3(B), dim3(kCmpBS), 0, st, a, ref, nn, mask);
   return hipGetLastError();
 }
 

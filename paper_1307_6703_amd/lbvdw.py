@@ -70,6 +70,41 @@ SIGNATURES = {
     "lb_batch_set_launch": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "lb_autotune": (ctypes.c_int, [_VP, ctypes.c_int32, _I32P, _I32P, _DP]),
     "lb_batch_autotune": (ctypes.c_int, [_VP, ctypes.c_int32, _I32P, _I32P, _DP]),
+    "lb_batch_get_moments_device": (ctypes.c_int, [_VP, _VP]),
+    "lb_batch_set_equilibrium_device": (ctypes.c_int, [_VP, _VP, _I32P]),
+    "lb_batch_step_subset": (ctypes.c_int, [_VP, ctypes.c_int64, _I32P]),
+    # include/lbsurrogate.h
+    "lbs_param_count": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64)]),
+    "lbs_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbs_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                  _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    "lbs_set_params": (ctypes.c_int, [_VP, _VP]),
+    "lbs_get_params": (ctypes.c_int, [_VP, _VP]),
+    "lbs_get_grads": (ctypes.c_int, [_VP, _VP]),
+    "lbs_forward": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
+    "lbs_train_step": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, ctypes.c_float, _VP]),
+    "lbs_destroy": (ctypes.c_int, [_VP]),
+    "lbs_pack": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_int32, _VP, _VP]),
+    "lbs_conv": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP, _VP,
+                                _VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_int32, _VP]),
+    "lbs_wgrad": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
+                                 _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                 _VP, ctypes.c_int32, _VP, _VP]),
+    "lbs_bias_grad": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_float, _VP, _VP, _VP]),
+    "lbs_mse": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _VP, _VP,
+                               _VP, _VP]),
+    "lbs_adam": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, ctypes.c_float, ctypes.c_int32, _VP]),
+    "lbs_fields_to_input": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
+                                           _VP, ctypes.c_int32, _VP, _VP, _VP]),
+    "lbs_make_target": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int64, _VP, _VP, _VP]),
+    "lbs_apply_output": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int64, _VP, _VP, _VP]),
+    "lbs_compare": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int64, _VP, _VP]),
+    "lbs_project_mass": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int64, _VP, _VP]),
 }
 
 _lib = None
@@ -114,6 +149,14 @@ def _host(a, shape) -> Optional[np.ndarray]:
     if a.size != int(np.prod(shape)):
         raise ValueError(f"expected {shape} values, got {a.shape}")
     return a.reshape(shape)
+
+
+def _require(t, dtype, numel: int):
+    """A contiguous device tensor of the given dtype and size (the C ABI
+    takes its raw pointer)."""
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel or not t.is_cuda:
+        raise ValueError(f"expected a contiguous {dtype} device tensor of {numel} elements, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
 
 
 def make_params(Lx, Ly, T=0.95, tau=1.0, kappa=0.3, N=0.3, Q=2.0, U=0.0, fext=None,
@@ -296,6 +339,38 @@ class Batch:
 
     def set_launch(self, threads: int = 0, rows: int = 0):
         _check(_lib.lb_batch_set_launch(self._h, int(threads), int(rows)))
+
+    def _mask(self, mask):
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.int32).reshape(-1))
+        if m.size != self.count:
+            raise ValueError(f"mask needs {self.count} entries, got {m.size}")
+        return m, m.ctypes.data_as(_I32P)
+
+    def moments_device(self, out=None):
+        """Moments of every instance (same size) as a device FP64 tensor
+        [count, 3, Ly, Lx] (asynchronous on the batch's stream)."""
+        import torch
+        Ly, Lx = self.shapes[0]
+        if out is None:
+            out = torch.empty((self.count, 3, Ly, Lx), dtype=torch.float64, device=self.workspace.device)
+        _require(out, torch.float64, self.count * 3 * Ly * Lx)
+        _check(_lib.lb_batch_get_moments_device(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def set_equilibrium(self, fields, mask):
+        """Re-enter the instances with mask != 0 as equilibrium populations of
+        the device FP64 fields [count, 3, Ly, Lx]."""
+        import torch
+        Ly, Lx = self.shapes[0]
+        _require(fields, torch.float64, self.count * 3 * Ly * Lx)
+        m, mp = self._mask(mask)
+        _check(_lib.lb_batch_set_equilibrium_device(self._h, ctypes.c_void_p(fields.data_ptr()), mp))
+
+    def step_subset(self, nsteps: int, mask):
+        """Advance only the instances with mask != 0 by an even number of steps."""
+        m, mp = self._mask(mask)
+        _check(_lib.lb_batch_step_subset(self._h, int(nsteps), mp))
+        return self
 
     def autotune(self, nsteps: int = 5):
         t, r, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()

@@ -9,13 +9,15 @@ import pytest
 from paper_1307_6703_amd import lbvdw
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "lbvdw.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("lbvdw.h", "lbsurrogate.h")]
 
 
 def _declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(?:lb_status|const char\*)\s+(lb_\w+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(?:lb_status|const char\*)\s+(lbs?_\w+)\s*\(", src))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -30,7 +32,9 @@ def test_header_declares_the_documented_calls():
     names = _declared()
     for must in ("lb_create", "lb_init_lattice", "lb_step_n", "lb_get_moments", "lb_reduce",
                  "lb_batch_create", "lb_batch_init", "lb_batch_step_n", "lb_batch_get_moments",
-                 "lb_batch_status", "lb_destroy", "lb_batch_destroy", "lb_last_error"):
+                 "lb_batch_status", "lb_destroy", "lb_batch_destroy", "lb_last_error",
+                 "lb_batch_step_subset", "lb_batch_set_equilibrium_device", "lbs_create",
+                 "lbs_forward", "lbs_train_step", "lbs_conv", "lbs_wgrad"):
         assert must in names
 
 
@@ -112,3 +116,24 @@ def test_product_package_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in txt.lower(), f
+
+
+def test_surrogate_sizes_and_validation(lib):
+    n = ctypes.c_int64()
+    assert lib.lbs_param_count(ctypes.byref(n)) == 0
+    # 3x3 convolutions 6->48, 4 x 48->48, 48->3, with biases
+    assert n.value == (9 * 6 * 48 + 48) + 4 * (9 * 48 * 48 + 48) + (9 * 48 * 3 + 3)
+    b_inf, b_tr = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.lbs_workspace_bytes(4, 128, 256, 0, ctypes.byref(b_inf)) == 0
+    assert lib.lbs_workspace_bytes(4, 128, 256, 1, ctypes.byref(b_tr)) == 0
+    act = 4 * 128 * 256 * 48 * 2
+    assert b_inf.value >= 2 * act and b_tr.value >= 14 * act
+    assert lib.lbs_workspace_bytes(0, 128, 256, 0, ctypes.byref(b_inf)) == lbvdw.LB_EINVAL
+    # unsupported channel pair and bad mode are rejected before any launch
+    st = lib.lbs_conv(0, 8, 32, None, None, None, None, None, None, None, None, 0, 1, 4, 4, None)
+    assert st == lbvdw.LB_EINVAL and "channel pair" in lib.lb_last_error().decode()
+    st = lib.lbs_conv(7, 8, 48, None, None, None, None, None, None, None, None, 0, 1, 4, 4, None)
+    assert st == lbvdw.LB_EINVAL and "mode" in lib.lb_last_error().decode()
+    st = lib.lbs_wgrad(16, 48, 16, 48, None, None, 1, 4, 4, 1.0, None, 1, None, None)
+    assert st == lbvdw.LB_EINVAL
+    assert lib.lbs_create(1, 4, 4, 0, None, 0, None, None) == lbvdw.LB_EINVAL

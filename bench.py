@@ -117,7 +117,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--batched-steps", type=int, default=2000,
                     help="steps of the 96-lattice batched sweep reported beside the headline (0: skip)")
-    ap.add_argument("--surrogate-seconds", type=float, default=60.0,
+    ap.add_argument("--surrogate-seconds", type=float, default=30.0,
                     help="training time of the learned surrogate reported beside the headline "
                          "(0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -124,14 +124,18 @@ lb_status lbs_conv(int32_t mode, int32_t ci, int32_t co, const void* d_x, const 
                    void* d_z, float* d_yf, int32_t nout, int32_t B, int32_t H, int32_t W,
                    void* hip_stream);
 
-/* Weight gradient dw[tap][ci][co] (ci < cir, co < cor; FP32) = scale *
- * sum over pixels p of x[p + offset(tap)][ci] gz[p][co], x [B][H][W][ci],
- * gz [B][H][W][co] bf16, with the convolution's boundary rules. d_part:
- * blocks x 9 ci co FP32 of scratch (per-workgroup partial sums, added in a
- * fixed order, so results are deterministic); 1 <= blocks <= 4096. */
+/* Weight and bias gradients: dw[tap][ci][co] (ci < cir, co < cor; FP32) =
+ * scale * sum over pixels p of x[p + offset(tap)][ci] gz[p][co], with the
+ * convolution's boundary rules, and db[co] = scale * sum_p gz[p][co] (db may
+ * be NULL); x [B][H][W][ci], gz [B][H][W][co] bf16. d_part: scratch of
+ * lbs_wgrad_scratch_floats FP32 values (per-workgroup partial sums, added in
+ * a fixed order, so results are deterministic); 1 <= blocks <= 4096
+ * workgroups. */
+lb_status lbs_wgrad_scratch_floats(int32_t ci, int32_t co, int32_t cir, int32_t cor, int32_t blocks,
+                                   int64_t* count);
 lb_status lbs_wgrad(int32_t ci, int32_t co, int32_t cir, int32_t cor, const void* d_x,
                     const void* d_gz, int32_t B, int32_t H, int32_t W, float scale, float* d_part,
-                    int32_t blocks, float* d_dw, void* hip_stream);
+                    int32_t blocks, float* d_dw, float* d_db, void* hip_stream);
 
 /* Bias gradient db[c] = scale * sum_p gz[p][c] for c < nreal; gz [npix][C]
  * bf16, C <= 64; d_part: 1024 C FP32 of scratch. */

@@ -15,7 +15,6 @@ namespace {
 
 constexpr int kLayers = LBS_BLOCKS + 2;
 constexpr int kWgradBlocks = 512;
-constexpr int kBiasBlocks = 1024;  // matches the bias kernels
 constexpr int kMsePart = 512;      // matches the loss kernel
 constexpr int kConvGridMax = 2048;
 
@@ -56,10 +55,12 @@ int64_t pack_bwd_elems(int l) {
   return (int64_t)s.CI * kpad(s.CO);
 }
 
+int64_t wgrad_scratch_floats(int ci, int co, int cir, int cor, int blocks);
+
 struct NetLayout {
   size_t params, grads, adam_m, adam_v, wf[kLayers], wb[kLayers];
   size_t h[LBS_BLOCKS + 1], z[LBS_BLOCKS + 1], dz[2], dh[2], gout, out;
-  size_t wpart, bpart, mpart, loss, total;
+  size_t wpart, mpart, loss, total;
 };
 
 NetLayout net_layout(int64_t npix, bool train) {
@@ -85,8 +86,8 @@ NetLayout net_layout(int64_t npix, bool train) {
     for (int i = 0; i < 2; ++i) L.dh[i] = take(act);
     L.gout = take((size_t)npix * LBS_OUT_CHANNELS * 2);
     L.out = take((size_t)npix * LBS_OUT * 4);
-    L.wpart = take((size_t)kWgradBlocks * 9 * LBS_WIDTH * LBS_WIDTH * 4);
-    L.bpart = take((size_t)kBiasBlocks * 64 * 4);
+    L.wpart = take((size_t)wgrad_scratch_floats(LBS_WIDTH, LBS_WIDTH, LBS_WIDTH, LBS_WIDTH,
+                                                kWgradBlocks) * 4);
     L.mpart = take((size_t)kMsePart * 8);
     L.loss = take(8);
   } else {
@@ -140,8 +141,14 @@ lb_status conv(int mode, int ci, int co, const void* x, const void* wp, const fl
   return LB_OK;
 }
 
+// scratch of a weight gradient: per-workgroup partials, then the FP64
+// partials of the reduction's first stage (8-byte aligned)
+int64_t wgrad_scratch_floats(int ci, int co, int cir, int cor, int blocks) {
+  return (int64_t)blocks * (9 * ci * co + co) + 2 + 2 * 16 * (int64_t)(9 * cir * cor + cor);
+}
+
 lb_status wgrad(int ci, int co, int cir, int cor, const void* x, const void* gz, int B, int H,
-                int W, float scale, float* part, int blocks, float* dw, hipStream_t st) {
+                int W, float scale, float* part, int blocks, float* dw, float* db, hipStream_t st) {
   sg::WgradArgs a;
   a.x = (const sg::bf16*)x;
   a.gz = (const sg::bf16*)gz;
@@ -152,7 +159,9 @@ lb_status wgrad(int ci, int co, int cir, int cor, const void* x, const void* gz,
   const int64_t nseg = (int64_t)((W + 63) / 64) * H * B;
   const int grid = (int)std::min<int64_t>(blocks, nseg);
   HIPCHK(sg::launch_wgrad(ci, co, a, grid, st));
-  HIPCHK(sg::launch_wgrad_reduce(part, grid, ci, co, cir, cor, scale, dw, st));
+  uintptr_t t = (uintptr_t)(part + (int64_t)blocks * (9 * ci * co + co));
+  t = (t + 7) & ~(uintptr_t)7;
+  HIPCHK(sg::launch_wgrad_reduce(part, grid, ci, co, cir, cor, scale, (double*)t, dw, db, st));
   return LB_OK;
 }
 
@@ -330,7 +339,6 @@ lb_status lbs_train_step(lbs_net* n, int32_t B, const void* d_x, const float* d_
   const float scale = (float)(1.0 / ((double)npix * LBS_OUT));
   float* grads = n->at<float>(L.grads);
   float* wpart = n->at<float>(L.wpart);
-  float* bpart = n->at<float>(L.bpart);
   auto grad_w = [&](int l) { return grads + param_offset(l); };
   auto grad_b = [&](int l) {
     const LayerShape s = layer_shape(l);
@@ -339,10 +347,9 @@ lb_status lbs_train_step(lbs_net* n, int32_t B, const void* d_x, const float* d_
   // output layer
   const int lo = kLayers - 1;
   if ((r = wgrad(LBS_WIDTH, LBS_OUT_CHANNELS, LBS_WIDTH, LBS_OUT, n->at<void>(L.h[LBS_BLOCKS]),
-                 n->at<void>(L.gout), B, H, W, scale, wpart, kWgradBlocks, grad_w(lo), st)) != LB_OK)
+                 n->at<void>(L.gout), B, H, W, scale, wpart, kWgradBlocks, grad_w(lo), grad_b(lo),
+                 st)) != LB_OK)
     return r;
-  HIPCHK(sg::launch_bias_grad(n->at<sg::bf16>(L.gout), npix, LBS_OUT_CHANNELS, LBS_OUT, scale, bpart,
-                              grad_b(lo), st));
   // dL/dh_top = conv^T(gout); dL/dz_top = dL/dh_top SiLU'(z_top)
   int a = 0;
   if ((r = conv(sg::BWD, LBS_OUT_CHANNELS, LBS_WIDTH, n->at<void>(L.gout), n->at<void>(L.wb[lo]),
@@ -352,10 +359,9 @@ lb_status lbs_train_step(lbs_net* n, int32_t B, const void* d_x, const float* d_
   // residual blocks, top down: dz[a] = dL/dz_l, dh[a] = dL/dh_l
   for (int l = LBS_BLOCKS; l >= 1; --l) {
     if ((r = wgrad(LBS_WIDTH, LBS_WIDTH, LBS_WIDTH, LBS_WIDTH, n->at<void>(L.h[l - 1]),
-                   n->at<void>(L.dz[a]), B, H, W, scale, wpart, kWgradBlocks, grad_w(l), st)) != LB_OK)
+                   n->at<void>(L.dz[a]), B, H, W, scale, wpart, kWgradBlocks, grad_w(l), grad_b(l),
+                   st)) != LB_OK)
       return r;
-    HIPCHK(sg::launch_bias_grad(n->at<sg::bf16>(L.dz[a]), npix, LBS_WIDTH, LBS_WIDTH, scale, bpart,
-                                grad_b(l), st));
     // dL/dh_{l-1} = dL/dh_l + conv^T(dL/dz_l); dL/dz_{l-1} = that SiLU'(z_{l-1})
     if ((r = conv(sg::BWD, LBS_WIDTH, LBS_WIDTH, n->at<void>(L.dz[a]), n->at<void>(L.wb[l]), nullptr,
                   n->at<void>(L.dh[a]), n->at<void>(L.z[l - 1]), n->at<void>(L.dz[a ^ 1]),
@@ -365,10 +371,8 @@ lb_status lbs_train_step(lbs_net* n, int32_t B, const void* d_x, const float* d_
   }
   // first layer
   if ((r = wgrad(LBS_IN_CHANNELS, LBS_WIDTH, LBS_IN_REAL, LBS_WIDTH, d_x, n->at<void>(L.dz[a]), B, H,
-                 W, scale, wpart, kWgradBlocks, grad_w(0), st)) != LB_OK)
+                 W, scale, wpart, kWgradBlocks, grad_w(0), grad_b(0), st)) != LB_OK)
     return r;
-  HIPCHK(sg::launch_bias_grad(n->at<sg::bf16>(L.dz[a]), npix, LBS_WIDTH, LBS_WIDTH, scale, bpart,
-                              grad_b(0), st));
   n->adam_t += 1;
   HIPCHK(sg::launch_adam(n->at<float>(L.params), grads, n->at<float>(L.adam_m),
                          n->at<float>(L.adam_v), (int)param_count(), lr, 0.9f, 0.999f, 1e-8f,
@@ -418,9 +422,19 @@ lb_status lbs_conv(int32_t mode, int32_t ci, int32_t co, const void* d_x, const 
               (hipStream_t)hip_stream);
 }
 
+lb_status lbs_wgrad_scratch_floats(int32_t ci, int32_t co, int32_t cir, int32_t cor, int32_t blocks,
+                                   int64_t* count) {
+  if (!count) return fail(LB_EINVAL, "count is NULL");
+  if (!wgrad_supported(ci, co)) return fail(LB_EINVAL, "unsupported channel pair (%d, %d)", ci, co);
+  if (cir < 1 || cir > ci || cor < 1 || cor > co) return fail(LB_EINVAL, "need 1 <= cir <= ci, 1 <= cor <= co");
+  if (blocks < 1 || blocks > 4096) return fail(LB_EINVAL, "blocks must be in [1, 4096]");
+  *count = wgrad_scratch_floats(ci, co, cir, cor, blocks);
+  return LB_OK;
+}
+
 lb_status lbs_wgrad(int32_t ci, int32_t co, int32_t cir, int32_t cor, const void* d_x,
                     const void* d_gz, int32_t B, int32_t H, int32_t W, float scale, float* d_part,
-                    int32_t blocks, float* d_dw, void* hip_stream) {
+                    int32_t blocks, float* d_dw, float* d_db, void* hip_stream) {
   if (!wgrad_supported(ci, co)) return fail(LB_EINVAL, "unsupported channel pair (%d, %d)", ci, co);
   if (cir < 1 || cir > ci || cor < 1 || cor > co) return fail(LB_EINVAL, "need 1 <= cir <= ci, 1 <= cor <= co");
   lb_status r = check_image(B, H, W);
@@ -428,7 +442,8 @@ lb_status lbs_wgrad(int32_t ci, int32_t co, int32_t cir, int32_t cor, const void
   if (!d_x || !d_gz || !d_part || !d_dw) return fail(LB_EINVAL, "NULL argument");
   if (!aligned16(d_x) || !aligned16(d_gz)) return fail(LB_EINVAL, "x and gz must be 16-byte aligned");
   if (blocks < 1 || blocks > 4096) return fail(LB_EINVAL, "blocks must be in [1, 4096]");
-  return wgrad(ci, co, cir, cor, d_x, d_gz, B, H, W, scale, d_part, blocks, d_dw,
+  if ((uintptr_t)d_part % 4) return fail(LB_EINVAL, "d_part must be 4-byte aligned");
+  return wgrad(ci, co, cir, cor, d_x, d_gz, B, H, W, scale, d_part, blocks, d_dw, d_db,
                (hipStream_t)hip_stream);
 }
 

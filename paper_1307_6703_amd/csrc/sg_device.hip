@@ -191,6 +191,7 @@ __global__ __launch_bounds__(NTH) void wgrad_kernel(WgradArgs a) {
   for (int i = 0; i < MPW; ++i)
 #pragma unroll
     for (int ns = 0; ns < NS; ++ns) acc[i][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;  // bias gradient partial of channel tid (tid < CO)
 
   // rows of A^T past M stay zero
   for (int i = tid; i < (MS * 16 - M) * PS; i += NTH) sa[M * PS + i] = (bf16)0.f;
@@ -223,6 +224,12 @@ __global__ __launch_bounds__(NTH) void wgrad_kernel(WgradArgs a) {
       for (int j = 0; j < 8; ++j) sg[(c8 * 8 + j) * PS + p] = v[j];
     }
     __syncthreads();
+    if (tid < CO) {
+      float t = 0.f;
+#pragma unroll 8
+      for (int p = 0; p < SEG; ++p) t += bf2f(sg[tid * PS + p]);
+      bsum += t;
+    }
 #pragma unroll
     for (int kc = 0; kc < SEG / 32; ++kc) {
       const int k = kc * 32 + lg * 8;
@@ -241,8 +248,10 @@ __global__ __launch_bounds__(NTH) void wgrad_kernel(WgradArgs a) {
       }
     }
   }
-  // partial sums of this workgroup: part[block][m][co]
-  float* out = a.part + (int64_t)blockIdx.x * M * CO;
+  // partial sums of this workgroup: part[block][m][co], then the bias
+  // partials part[block][M CO + co]
+  float* out = a.part + (int64_t)blockIdx.x * (M * CO + CO);
+  if (tid < CO) out[M * CO + tid] = bsum;
 #pragma unroll
   for (int i = 0; i < MPW; ++i) {
     const int ms = wave + 4 * i;
@@ -270,24 +279,60 @@ hipError_t launch_wgrad(int ci, int co, const WgradArgs& a, int grid, hipStream_
   return hipErrorInvalidValue;
 }
 
-// Fixed-order sum of the workgroup partials onto the real channels:
-// dw[(tap*cir + ci)*cor + co] = scale * sum_b part[b][(tap*CI + ci)*CO + co].
-__global__ void wgrad_reduce_kernel(const float* __restrict__ part, int nblk, int CI, int CO,
-                                    int cir, int cor, float scale, float* __restrict__ dw) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 9 * cir * cor) return;
+// Fixed-order sum of the workgroup partials onto the real channels, in two
+// stages (stage 1: kRedGroups consecutive runs of blocks, stage 2: the runs).
+// Output element i < 9 cir cor: dw[(tap*cir + ci)*cor + co] from partial
+// entry (tap*CI + ci)*CO + co; i >= 9 cir cor: db[co] from entry 9 CI CO + co.
+constexpr int kRedGroups = 16;
+
+__device__ __forceinline__ int64_t wgrad_entry(int i, int CI, int CO, int cir, int cor) {
+  const int nw = 9 * cir * cor;
+  if (i >= nw) return (int64_t)9 * CI * CO + (i - nw);
   const int co = i % cor, ci = (i / cor) % cir, tap = i / (cor * cir);
-  const int64_t j = (int64_t)(tap * CI + ci) * CO + co, n = 9 * CI * CO;
+  return (int64_t)(tap * CI + ci) * CO + co;
+}
+
+__global__ void wgrad_reduce1_kernel(const float* __restrict__ part, int nblk, int CI, int CO,
+                                     int cir, int cor, double* __restrict__ tmp) {
+  const int n = 9 * cir * cor + cor;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int g = blockIdx.y;
+  const int per = (nblk + kRedGroups - 1) / kRedGroups;
+  const int b0 = g * per, b1 = min(nblk, b0 + per);
+  const int64_t stride = (int64_t)9 * CI * CO + CO, j = wgrad_entry(i, CI, CO, cir, cor);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int b = b0;
+  for (; b + 3 < b1; b += 4) {
+    s0 += part[b * stride + j];
+    s1 += part[(b + 1) * stride + j];
+    s2 += part[(b + 2) * stride + j];
+    s3 += part[(b + 3) * stride + j];
+  }
+  for (; b < b1; ++b) s0 += part[b * stride + j];
+  tmp[(int64_t)g * n + i] = (s0 + s1) + (s2 + s3);
+}
+
+__global__ void wgrad_reduce2_kernel(const double* __restrict__ tmp, int n, int nw, float scale,
+                                     float* __restrict__ dw, float* __restrict__ db) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[b * n + j];
-  dw[i] = (float)(s * scale);
+#pragma unroll
+  for (int g = 0; g < kRedGroups; ++g) s += tmp[(int64_t)g * n + i];
+  if (i < nw)
+    dw[i] = (float)(s * scale);
+  else if (db)
+    db[i - nw] = (float)(s * scale);
 }
 
 hipError_t launch_wgrad_reduce(const float* part, int nblk, int CI, int CO, int cir, int cor,
-                               float scale, float* dw, hipStream_t st) {
-  const int n = 9 * cir * cor;
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, st, part, nblk, CI,
-                     CO, cir, cor, scale, dw);
+                               float scale, double* tmp, float* dw, float* db, hipStream_t st) {
+  const int nw = 9 * cir * cor, n = nw + cor;
+  hipLaunchKernelGGL(wgrad_reduce1_kernel, dim3((n + 255) / 256, kRedGroups), dim3(256), 0, st, part,
+                     nblk, CI, CO, cir, cor, tmp);
+  hipLaunchKernelGGL(wgrad_reduce2_kernel, dim3((n + 255) / 256), dim3(256), 0, st, tmp, n, nw,
+                     scale, dw, db);
   return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ struct ConvArgs {
 struct WgradArgs {
   const bf16* x;       // layer input [B,H,W,CI]
   const bf16* gz;      // dL/dz [B,H,W,CO]
-  float* part;         // per-workgroup partial sums [grid][9 CI][CO]
+  float* part;         // per-workgroup partial sums [grid][9 CI CO + CO]
   int B, H, W;
 };
 
@@ -39,8 +39,10 @@ struct Scales {
 
 hipError_t launch_conv(int ci, int co, int mode, const ConvArgs& a, int grid, hipStream_t st);
 hipError_t launch_wgrad(int ci, int co, const WgradArgs& a, int grid, hipStream_t st);
+// Per-workgroup partial sums of the weight gradient: [grid][9 CI CO + CO]
+// (the last CO entries: bias partials). tmp: 16 (9 cir cor + cor) doubles.
 hipError_t launch_wgrad_reduce(const float* part, int nblk, int CI, int CO, int cir, int cor,
-                               float scale, float* dw, hipStream_t st);
+                               float scale, double* tmp, float* dw, float* db, hipStream_t st);
 hipError_t launch_bias_grad(const bf16* gz, int64_t npix, int C, int nreal, float scale,
                             float* part, float* db, hipStream_t st);
 hipError_t launch_mse(const float* pred, const float* target, int64_t npix, int nout, int CO,

@@ -92,7 +92,10 @@ SIGNATURES = {
                                 ctypes.c_int32, _VP]),
     "lbs_wgrad": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
                                  _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
-                                 _VP, ctypes.c_int32, _VP, _VP]),
+                                 _VP, ctypes.c_int32, _VP, _VP, _VP]),
+    "lbs_wgrad_scratch_floats": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_int64)]),
     "lbs_bias_grad": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_float, _VP, _VP, _VP]),
     "lbs_mse": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _VP, _VP,

@@ -210,13 +210,18 @@ def conv(mode, ci, co, x, wpack, bias=None, res=None, zprev=None, want_z=False, 
 
 
 def wgrad(ci, co, cir, cor, x, gz, scale=1.0, blocks=512):
+    """Weight and bias gradients (lbs_wgrad): (dw [9*cir*cor], db [cor])."""
     import torch
     B, H, W, _ = x.shape
-    part = torch.empty(blocks * 9 * ci * co, dtype=torch.float32, device=x.device)
+    lib = load_library()
+    n = ctypes.c_int64()
+    _check(lib.lbs_wgrad_scratch_floats(ci, co, cir, cor, int(blocks), ctypes.byref(n)))
+    part = torch.empty(n.value, dtype=torch.float32, device=x.device)
     dw = torch.empty(9 * cir * cor, dtype=torch.float32, device=x.device)
-    _check(load_library().lbs_wgrad(ci, co, cir, cor, _vp(x), _vp(gz), B, H, W, float(scale), _vp(part),
-                                int(blocks), _vp(dw), _stream()))
-    return dw
+    db = torch.empty(cor, dtype=torch.float32, device=x.device)
+    _check(lib.lbs_wgrad(ci, co, cir, cor, _vp(x), _vp(gz), B, H, W, float(scale), _vp(part),
+                         int(blocks), _vp(dw), _vp(db), _stream()))
+    return dw, db
 
 
 def bias_grad(gz, nreal, scale=1.0):
@@ -317,6 +322,18 @@ def conditions(draws, device="cuda"):
     return vx.contiguous(), cond.contiguous()
 
 
+def screen(draws, steps: int, keep: Optional[int] = None):
+    """The draws whose lattices pass every stability check over `steps`
+    steps (a stiff quench under strong shear can fail), in order, at most
+    `keep` of them."""
+    b = _batch_for(draws)
+    b.step(steps)
+    status = b.status()
+    b.close()
+    ok = [w for w, s in zip(draws, status) if s == 0]
+    return ok[:keep] if keep is not None else ok
+
+
 def generate_data(draws, warmup: int, chunks: int, K: int = 50, scales=None):
     """Run the lattices of `draws` (one size) for `warmup` steps, then record
     `chunks` chunks of K steps: inputs [chunks*B,H,W,8] bf16 and targets
@@ -346,22 +363,28 @@ def generate_data(draws, warmup: int, chunks: int, K: int = 50, scales=None):
 
 def train(net: Net, x, tgt, iters: int, batch: int = 16, lr: float = 1e-3, seed: int = 0,
           log_every: int = 100, time_limit: Optional[float] = None):
-    """Minibatch Adam with a cosine learning-rate decay. Minibatches are
-    contiguous runs of `batch` samples at random offsets. Returns
-    [(iteration, loss)] sampled every log_every iterations."""
+    """Minibatch Adam with a cosine learning-rate decay over the iterations
+    or, with a time limit, over the time. Minibatches are contiguous runs of
+    `batch` samples at random offsets. Returns [(iteration, loss)] sampled
+    every log_every iterations (the loss of that iteration's minibatch)."""
     import torch
     g = np.random.Generator(np.random.PCG64(seed))
     n = x.shape[0]
     hist = []
     t0 = time.perf_counter()
+    frac = 0.0
     for it in range(iters):
         s = int(g.integers(0, n - batch + 1))
-        cur = lr * 0.5 * (1.0 + np.cos(np.pi * it / iters))
+        cur = lr * 0.5 * (1.0 + np.cos(np.pi * frac))
         loss = net.train_step(x[s:s + batch], tgt[s:s + batch], max(cur, lr * 0.02))
+        frac = (it + 1) / iters
         if it % log_every == 0 or it == iters - 1:
             hist.append((it, float(loss.item())))
-            if time_limit is not None and time.perf_counter() - t0 > time_limit:
-                break
+            if time_limit is not None:
+                el = time.perf_counter() - t0
+                frac = max(frac, el / time_limit)
+                if el > time_limit:
+                    break
     torch.cuda.synchronize()
     return hist
 
@@ -386,20 +409,27 @@ class SurrogateRun:
     """Advance a batch of same-size lattices chunk by chunk with the network,
     audited by the lattice (see the module docstring).
 
-    tol: maximum relative density error of an audited prediction;
-    mass_tol: maximum relative change of the total density of a raw
-    prediction (a sanity gate: accepted predictions are projected onto the
-    exact FP64 mass afterwards, so the run's own mass drift stays at
-    rounding level); audit_every: every instance is audited at least once per
-    audit_every chunks; penalty: chunks an instance stays on the lattice after
-    a failed audit."""
+    An instance is trusted after `need` consecutive audits within `tol`
+    (relative density error against the lattice's own chunk: the maximum
+    over nodes of |dn| / n for norm "max", the root-mean-square ratio
+    ||dn||_2 / ||n||_2 for norm "rms"); until
+    then it runs on the lattice with its predictions audited every chunk.
+    A trusted instance is audited once every `audit_every` chunks (rotating)
+    and goes back on probation when an audit fails. mass_tol bounds the
+    relative change of the total density of a raw prediction (a sanity gate:
+    accepted predictions are projected onto the exact FP64 mass afterwards,
+    so the run's own mass drift stays at rounding level)."""
 
     def __init__(self, net: Net, batch: Batch, draws, K: int = 50, tol: float = 1e-2,
-                 mass_tol: float = 1e-2, audit_every: int = 8, penalty: int = 4, scales=None):
+                 mass_tol: float = 1e-2, audit_every: int = 8, need: int = 1, norm: str = "max",
+                 scales=None):
         import torch
+        if norm not in ("max", "rms"):
+            raise ValueError("norm must be 'max' or 'rms'")
+        self.norm = norm
         self.net, self.b, self.K = net, batch, int(K)
         self.tol, self.mass_tol = tol, mass_tol
-        self.audit_every, self.penalty = int(audit_every), int(penalty)
+        self.audit_every, self.need = int(audit_every), int(need)
         self.scales = scales
         self.B = batch.count
         H, W = batch.shapes[0]
@@ -411,7 +441,7 @@ class SurrogateRun:
         self.x = torch.empty((self.B, H, W, IN_CHANNELS), dtype=torch.bfloat16, device=dev)
         self.out = torch.empty((self.B, H, W, OUT), dtype=torch.float32, device=dev)
         self.cmp = torch.empty((self.B, 6), dtype=torch.float64, device=dev)
-        self.untrusted_until = np.zeros(self.B, dtype=np.int64)
+        self.passes = np.zeros(self.B, dtype=np.int64)
         self.stats = RunStats()
 
     def chunk(self):
@@ -426,24 +456,28 @@ class SurrogateRun:
         raw = compare(self.f1, self.f0, self.cmp).cpu().numpy()
         mass_drift = np.abs(raw[:, 0] - raw[:, 1]) / raw[:, 1]
         bad = (raw[:, 3] > 0) | ~(mass_drift <= self.mass_tol)
-        trusted = self.untrusted_until <= c
-        audit = trusted & ((np.arange(B) % self.audit_every) == (c % self.audit_every))
-        lattice = ~trusted | bad | audit
+        trusted = self.passes >= self.need
+        audit = ~bad & (~trusted | ((np.arange(B) % self.audit_every) == (c % self.audit_every)))
+        lattice = bad | audit | ~trusted
         accept = ~lattice
-        self.stats.mass_rejects += int((bad & trusted).sum())
-        # project every prediction that may be used or audited
-        proj = torch.from_numpy((trusted & ~bad).astype(np.int32)).to(self.f0.device)
+        self.stats.mass_rejects += int(bad.sum())
+        self.passes[bad] = 0
+        # project every prediction that is used or audited
+        proj = torch.from_numpy((~bad).astype(np.int32)).to(self.f0.device)
         project_mass(self.f1, self.f0, proj)
         b.step_subset(self.K, lattice.astype(np.int32))
         if audit.any():
             b.moments_device(self.flb)
-            err = compare(self.f1, self.flb, self.cmp).cpu().numpy()[:, 2]
-            for i in np.nonzero(audit & ~bad)[0]:
+            cm = compare(self.f1, self.flb, self.cmp).cpu().numpy()
+            err = cm[:, 2] if self.norm == "max" else np.sqrt(cm[:, 4] / cm[:, 5])
+            for i in np.nonzero(audit)[0]:
                 self.stats.audits += 1
                 self.stats.audit_errors.append(float(err[i]))
-                if not (err[i] <= self.tol):
+                if err[i] <= self.tol:
+                    self.passes[i] += 1
+                else:
                     self.stats.audit_failures += 1
-                    self.untrusted_until[i] = c + 1 + self.penalty
+                    self.passes[i] = 0
         b.set_equilibrium(self.f1, accept.astype(np.int32))
         self.stats.lattice_chunks += int(lattice.sum())
         self.stats.surrogate_chunks += int(accept.sum())
@@ -456,7 +490,7 @@ FLOPS_PER_NODE = 2 * 9 * (IN_REAL * WIDTH + BLOCKS * WIDTH * WIDTH + WIDTH * OUT
 
 def experiment(H: int = 128, W: int = 256, train_count: int = 256, train_seed: int = 2024,
                test_count: int = 256, test_seed: int = 99, warmup: int = 300,
-               data_chunks: int = 12, K: int = 50, iters: int = 20000, batch: int = 16,
+               data_chunks: int = 12, K: int = 50, iters: int = 10**7, batch: int = 16,
                lr: float = 2e-3, train_seconds: float = 60.0, eval_chunks: int = 20,
                audit_every: int = 8, tol: float = 1e-2, log=None):
     """Train on lattice data, then advance `test_count` fresh lattices
@@ -472,10 +506,12 @@ def experiment(H: int = 128, W: int = 256, train_count: int = 256, train_seed: i
 
     out = {"size": f"{W}x{H}", "K": K}
     t0 = time.perf_counter()
-    draws = ls.surrogate_draws(train_count, seed=train_seed, Lx=W, Ly=H)
+    raw = ls.surrogate_draws(train_count, seed=train_seed, Lx=W, Ly=H)
+    draws = screen(raw, warmup + data_chunks * K)
     x, tgt, status = generate_data(draws, warmup, data_chunks, K)
+    assert all(s == 0 for s in status)
     out["train_samples"] = int(x.shape[0])
-    out["train_unstable"] = sum(1 for s in status if s)
+    out["train_draws_dropped_unstable"] = len(raw) - len(draws)
     say(f"data: {x.shape[0]} samples in {time.perf_counter() - t0:.1f} s")
     net_t = Net(batch, H, W, train=True)
     net_t.set_params(init_params(0))
@@ -484,61 +520,70 @@ def experiment(H: int = 128, W: int = 256, train_count: int = 256, train_seed: i
     hist = train(net_t, x, tgt, iters, batch, lr, log_every=200, time_limit=train_seconds)
     t_train = time.perf_counter() - t1
     its = hist[-1][0] + 1
+    tail = [l for _, l in hist[-10:]]
     out["train"] = {"iterations": its, "batch": batch, "seconds": round(t_train, 1),
-                    "loss_first": hist[0][1], "loss_last": hist[-1][1],
+                    "loss_first": hist[0][1], "loss_last10_mean": float(np.mean(tail)),
                     "train_tflops": round(3 * FLOPS_PER_NODE * H * W * batch * its / t_train / 1e12, 1)}
-    say(f"train: {its} iterations in {t_train:.1f} s, loss {hist[0][1]:.3e} -> {hist[-1][1]:.3e}")
+    say(f"train: {its} iterations in {t_train:.1f} s, loss {hist[0][1]:.3e} -> {np.mean(tail):.3e}")
     params = net_t.params().clone()
     net_t.close()
     del x, tgt, net_t
     torch.cuda.empty_cache()
 
-    test = ls.surrogate_draws(test_count, seed=test_seed, Lx=W, Ly=H)
+    raw = ls.surrogate_draws(test_count + test_count // 4, seed=test_seed, Lx=W, Ly=H)
+    test = screen(raw, warmup + eval_chunks * K, keep=test_count)
+    out["test_draws_dropped_unstable"] = raw.index(test[-1]) + 1 - len(test)
+    test_count = len(test)
     net = Net(test_count, H, W)
     net.set_params(params)
-    ref = _batch_for(test)
-    sgb = _batch_for(test)
-    ref.step(warmup)
-    sgb.step(warmup)
-    m0 = np.array([sgb.reduce(i)["mass"] for i in range(test_count)])
     steps = eval_chunks * K
+    ref = _batch_for(test)
+    ref.step(warmup)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ref.step(steps)
     torch.cuda.synchronize()
     t_lb = time.perf_counter() - t2
-    run = SurrogateRun(net, sgb, test, K=K, tol=tol, audit_every=audit_every)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    for _ in range(eval_chunks):
-        run.chunk()
-    torch.cuda.synchronize()
-    t_sg = time.perf_counter() - t3
     fr = ref.moments_device()
-    fs = sgb.moments_device()
-    c = compare(fs, fr).cpu().numpy()
-    max_err = c[:, 2]
-    rms_err = np.sqrt(c[:, 4] / c[:, 5])
-    m1 = np.array([sgb.reduce(i)["mass"] for i in range(test_count)])
-    st = run.stats
-    out["eval"] = {
-        "instances": test_count, "steps": steps, "warmup_steps": warmup,
-        "lattice_seconds": round(t_lb, 4), "surrogate_seconds": round(t_sg, 4),
-        "speedup": round(t_lb / t_sg, 3),
-        "final_density_error_max": {"max": float(max_err.max()), "median": float(np.median(max_err)),
-                                    "frac_le_tol": float(np.mean(max_err <= tol))},
-        "final_density_error_rms": {"max": float(rms_err.max()), "median": float(np.median(rms_err))},
-        "fallback_rate": round(st.fallback_rate, 4), "audits": st.audits,
-        "audit_failures": st.audit_failures, "mass_rejects": st.mass_rejects,
-        "audit_error_median": float(np.median(st.audit_errors)) if st.audit_errors else None,
-        "mass_drift_max": float(np.max(np.abs(m1 - m0) / m0)),
-        "tol": tol, "audit_every": audit_every,
-    }
-    say(f"eval: lattice {t_lb * 1e3:.1f} ms, surrogate {t_sg * 1e3:.1f} ms, "
-        f"fallback {st.fallback_rate:.3f}, max err median {np.median(max_err):.3e}")
+    out["eval"] = {"instances": test_count, "steps": steps, "warmup_steps": warmup,
+                   "lattice_seconds": round(t_lb, 4), "tol": tol, "audit_every": audit_every}
+    for norm in ("max", "rms"):
+        sgb = _batch_for(test)
+        sgb.step(warmup)
+        m0 = np.array([sgb.reduce(i)["mass"] for i in range(test_count)])
+        run = SurrogateRun(net, sgb, test, K=K, tol=tol, audit_every=audit_every, norm=norm)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for _ in range(eval_chunks):
+            run.chunk()
+        torch.cuda.synchronize()
+        t_sg = time.perf_counter() - t3
+        fs = sgb.moments_device()
+        c = compare(fs, fr).cpu().numpy()
+        alive = np.array(sgb.status()) == 0
+        max_err = np.where(alive, c[:, 2], np.inf)
+        rms_err = np.where(alive, np.sqrt(c[:, 4] / c[:, 5]), np.inf)
+        m1 = np.array([sgb.reduce(i)["mass"] if alive[i] else np.nan for i in range(test_count)])
+        st = run.stats
+        err_final = max_err if norm == "max" else rms_err
+        out["eval"][f"audit_{norm}"] = {
+            "surrogate_seconds": round(t_sg, 4), "speedup": round(t_lb / t_sg, 3),
+            "fallback_rate": round(st.fallback_rate, 4), "audits": st.audits,
+            "audit_failures": st.audit_failures, "mass_rejects": st.mass_rejects,
+            "audit_error_median": float(np.median(st.audit_errors)) if st.audit_errors else None,
+            "final_error_max_norm": {"max": float(max_err.max()), "median": float(np.median(max_err))},
+            "final_error_rms": {"max": float(rms_err.max()), "median": float(np.median(rms_err))},
+            "final_frac_within_tol": float(np.mean(err_final <= tol)),
+            "mass_drift_max": float(np.nanmax(np.abs(m1 - m0) / m0)),
+            "diverged": int((~alive).sum()),
+        }
+        say(f"eval[{norm}]: lattice {t_lb * 1e3:.1f} ms, surrogate {t_sg * 1e3:.1f} ms, "
+            f"fallback {st.fallback_rate:.3f}, audit err median "
+            f"{out['eval'][f'audit_{norm}']['audit_error_median']}, diverged {(~alive).sum()}")
+        sgb.close()
     # forward throughput on the whole test batch
     vx, cond = conditions(test)
-    xin = fields_to_input(fs, vx, cond, True)
+    xin = fields_to_input(fr, vx, cond, True)
     yo = torch.empty((test_count, H, W, OUT), dtype=torch.float32, device="cuda")
     net.forward(xin, yo)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -553,7 +598,6 @@ def experiment(H: int = 128, W: int = 256, train_count: int = 256, train_seed: i
     out["forward"] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) / 1e12, 1),
                       "peak_bf16_tflops": 2500.0, "frac": round(flops / (ms * 1e-3) / 1e12 / 2500.0, 4),
                       "gflop_per_instance": round(FLOPS_PER_NODE * H * W / 1e9, 3)}
-    for b in (ref, sgb):
-        b.close()
+    ref.close()
     net.close()
     return out

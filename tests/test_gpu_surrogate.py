@@ -141,11 +141,11 @@ def test_wgrad_matches_reference(torch_cuda, ci, cout, cir, cor, shape, blocks):
     g = _rng(ci * 1000 + cout + W)
     x_d, x = _bf16(torch, g.normal(size=(B, H, W, ci)))
     gz_d, gz = _bf16(torch, g.normal(size=(B, H, W, cout)))
-    dw = sg.wgrad(ci, cout, cir, cor, x_d, gz_d, scale=0.5, blocks=blocks)
+    dw, db = sg.wgrad(ci, cout, cir, cor, x_d, gz_d, scale=0.5, blocks=blocks)
     torch.cuda.synchronize()
-    exp = 0.5 * co.conv3x3_wgrad(x[..., :cir], gz[..., :cor])[0].reshape(-1)
-    got = _f64(dw)
-    assert np.max(np.abs(got - exp)) <= 1e-5 * np.max(np.abs(exp)) + 1e-12
+    ew, eb = co.conv3x3_wgrad(x[..., :cir], gz[..., :cor])
+    for got, exp in ((_f64(dw), 0.5 * ew.reshape(-1)), (_f64(db), 0.5 * eb)):
+        assert np.max(np.abs(got - exp)) <= 1e-5 * np.max(np.abs(exp)) + 1e-12
 
 
 def test_bias_grad_mse_adam(torch_cuda):
@@ -334,7 +334,7 @@ def test_audited_run_all_audits_equals_lattice(torch_cuda):
     net = sg.Net(4, 32, 64)
     net.set_params(sg.init_params(1))
     a = sg._batch_for(draws, check_every=0, drift=False)
-    run = sg.SurrogateRun(net, a, draws, K=10, audit_every=1, mass_tol=1.0, penalty=0)
+    run = sg.SurrogateRun(net, a, draws, K=10, audit_every=1, mass_tol=1.0)
     for _ in range(3):
         run.chunk()
     assert run.stats.fallback_rate == 1.0 and run.stats.audits == 12
@@ -348,25 +348,43 @@ def test_audited_run_all_audits_equals_lattice(torch_cuda):
     net.close()
 
 
-def test_audited_run_conserves_mass_and_rejects(torch_cuda):
-    """Accepted predictions keep each instance's FP64 mass; a zero tolerance
-    sends every audited instance back to the lattice."""
+def test_audited_run_trust_rotation_and_mass(torch_cuda):
+    """With a network that predicts no change, every audit within a loose
+    tolerance passes: instances are audited on the lattice while on
+    probation, then half of them per chunk (rotation), the rest re-enter
+    from the prediction, and each instance keeps its FP64 mass."""
     from paper_1307_6703_amd import surrogate as sg
-    _say("audited run, mass and rejection")
+    _say("audited run, trust rotation and mass")
     draws = _draws(4, 64, 32, 9)
     net = sg.Net(4, 32, 64)
-    net.set_params(sg.init_params(2))
+    net.set_params(np.zeros(sg.param_count(), np.float32))
     a = sg._batch_for(draws, check_every=0, drift=False)
     m0 = [a.reduce(i)["mass"] for i in range(4)]
-    run = sg.SurrogateRun(net, a, draws, K=10, tol=0.0, audit_every=2, penalty=100,
-                          mass_tol=1.0)
-    for _ in range(4):
-        run.chunk()
+    run = sg.SurrogateRun(net, a, draws, K=10, tol=1.0, audit_every=2)
+    accepted = [run.chunk() for _ in range(4)]
     st = run.stats
-    assert st.audits == 2 + 2 and st.audit_failures == 4  # chunks 0, 1 audit all four once
-    assert st.surrogate_chunks == 2 + 0 and st.lattice_chunks == 16 - 2
+    assert [list(np.nonzero(x)[0]) for x in accepted] == [[], [0, 2], [1, 3], [0, 2]]
+    assert (st.audits, st.audit_failures, st.surrogate_chunks, st.lattice_chunks) == (10, 0, 6, 10)
     for i in range(4):
         m = a.reduce(i)["mass"]
         assert abs(m - m0[i]) <= 1e-6 * m0[i]
+    a.close()
+    net.close()
+
+
+def test_audited_run_rejects_beyond_tolerance(torch_cuda):
+    """A zero tolerance fails every audit: nothing leaves probation and the
+    run stays on the lattice."""
+    from paper_1307_6703_amd import surrogate as sg
+    _say("audited run, rejection")
+    draws = _draws(4, 64, 32, 10)
+    net = sg.Net(4, 32, 64)
+    net.set_params(sg.init_params(2))
+    a = sg._batch_for(draws, check_every=0, drift=False)
+    run = sg.SurrogateRun(net, a, draws, K=10, tol=0.0, audit_every=2, mass_tol=1.0)
+    for _ in range(4):
+        run.chunk()
+    st = run.stats
+    assert (st.audits, st.audit_failures, st.surrogate_chunks, st.lattice_chunks) == (16, 16, 0, 16)
     a.close()
     net.close()

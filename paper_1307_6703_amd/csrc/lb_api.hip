@@ -387,18 +387,28 @@ lb_status lb_autotune(lb_handle* h, int32_t nsteps, int32_t* threads, int32_t* r
   if (nsteps < 1) return fail(LB_EINVAL, "nsteps must be >= 1");
   if (!h->has_state) return fail(LB_ESTATE, "lattice has no state");
   if (h->unstable) return fail(LB_ESTATE, "lattice was flagged unstable");
-  const int cand_t[] = {128, 256};
-  const int cand_r[] = {16, 32, 64, 128, 256, 512};
+  // candidate shapes: strip widths up to one strip per row, and for each the
+  // chunk heights that fill the resident workgroups once or twice, plus a
+  // few fixed heights
+  std::vector<std::pair<int, int>> cand;
+  for (int t : {128, 256, 512}) {
+    if (t == 512 && !h->p.fp32) continue;
+    if (t > 128 && h->p.Lx + 6 <= t / 2) continue;
+    std::vector<int> rs = {default_rows(&h->p, t, 1), default_rows(&h->p, t, 2), 16, 64};
+    std::sort(rs.begin(), rs.end());
+    rs.erase(std::unique(rs.begin(), rs.end()), rs.end());
+    for (int rw : rs)
+      if (rw <= h->p.Ly) cand.push_back({t, rw});
+  }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   double best = 1e300;
   int bt = h->threads, br = h->rows;
   lb_status r = LB_OK;
-  for (int t : cand_t) {
-    if (t > 128 && h->p.Lx + 6 <= 128) continue;
-    for (int rw : cand_r) {
-      if (rw > h->p.Ly && rw != cand_r[0]) continue;
+  for (const auto& c : cand) {
+    const int t = c.first, rw = c.second;
+    {
       if ((r = set_tiles(h, t, rw)) != LB_OK) break;
       if ((r = step_impl(h, 1, false)) != LB_OK) break;  // warm-up
       if (hipEventRecord(e0, h->st) != hipSuccess) { r = fail(LB_EDEVICE, "event record failed"); break; }

@@ -437,7 +437,7 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t nsteps, int32_t* threads, int32
   for (int i = 0; i < b->count; ++i)
     if (!b->inst[i].has_state) return fail(LB_ESTATE, "instance %d has no state", i);
   if (b->unstable_any) return fail(LB_ESTATE, "an instance was flagged unstable");
-  const int cand_t[] = {128, 256};
+  const int cand_t[] = {128, 256, 512};
   const int cand_r[] = {16, 32, 64, 128, 256};
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -447,6 +447,7 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t nsteps, int32_t* threads, int32
   lb_status r = LB_OK;
   for (int t : cand_t)
     for (int rw : cand_r) {
+      if (t == 512 && !b->fp32) continue;
       if (r != LB_OK) break;
       if ((r = batch_tiles(b, t, rw)) != LB_OK) break;
       if ((r = enqueue_steps(b, 1, false)) != LB_OK) break;

@@ -283,8 +283,21 @@ __device__ __forceinline__ void pull_row(R v[9], __amdgpu_buffer_rsrc_t S, uint3
   v[8] = buf_ld((R*)nullptr, S, v8, (int)(p8 * pbytes + o_n));
 }
 
+// Rows of populations in flight ahead of stage A, and the waves per SIMD the
+// register budget is sized for (FP32; FP64 always sizes for one wave). Two
+// rows at 3 waves per SIMD (about 140 VGPRs, no spills) measured fastest on
+// the 8192 x 2048 lattice: one 512-thread workgroup per CU, 255 workgroups.
+#ifndef LB_PREFETCH
+#define LB_PREFETCH 2
+#endif
+#ifndef LB_WAVES_PER_SIMD
+#define LB_WAVES_PER_SIMD 3
+#endif
+constexpr int kPrefetch = LB_PREFETCH;
+static_assert(kPrefetch == 1 || kPrefetch == 2 || kPrefetch == 4, "prefetch depth must divide 8");
+
 template <typename R, int NT, bool MOM>
-__global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void step_kernel(
+__global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void step_kernel(
     const Desc* __restrict__ descs, const Tile* __restrict__ tiles, int ntiles, int parity,
     int flags) {
   // Workgroups are dealt round-robin over the 8 XCDs; give each XCD a
@@ -343,8 +356,9 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void step_kernel(
   __shared__ Quad<R> JR[4][NT + 2];    // (j*_x, j*_y, F_x, F_y)
   const int u = t + 1;                 // padded column index
 
+  constexpr int P = kPrefetch;
   R f[4][9];     // pulled populations, slot j % 4
-  R pf[9];       // next row's pulled populations, in flight
+  R pf[P][9];    // the next P rows' pulled populations, in flight (slot j % P)
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -361,18 +375,21 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void step_kernel(
   const int K = (y1 - y0) + 6;
   const int a0 = dir > 0 ? y0 - 3 : y1 + 2;
 
-  pull_row<R>(pf, Sin, pbytes, Lx, Ly, periodic, map_row_any(a0, Ly, periodic), vc, vm, vp);
+#pragma unroll
+  for (int j = 0; j < P; ++j)
+    pull_row<R>(pf[j], j < K ? Sin : Snone, pbytes, Lx, Ly, periodic,
+                map_row_any(a0 + dir * j, Ly, periodic), vc, vm, vp);
 
   for (int kb = 0; kb < K; kb += 8) {
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       const int k = kb + s;
       const int a = a0 + dir * k;
-      // ---- stage A: row a (its loads were issued one iteration ago) ----------
+      // ---- stage A: row a (its loads were issued P iterations ago) -----------
       if (k < K) {
         R* v = f[s & 3];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) v[i] = pf[i];
+        for (int i = 0; i < 9; ++i) v[i] = pf[s % P][i];
         if (shift != (R)0) {
           v[0] += sh0;
 #pragma unroll
@@ -383,9 +400,10 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void step_kernel(
         const R dn = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])) + v[8];
         nR[s][u] = dn;
       }
-      // prefetch row a + dir (dropped past the last pipeline row)
-      pull_row<R>(pf, (k + 1 < K) ? Sin : Snone, pbytes, Lx, Ly, periodic,
-                  map_row_any(a + dir, Ly, periodic), vc, vm, vp);
+      // prefetch row a + P dir into the slot just consumed (dropped past the
+      // last pipeline row)
+      pull_row<R>(pf[s % P], (k + P < K) ? Sin : Snone, pbytes, Lx, Ly, periodic,
+                  map_row_any(a + P * dir, Ly, periodic), vc, vm, vp);
       __syncthreads();
       // ---- stage B: row a - dir: Laplacian and pressure term -----------------
       if (k >= 2 && k < K && actB) {

@@ -94,16 +94,19 @@ inline Layout layout_for(const lb_params* p, size_t base = 0) {
   return L;
 }
 
+// Strip width: one strip per row for narrow lattices; 512-thread strips
+// (one workgroup per CU) once the lattice fills the device with them.
 inline int default_threads(const lb_params* p) {
   if (p->Lx + 6 <= 64) return 64;
   if (p->Lx + 6 <= 128 || !p->fp32) return 128;
   if (p->Lx + 6 <= 256) return 256;
   if (p->Lx + 6 <= 320) return 320;  // one strip per row (e.g. 256-wide lattices)
+  if ((int64_t)p->Lx * p->Ly >= ((int64_t)1 << 22)) return 512;
   return 256;
 }
 
 // Workgroups of the step kernel that fit on the device at once: FP32 runs at
-// 4 waves per SIMD (128 VGPRs), FP64 at 2.
+// 3 waves per SIMD (about 140 VGPRs), FP64 at 2.
 inline int resident_slots(const lb_params* p, int threads) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
@@ -111,18 +114,23 @@ inline int resident_slots(const lb_params* p, int threads) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
       cus = v;
   }
-  const int waves_per_cu = (p->fp32 ? 4 : 2) * 4;
+  const int waves_per_cu = (p->fp32 ? 3 : 2) * 4;
   return cus * std::max(1, waves_per_cu / ((threads + 63) / 64));
 }
 
-// Rows per chunk: as few chunks as fill the resident workgroups once, and a
-// height of 2 mod 8 so the kernel's 8-row unrolled march has no idle tail.
-inline int default_rows(const lb_params* p, int threads) {
-  const int strips = (p->Lx + threads - 7) / (threads - 6);
-  const int chunks = std::max(1, resident_slots(p, threads) / strips);
-  int rows = (p->Ly + chunks - 1) / chunks;
+// Rows per chunk for a target number of chunks: a height of 2 mod 8 so the
+// kernel's 8-row unrolled march has no idle tail.
+inline int rows_for_chunks(int Ly, int chunks) {
+  int rows = (Ly + std::max(chunks, 1) - 1) / std::max(chunks, 1);
   rows = ((std::max(rows, 10) - 2 + 7) / 8) * 8 + 2;
-  return std::min(rows, p->Ly);
+  return std::min(rows, Ly);
+}
+
+// Rows per chunk: as few chunks as fill the resident workgroups `rounds`
+// times.
+inline int default_rows(const lb_params* p, int threads, int rounds = 1) {
+  const int strips = (p->Lx + threads - 7) / (threads - 6);
+  return rows_for_chunks(p->Ly, rounds * resident_slots(p, threads) / strips);
 }
 
 // Tiles of one lattice: strips of threads-6 columns, chunks of `rows` rows,

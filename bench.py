@@ -214,6 +214,20 @@ def main():
     print(f"[bench] step kernel {k_ms * 1e3:.1f} us/launch, {achieved:.0f} GB/s algorithmic",
           file=sys.stderr, flush=True)
 
+    # the same bytes moved by a plain device copy: the streaming rate this
+    # GPU reaches in practice (read + write), for context beside the peak
+    src = torch.empty(w.nodes * 9, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e4, e5 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e4.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e5.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 4 / (e4.elapsed_time(e5) / 10 * 1e-3) / 1e9
+    del src, dst
+
     out = {
         "metric": "MLUPS",
         "value": round(mlups, 1),
@@ -237,7 +251,9 @@ def main():
                      "traffic": measured_traffic(w.nodes),
                      "kernel": "step_kernel<float,%d>" % threads,
                      "us_per_launch": round(k_ms * 1e3, 2),
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "copy_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(achieved / copy_gbs, 4)},
         "hbm_frac_of_peak": round(mlups * 1e6 * BYTES_PER_UPDATE_FP32 / 1e9 / HBM_PEAK_GBS, 4),
         "mass_drift": abs(red["mass"] - m0) / m0,
         "gpu": torch.cuda.get_device_name(0),

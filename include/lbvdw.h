@@ -20,9 +20,10 @@
  * density F_l = F_p / 3). Densities are the reduced density n / n_c, T is
  * T / T_c. Velocities are in dx/dt.
  *
- * Layout: populations are planes P[i][y][x] (x fastest), i = 0 rest, 1 E, 2 N,
- * 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE. Host field arrays are row-major [Ly][Lx]
- * FP64. x is periodic. With walls, rows 0 and Ly-1 are the wall nodes: the
+ * Layout: population arrays exchanged with the caller are planes P[i][y][x]
+ * (x fastest), i = 0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE (on the
+ * device the library keeps the nine planes of each row adjacent,
+ * [y][i][x]). Host field arrays are row-major [Ly][Lx] FP64. x is periodic. With walls, rows 0 and Ly-1 are the wall nodes: the
  * lower wall moves at -U, the upper at +U (shear rate 2U/(Ly-1)).
  *
  * Precision: fp32 = 0 stores and computes populations in FP64. fp32 = 1 stores

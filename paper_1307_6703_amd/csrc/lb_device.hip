@@ -50,6 +50,12 @@ __host__ __device__ inline double rest_weight_hd(int i, double T) {
 
 double rest_weight(int i, double T) { return rest_weight_hd(i, T); }
 
+// Populations are stored row-interleaved: the nine planes of one lattice row
+// are adjacent, S[(9 y + i) Lx + x]. Index of population i at node k = y Lx + x.
+__device__ __forceinline__ int64_t pidx(int i, int64_t k, int64_t y, int Lx) {
+  return k + (8 * y + i) * (int64_t)Lx;
+}
+
 template <typename R>
 struct Par {
   R nbar, T, omega, sF, kappa3, third, N, M, Q, Rw, Ub, Ut;
@@ -253,12 +259,11 @@ __device__ __forceinline__ RowMap map_row_any(int a, int Ly, int periodic) {
 }
 
 template <typename R>
-__device__ __forceinline__ void pull_row(R v[9], __amdgpu_buffer_rsrc_t S, uint32_t pbytes, int Lx,
-                                         int Ly, int periodic, const RowMap& m, int vc, int vm,
-                                         int vp) {
+__device__ __forceinline__ void pull_row(R v[9], __amdgpu_buffer_rsrc_t S, uint32_t pbytes,
+                                         uint32_t rb, int Ly, int periodic, const RowMap& m, int vc,
+                                         int vm, int vp) {
   // source rows y - c_y (wrapped when periodic); at a wall node the slots
   // whose source lies outside take the node's own outgoing populations
-  const uint32_t rb = (uint32_t)Lx * (uint32_t)sizeof(R);
   int rs = m.phys - 1, rn = m.phys + 1;
   if (periodic) {
     rs = rs < 0 ? rs + Ly : rs;
@@ -312,7 +317,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
   const Desc& d = descs[inst];
   const int Lx = d.Lx, Ly = d.Ly, periodic = d.periodic;
   const int64_t nn = (int64_t)Lx * Ly;
-  const int rowb = Lx * (int)sizeof(R);            // bytes of one row
+  const int rowb = 9 * Lx * (int)sizeof(R);        // bytes of one row (nine planes)
   const int arrb = (int)(9 * nn * (int64_t)sizeof(R));  // bytes of the nine planes (< 2 GiB)
   const __amdgpu_buffer_rsrc_t Sin = make_rsrc(d.S[parity], arrb);
   const __amdgpu_buffer_rsrc_t Sout = make_rsrc(d.S[parity ^ 1], arrb);
@@ -345,7 +350,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
   const int vm = actA ? xm * (int)sizeof(R) : arrb;
   const int vp = actA ? xp * (int)sizeof(R) : arrb;
   const R fx3 = actC ? fext3[xc] : (R)0;
-  const uint32_t pbytes = (uint32_t)(nn * (int64_t)sizeof(R));
+  const uint32_t pbytes = (uint32_t)Lx * (uint32_t)sizeof(R);  // plane stride within a row
 
   // LDS rings indexed by pipeline row j (row a_j = a_0 + dir j): slot j % 8
   // for n, j % 4 for the others. With the loop unrolled by 8 every slot is a
@@ -377,7 +382,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
 
 #pragma unroll
   for (int j = 0; j < P; ++j)
-    pull_row<R>(pf[j], j < K ? Sin : Snone, pbytes, Lx, Ly, periodic,
+    pull_row<R>(pf[j], j < K ? Sin : Snone, pbytes, (uint32_t)rowb, Ly, periodic,
                 map_row_any(a0 + dir * j, Ly, periodic), vc, vm, vp);
 
   for (int kb = 0; kb < K; kb += 8) {
@@ -402,7 +407,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
       }
       // prefetch row a + P dir into the slot just consumed (dropped past the
       // last pipeline row)
-      pull_row<R>(pf[s % P], (k + P < K) ? Sin : Snone, pbytes, Lx, Ly, periodic,
+      pull_row<R>(pf[s % P], (k + P < K) ? Sin : Snone, pbytes, (uint32_t)rowb, Ly, periodic,
                   map_row_any(a + P * dir, Ly, periodic), vc, vm, vp);
       __syncthreads();
       // ---- stage B: row a - dir: Laplacian and pressure term -----------------
@@ -572,7 +577,7 @@ __global__ void init_kernel(const Desc* __restrict__ desc, int parity, const dou
       const double cu = cx(i) * ux + cy(i) * uy;
       const double wr = rest_weight_hd(i, d.T);
       const double g = wr * (n - d.nbar) + w[i] * n * (3.0 * cu + 4.5 * cu * cu - usq);
-      S[i * nn + k] = (R)g;
+      S[pidx(i, k, k / d.Lx, d.Lx)] = (R)g;
     }
     if (d.mom) {
       d.mom[k] = n;
@@ -642,9 +647,10 @@ __global__ __launch_bounds__(kRedBS) void reduce_kernel(const Desc* __restrict__
   for (int i = 0; i < 9; ++i) wr[i] = rest_weight_hd(i, d.T) * base;
   for (int64_t k = blockIdx.x * (int64_t)kRedBS + threadIdx.x; k < nn; k += (int64_t)gridDim.x * kRedBS) {
     double rho = 0, px = 0, py = 0;
+    const int64_t y = k / d.Lx;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const double f = (double)S[i * nn + k] + wr[i];
+      const double f = (double)S[pidx(i, k, y, d.Lx)] + wr[i];
       rho += f;
       px += cx(i) * f;
       py += cy(i) * f;
@@ -749,7 +755,8 @@ __global__ void get_pops_kernel(const Desc* __restrict__ desc, int parity, int p
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nn;
        k += (int64_t)gridDim.x * blockDim.x)
     for (int i = p0; i < p1; ++i)
-      out[(int64_t)(i - p0) * nn + k] = (double)S[(int64_t)i * nn + k] + rest_weight_hd(i, d.T) * base;
+      out[(int64_t)(i - p0) * nn + k] =
+          (double)S[pidx(i, k, k / d.Lx, d.Lx)] + rest_weight_hd(i, d.T) * base;
 }
 
 template <typename R>
@@ -760,7 +767,8 @@ __global__ void set_pops_kernel(const Desc* __restrict__ desc, int parity, int p
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nn;
        k += (int64_t)gridDim.x * blockDim.x)
     for (int i = p0; i < p1; ++i)
-      S[(int64_t)i * nn + k] = (R)(in[(int64_t)(i - p0) * nn + k] - rest_weight_hd(i, d.T) * d.nbar);
+      S[pidx(i, k, k / d.Lx, d.Lx)] =
+          (R)(in[(int64_t)(i - p0) * nn + k] - rest_weight_hd(i, d.T) * d.nbar);
 }
 
 hipError_t launch_get_pops(bool fp32, const Desc* d_desc, int parity, int p0, int p1, int64_t nn,
@@ -818,7 +826,8 @@ __global__ void scatter_eq_kernel(const Desc* __restrict__ descs, ReduceOut* __r
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       const double cu = cx(q) * ux + cy(q) * uy;
-      S[q * nn + k] = (R)(rest_weight_hd(q, d.T) * (n - d.nbar) + w[q] * n * (3.0 * cu + 4.5 * cu * cu - usq));
+      S[pidx(q, k, k / d.Lx, d.Lx)] =
+          (R)(rest_weight_hd(q, d.T) * (n - d.nbar) + w[q] * n * (3.0 * cu + 4.5 * cu * cu - usq));
     }
     d.mom[k] = n;
     d.mom[nn + k] = ux;

@@ -12,7 +12,7 @@ namespace lbk {
 // One lattice as the kernels see it. Lives in device memory (an array of
 // these for a batch, one for a single lattice).
 struct Desc {
-  void* S[2];            // population planes [9][Ly][Lx], buffers 0 and 1
+  void* S[2];            // populations [Ly][9][Lx] (planes of a row adjacent), buffers 0 and 1
   const void* fext3;     // per-column F_ext,x / 3 (lattice units), Lx values
   double* mom;           // n, ux, uy planes (FP64) of the last step, or null
   const double* shift;   // pending uniform density shift, or null

@@ -268,3 +268,25 @@ def test_rest_state_is_stationary():
     S0 = o.S.copy()
     o.run(10)
     assert np.abs(o.S - S0).max() < 1e-15
+
+
+def test_window_runs_are_exact_inside_the_dependency_cone():
+    """One step reaches 4 columns (pulls +-1, density stencils +-3), so a run on
+    a window of a periodic lattice, itself periodic at the cut edges, equals the
+    full run bitwise on columns farther than 4 S from the edges after S steps.
+    (Used by the full-size GPU test to check 100 steps of 8192 x 2048.)"""
+    Lx, Ly, S = 300, 40, 20
+    w = ls.Workload("window", Lx, Ly, T=0.9, V0=0.01, k=4, U=0.08, seed=5)
+    n0, fext = w.n0(), w.fext()
+    full = OracleLB(Params(Lx, Ly, T=w.T, N=w.N, Q=w.Q, U=w.U), n0, fext=fext)
+    full.run(S)
+    half, x0 = 4 * S + 10, 7
+    cols = np.arange(x0 - half, x0 + half) % Lx
+    win = OracleLB(Params(cols.size, Ly, T=w.T, N=w.N, Q=w.Q, U=w.U),
+                   np.ascontiguousarray(n0[:, cols]), fext=np.ascontiguousarray(fext[cols]))
+    win.run(S)
+    keep = slice(half - 10, half + 10)
+    for a, b in ((win.n, full.n), (win.ux, full.ux), (win.uy, full.uy)):
+        assert np.array_equal(a[:, keep], b[:, cols[keep]])
+    # the cut edges do differ: the window is not trivially equal
+    assert np.abs(win.n[:, :5] - full.n[:, cols[:5]]).max() > 1e-6

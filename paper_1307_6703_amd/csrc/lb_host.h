@@ -98,7 +98,9 @@ inline Layout layout_for(const lb_params* p, size_t base = 0) {
 // (one workgroup per CU) once the lattice fills the device with them.
 inline int default_threads(const lb_params* p) {
   if (p->Lx + 6 <= 64) return 64;
-  if (p->Lx + 6 <= 128 || !p->fp32) return 128;
+  // FP64 (two waves per SIMD): 256-thread strips once the lattice is large
+  if (!p->fp32) return ((int64_t)p->Lx * p->Ly >= ((int64_t)1 << 22) && p->Lx + 6 > 128) ? 256 : 128;
+  if (p->Lx + 6 <= 128) return 128;
   if (p->Lx + 6 <= 256) return 256;
   if (p->Lx + 6 <= 320) return 320;  // one strip per row (e.g. 256-wide lattices)
   if ((int64_t)p->Lx * p->Ly >= ((int64_t)1 << 22)) return 512;

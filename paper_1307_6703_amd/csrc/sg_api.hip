@@ -16,7 +16,7 @@ namespace {
 constexpr int kLayers = LBS_BLOCKS + 2;
 constexpr int kWgradBlocks = 512;
 constexpr int kMsePart = 512;      // matches the loss kernel
-constexpr int kConvGridMax = 2048;
+constexpr int kConvGridMax = 1 << 20;  // the launcher caps the grid at the resident workgroups
 
 int kpad(int kin) { return (9 * kin + 31) / 32 * 32; }
 
@@ -409,7 +409,9 @@ lb_status lbs_conv(int32_t mode, int32_t ci, int32_t co, const void* d_x, const 
   lb_status r = check_image(B, H, W);
   if (r != LB_OK) return r;
   if (!d_x || !d_wpack) return fail(LB_EINVAL, "x and wpack are required");
-  if (!aligned16(d_x) || !aligned16(d_wpack)) return fail(LB_EINVAL, "x and wpack must be 16-byte aligned");
+  if (!aligned16(d_x) || !aligned16(d_wpack) || !aligned16(d_y) || !aligned16(d_z) ||
+      !aligned16(d_res) || !aligned16(d_zprev) || !aligned16(d_yf))
+    return fail(LB_EINVAL, "tensors must be 16-byte aligned");
   if (mode == sg::FWD_OUT) {
     if (!d_yf) return fail(LB_EINVAL, "output mode needs yf");
     if (nout < 1 || nout > co) return fail(LB_EINVAL, "nout must be in [1, %d]", co);

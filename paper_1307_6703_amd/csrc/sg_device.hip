@@ -44,16 +44,54 @@ __host__ __device__ constexpr int kpad() { return (9 * CI + 31) / 32 * 32; }
 // 3x3 convolution (forward, or input-gradient with flipped weights).
 // Persistent workgroups: the packed weights are staged in LDS once, then each
 // workgroup walks tiles of TR rows x TW columns of one image. Each wave owns
-// one output row: 4 M-subtiles of 16 pixels by CO/16 N-subtiles.
+// one output row: 4 M-subtiles of 16 pixels by CO/16 N-subtiles. The next
+// tile's input is loaded into registers while the matrix cores work on the
+// current one; results go through LDS (FP32) so that the epilogue reads and
+// writes whole 16-byte vectors of 8 channels.
 // ---------------------------------------------------------------------------
+template <int CI, int CO>
+struct ConvShape {
+  static constexpr int K = 9 * CI, KP = kpad<CI>(), NS = CO / 16;
+  static constexpr int PX = CI + 8;   // LDS pixel stride (elements): conflict-free 16-byte reads
+  static constexpr int WS = KP + 8;   // LDS weight row stride
+  static constexpr int TCOLS = TW + 2, TROWS = TR + 2;
+  static constexpr int CH = CI / 8;   // 16-byte chunks per input pixel
+  static constexpr int NLD = TROWS * TCOLS * CH;
+  static constexpr int PER = (NLD + NTH - 1) / NTH;  // input chunks per thread
+  static constexpr int SE = CO + 4;   // LDS stride (floats) of one output pixel
+};
+
+template <int CI, int CO>
+__device__ __forceinline__ void conv_load_tile(uint4* pre, const bf16* x,
+                                               int tile, int tilesX, int tilesY, int H, int W) {
+  using S = ConvShape<CI, CO>;
+  const int tx = tile % tilesX, ty = (tile / tilesX) % tilesY, img = tile / (tilesX * tilesY);
+  const int x0 = tx * TW, h0 = ty * TR;
+#pragma unroll
+  for (int j = 0; j < S::PER; ++j) {
+    const int i = threadIdx.x + j * NTH;
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (i < S::NLD) {
+      const int c = i % S::CH, pix = i / S::CH;
+      const int col = pix % S::TCOLS, row = pix / S::TCOLS;
+      const int h = h0 - 1 + row;
+      int xx = (x0 - 1 + col) % W;
+      if (xx < 0) xx += W;
+      if (h >= 0 && h < H)
+        v = *(const uint4*)(x + (((int64_t)img * H + h) * W + xx) * CI + c * 8);
+    }
+    pre[j] = v;
+  }
+}
+
 template <int CI, int CO, int MODE>
 __global__ __launch_bounds__(NTH) void conv_kernel(ConvArgs a) {
-  constexpr int K = 9 * CI, KP = kpad<CI>(), NS = CO / 16;
-  constexpr int PX = CI + 8;   // LDS pixel stride (elements): conflict-free 16-byte reads
-  constexpr int WS = KP + 8;   // LDS weight row stride
-  constexpr int TCOLS = TW + 2, TROWS = TR + 2;
-  __shared__ __attribute__((aligned(16))) bf16 sx[TROWS * TCOLS * PX];
+  using S = ConvShape<CI, CO>;
+  constexpr int KP = S::KP, NS = S::NS, PX = S::PX, WS = S::WS, TCOLS = S::TCOLS;
+  constexpr int K = S::K, SE = S::SE;
+  __shared__ __attribute__((aligned(16))) bf16 sx[S::TROWS * TCOLS * PX];
   __shared__ __attribute__((aligned(16))) bf16 sw[CO * WS];
+  __shared__ __attribute__((aligned(16))) float se[TR * TW * SE];
 
   const int tid = threadIdx.x;
   for (int i = tid; i < CO * (KP / 8); i += NTH) {
@@ -65,27 +103,26 @@ __global__ __launch_bounds__(NTH) void conv_kernel(ConvArgs a) {
   const int ntiles = tilesX * tilesY * a.B;
   const int wave = tid >> 6, lane = tid & 63, lm = lane & 15, lg = lane >> 4;
 
+  uint4 pre[S::PER];
+  if (blockIdx.x < ntiles) conv_load_tile<CI, CO>(pre, a.x, blockIdx.x, tilesX, tilesY, a.H, a.W);
+
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int tx = tile % tilesX;
     const int ty = (tile / tilesX) % tilesY;
     const int img = tile / (tilesX * tilesY);
     const int x0 = tx * TW, h0 = ty * TR;
-    __syncthreads();  // previous tile's reads of sx are done (and sw is staged)
-    {
-      constexpr int CH = CI / 8;
-      for (int i = tid; i < TROWS * TCOLS * CH; i += NTH) {
-        const int c = i % CH, pix = i / CH;
-        const int col = pix % TCOLS, row = pix / TCOLS;
-        const int h = h0 - 1 + row;
-        int xx = (x0 - 1 + col) % a.W;
-        if (xx < 0) xx += a.W;
-        uint4 v = {0u, 0u, 0u, 0u};
-        if (h >= 0 && h < a.H)
-          v = *(const uint4*)(a.x + (((int64_t)img * a.H + h) * a.W + xx) * CI + c * 8);
-        *(uint4*)&sx[(row * TCOLS + col) * PX + c * 8] = v;
+    __syncthreads();  // the previous tile's readers of sx and se are done (and sw is staged)
+#pragma unroll
+    for (int j = 0; j < S::PER; ++j) {
+      const int i = tid + j * NTH;
+      if (i < S::NLD) {
+        const int c = i % S::CH, pix = i / S::CH;
+        *(uint4*)&sx[pix * PX + c * 8] = pre[j];
       }
     }
     __syncthreads();
+    if (tile + (int)gridDim.x < ntiles)  // in flight during the matrix work
+      conv_load_tile<CI, CO>(pre, a.x, tile + gridDim.x, tilesX, tilesY, a.H, a.W);
 
     f32x4 acc[4][NS];
 #pragma unroll
@@ -112,43 +149,84 @@ __global__ __launch_bounds__(NTH) void conv_kernel(ConvArgs a) {
       }
     }
 
-    // epilogue: D[m][n] -> pixel x0 + 16 ms + 4 lg + r, channel 16 ns + lm
-    const int h = h0 + wave;
-    if (h < a.H) {
+    // D[m][n] -> pixel (wave, 16 ms + 4 lg + r), channel 16 ns + lm, plus the bias
+#pragma unroll
+    for (int ns = 0; ns < NS; ++ns) {
+      const int co = ns * 16 + lm;
+      const float bv = (a.bias && (MODE != FWD_OUT || co < a.nout)) ? a.bias[co] : 0.f;
 #pragma unroll
       for (int ms = 0; ms < 4; ++ms)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int xx = x0 + ms * 16 + lg * 4 + r;
-          if (xx >= a.W) continue;
-          const int64_t p = ((int64_t)img * a.H + h) * a.W + xx;
+        for (int r = 0; r < 4; ++r)
+          se[(wave * TW + ms * 16 + lg * 4 + r) * SE + co] = acc[ms][ns][r] + bv;
+    }
+    __syncthreads();
+
+    // epilogue: one 8-channel vector per work item, coalesced
+    if (MODE == FWD_OUT) {
+      for (int i = tid; i < TR * TW; i += NTH) {
+        const int row = i / TW, px = i % TW, h = h0 + row, xx = x0 + px;
+        if (h >= a.H || xx >= a.W) continue;
+        const int64_t p = ((int64_t)img * a.H + h) * a.W + xx;
+        for (int c = 0; c < a.nout; ++c) a.yf[p * a.nout + c] = se[i * SE + c];
+      }
+    } else {
+      constexpr int C8 = CO / 8;
+      for (int i = tid; i < TR * TW * C8; i += NTH) {
+        const int c8 = i % C8, pi = i / C8;
+        const int row = pi / TW, px = pi % TW, h = h0 + row, xx = x0 + px;
+        if (h >= a.H || xx >= a.W) continue;
+        const int64_t off = (((int64_t)img * a.H + h) * a.W + xx) * CO + c8 * 8;
+        const float4 v0 = *(const float4*)&se[pi * SE + c8 * 8];
+        const float4 v1 = *(const float4*)&se[pi * SE + c8 * 8 + 4];
+        const float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        bf16x8 yo, zo;
+        if (MODE == FWD_FIRST) {
 #pragma unroll
-          for (int ns = 0; ns < NS; ++ns) {
-            const int co = ns * 16 + lm;
-            if (MODE == FWD_OUT && co >= a.nout) continue;  // padded channels: no bias entry
-            const float v = acc[ms][ns][r] + (a.bias ? a.bias[co] : 0.f);
-            if (MODE == FWD_FIRST) {
-              a.y[p * CO + co] = f2bf(silu(v));
-              if (a.z) a.z[p * CO + co] = f2bf(v);
-            } else if (MODE == FWD_RES) {
-              a.y[p * CO + co] = f2bf(bf2f(a.res[p * CO + co]) + silu(v));
-              if (a.z) a.z[p * CO + co] = f2bf(v);
-            } else if (MODE == FWD_OUT) {
-              a.yf[p * a.nout + co] = v;
-            } else {  // BWD: v = dL/dh of this layer's input (+ the residual path)
-              const float g = v + (a.res ? bf2f(a.res[p * CO + co]) : 0.f);
-              if (a.z) a.z[p * CO + co] = f2bf(g);
-              a.y[p * CO + co] = f2bf(g * silu_grad(bf2f(a.zprev[p * CO + co])));
-            }
+          for (int j = 0; j < 8; ++j) {
+            yo[j] = f2bf(silu(v[j]));
+            zo[j] = f2bf(v[j]);
+          }
+        } else if (MODE == FWD_RES) {
+          const bf16x8 rr = *(const bf16x8*)(a.res + off);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            yo[j] = f2bf(bf2f(rr[j]) + silu(v[j]));
+            zo[j] = f2bf(v[j]);
+          }
+        } else {  // BWD: v = dL/dh of this layer's input (+ the residual path)
+          bf16x8 rr = bf16x8{};
+          if (a.res) rr = *(const bf16x8*)(a.res + off);
+          const bf16x8 zp = *(const bf16x8*)(a.zprev + off);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const float g = v[j] + bf2f(rr[j]);
+            zo[j] = f2bf(g);
+            yo[j] = f2bf(g * silu_grad(bf2f(zp[j])));
           }
         }
+        *(bf16x8*)(a.y + off) = yo;
+        if (a.z) *(bf16x8*)(a.z + off) = zo;
+      }
     }
   }
 }
 
 template <int CI, int CO, int MODE>
 static hipError_t launch_conv_t(const ConvArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((conv_kernel<CI, CO, MODE>), dim3(grid), dim3(NTH), 0, st, a);
+  // persistent: at most the workgroups that fit on the device at once
+  static int resident = 0;
+  if (!resident) {
+    int dev = 0, cus = 256, per = 1;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, conv_kernel<CI, CO, MODE>, NTH, 0) !=
+            hipSuccess || per < 1)
+      per = 1;
+    resident = cus * per;
+  }
+  hipLaunchKernelGGL((conv_kernel<CI, CO, MODE>), dim3(grid < resident ? grid : resident), dim3(NTH),
+                     0, st, a);
   return hipGetLastError();
 }
 

@@ -280,26 +280,61 @@ __global__ __launch_bounds__(NTH) void wgrad_kernel(WgradArgs a) {
     const int sx = sgi % segX, h = (sgi / segX) % a.H, img = sgi / (segX * a.H);
     const int x0 = sx * SEG;
     __syncthreads();
-    // A^T[tap*CI + ci][p] = x[h + dy][x0 + p + dx][ci] (0 outside rows, or past W)
-    for (int i = tid; i < 9 * SEG * (CI / 8); i += NTH) {
-      const int c8 = i % (CI / 8), p = (i / (CI / 8)) % SEG, tap = i / ((CI / 8) * SEG);
-      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-      const int hh = h + dy;
-      int xx = (x0 + p + dx) % a.W;
-      if (xx < 0) xx += a.W;
-      bf16x8 v = bf16x8{};
-      if (hh >= 0 && hh < a.H && x0 + p < a.W)
-        v = *(const bf16x8*)(a.x + (((int64_t)img * a.H + hh) * a.W + xx) * CI + c8 * 8);
+    // A^T[tap*CI + ci][p] = x[h + dy][x0 + p + dx][ci] (0 outside rows, or past W), built
+    // from blocks of 8 pixels x 8 channels: eight 16-byte loads, a register transpose,
+    // eight 16-byte LDS stores
+    constexpr int CA = CI / 8, NA = 9 * (SEG / 8) * CA;
+    for (int it = tid; it < NA + (SEG / 8) * (CO / 8); it += NTH) {
+      uint4 in[8];
+      int row0;                // LDS row of channel 0 of this block
+      bf16* base;
+      int g;                   // pixel group
+      if (it < NA) {
+        const int c8 = it % CA, t2 = it / CA;
+        g = t2 % (SEG / 8);
+        const int tap = t2 / (SEG / 8);
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const int hh = h + dy;
+        const bool rowok = hh >= 0 && hh < a.H;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) sa[(tap * CI + c8 * 8 + j) * PS + p] = v[j];
-    }
-    for (int i = tid; i < SEG * (CO / 8); i += NTH) {
-      const int c8 = i % (CO / 8), p = i / (CO / 8);
-      bf16x8 v = bf16x8{};
-      if (x0 + p < a.W)
-        v = *(const bf16x8*)(a.gz + (((int64_t)img * a.H + h) * a.W + x0 + p) * CO + c8 * 8);
+        for (int q = 0; q < 8; ++q) {
+          const int p = g * 8 + q;
+          int xx = (x0 + p + dx) % a.W;
+          if (xx < 0) xx += a.W;
+          in[q] = uint4{0u, 0u, 0u, 0u};
+          if (rowok && x0 + p < a.W)
+            in[q] = *(const uint4*)(a.x + (((int64_t)img * a.H + hh) * a.W + xx) * CI + c8 * 8);
+        }
+        row0 = tap * CI + c8 * 8;
+        base = sa;
+      } else {
+        const int j2 = it - NA, c8 = j2 % (CO / 8);
+        g = j2 / (CO / 8);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) sg[(c8 * 8 + j) * PS + p] = v[j];
+        for (int q = 0; q < 8; ++q) {
+          const int p = g * 8 + q;
+          in[q] = uint4{0u, 0u, 0u, 0u};
+          if (x0 + p < a.W)
+            in[q] = *(const uint4*)(a.gz + (((int64_t)img * a.H + h) * a.W + x0 + p) * CO + c8 * 8);
+        }
+        row0 = c8 * 8;
+        base = sg;
+      }
+      // transpose: out row (channel) 2w holds the low halves of dword w of the 8
+      // pixels, row 2w + 1 the high halves; dword k of a row packs pixels 2k, 2k + 1
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        uint32_t lo[4], hi[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t e = ((const uint32_t*)&in[2 * k])[w];
+          const uint32_t o = ((const uint32_t*)&in[2 * k + 1])[w];
+          lo[k] = __builtin_amdgcn_perm(o, e, 0x05040100u);
+          hi[k] = __builtin_amdgcn_perm(o, e, 0x07060302u);
+        }
+        *(uint4*)&base[(row0 + 2 * w) * PS + g * 8] = uint4{lo[0], lo[1], lo[2], lo[3]};
+        *(uint4*)&base[(row0 + 2 * w + 1) * PS + g * 8] = uint4{hi[0], hi[1], hi[2], hi[3]};
+      }
     }
     __syncthreads();
     if (tid < CO) {

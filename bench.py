@@ -149,7 +149,7 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one MI355X: the lattice fits one GPU's HBM and this build "
+        print("bench.py measures one MI355X: the lattice fits one GPU's HBM and this library "
               "has no multi-GPU path; run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

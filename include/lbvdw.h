@@ -165,6 +165,12 @@ lb_status lb_batch_get_moments(lb_batch* b, int32_t idx, double* n, double* ux, 
 lb_status lb_batch_reduce(lb_batch* b, int32_t idx, double out[6]);
 /* Per-instance status of the checks so far (LB_OK or LB_EUNSTABLE); syncs. */
 lb_status lb_batch_status(lb_batch* b, int32_t* per_instance);
+/* Take every instance that failed a check out of the batch so that the
+ * others can keep stepping (lb_batch_step_n otherwise returns LB_ESTATE once
+ * any instance is unstable). Dropped instances keep their last state and
+ * report LB_EUNSTABLE. *dropped (may be NULL) receives the number of
+ * instances dropped so far. LB_ESTATE if every instance is unstable. Syncs. */
+lb_status lb_batch_drop_unstable(lb_batch* b, int32_t* dropped);
 lb_status lb_batch_destroy(lb_batch* b);
 
 /* ---- batch calls for a learned surrogate (all instances the same size) ----

@@ -82,6 +82,7 @@ struct lb_batch {
   bool pending_shift = false;
   bool unstable_any = false;
   std::vector<int> unstable;
+  std::vector<char> dropped;  // instances taken out of the steps (lb_batch_drop_unstable)
   // graphs of kGraphSteps steps, keyed by the pending-shift state at entry;
   // recorded on a private stream (the caller's may be the null stream, which
   // cannot be captured) and replayed on the caller's
@@ -108,7 +109,7 @@ void drop_graphs(lb_batch* b) {
 std::vector<Tile> tile_list(const lb_batch* b, int threads, int rows, const int32_t* mask) {
   std::vector<int> order;
   for (int i = 0; i < b->count; ++i)
-    if (!mask || mask[i]) order.push_back(i);
+    if ((!mask || mask[i]) && !b->dropped[i]) order.push_back(i);
   std::stable_sort(order.begin(), order.end(),
                    [&](int x, int y) { return inst_nodes(b, x) > inst_nodes(b, y); });
   std::vector<Tile> all;
@@ -140,7 +141,7 @@ lb_status enqueue_checks(lb_batch* b, int mode, int only = -1, const int32_t* ma
   for (int i = 0; i < b->count; ++i) {
     if (only >= 0 && i != only) continue;
     if (mask && !mask[i]) continue;
-    if (!b->inst[i].has_state) continue;
+    if (!b->inst[i].has_state || b->dropped[i]) continue;
     const int64_t nn = inst_nodes(b, i);
     HIPCHK(lbk::launch_reduce(b->fp32, b->ddesc + i, b->parity, nn, b->dpart,
                               (mode == 2 && b->pending_shift) ? 1 : 0, b->st));
@@ -218,7 +219,7 @@ lb_status read_batch_status(lb_batch* b) {
   HIPCHK(hipMemcpyAsync(r.data(), b->dred, sizeof(ReduceOut) * b->count, hipMemcpyDeviceToHost, b->st));
   HIPCHK(hipStreamSynchronize(b->st));
   for (int i = 0; i < b->count; ++i)
-    if (r[i].status & 1u) {
+    if ((r[i].status & 1u) && !b->dropped[i]) {
       b->unstable[i] = 1;
       b->unstable_any = true;
     }
@@ -273,6 +274,7 @@ lb_status lb_batch_create(int32_t count, const lb_params* p, void* dev_ws, size_
   b->dpart = (double*)(b->ws + b->B.part);
   b->hdesc.resize(count);
   b->unstable.assign(count, 0);
+  b->dropped.assign(count, 0);
   auto cleanup = [&](lb_status e) { delete b; return e; };
   for (int i = 0; i < count; ++i) {
     Inst& I = b->inst[i];
@@ -540,6 +542,23 @@ lb_status lb_batch_step_subset(lb_batch* b, int64_t nsteps, const int32_t* mask)
   if (r != LB_OK) return r;
   for (int i = 0; i < b->count; ++i)
     if (mask[i]) b->inst[i].moments_valid = true;
+  return LB_OK;
+}
+
+lb_status lb_batch_drop_unstable(lb_batch* b, int32_t* dropped) {
+  if (!b) return fail(LB_EINVAL, "batch is NULL");
+  lb_status r = read_batch_status(b);
+  if (r != LB_OK) return r;
+  int n = 0;
+  for (int i = 0; i < b->count; ++i) {
+    if (b->unstable[i] && !b->dropped[i]) b->dropped[i] = 1;
+    n += b->dropped[i];
+  }
+  if (n == b->count) return fail(LB_ESTATE, "every instance is unstable");
+  b->unstable_any = false;
+  // rebuild the tile table without the dropped instances (drops the graphs)
+  if ((r = batch_tiles(b, b->threads, b->rows)) != LB_OK) return r;
+  if (dropped) *dropped = n;
   return LB_OK;
 }
 

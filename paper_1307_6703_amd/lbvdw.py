@@ -64,6 +64,7 @@ SIGNATURES = {
     "lb_batch_get_moments": (ctypes.c_int, [_VP, ctypes.c_int32, _DP, _DP, _DP]),
     "lb_batch_reduce": (ctypes.c_int, [_VP, ctypes.c_int32, _DP]),
     "lb_batch_status": (ctypes.c_int, [_VP, _I32P]),
+    "lb_batch_drop_unstable": (ctypes.c_int, [_VP, _I32P]),
     "lb_batch_destroy": (ctypes.c_int, [_VP]),
     "lb_set_launch": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "lb_get_launch": (ctypes.c_int, [_VP, _I32P, _I32P, _I32P]),
@@ -342,6 +343,13 @@ class Batch:
 
     def set_launch(self, threads: int = 0, rows: int = 0):
         _check(_lib.lb_batch_set_launch(self._h, int(threads), int(rows)))
+
+    def drop_unstable(self) -> int:
+        """Take instances that failed a check out of the steps; returns how
+        many have been dropped so far."""
+        n = ctypes.c_int32()
+        _check(_lib.lb_batch_drop_unstable(self._h, ctypes.byref(n)))
+        return n.value
 
     def _mask(self, mask):
         m = np.ascontiguousarray(np.asarray(mask, dtype=np.int32).reshape(-1))

@@ -99,6 +99,18 @@ def test_batch_reports_unstable_instances(torch_cuda):
     assert st[0] == lbvdw.LB_OK and st[1] == lbvdw.LB_EUNSTABLE
     with pytest.raises(LBError):
         b.step(1)
+    # dropping the unstable instance lets the other one go on, unchanged by
+    # its neighbour: it equals a batch that never held the unstable one
+    assert b.drop_unstable() == 1
+    b.step(200)
+    assert b.status() == [lbvdw.LB_OK, lbvdw.LB_EUNSTABLE]
+    c = Batch([good], fp32=True, check_every=10)
+    c.init(0, ls.noisy_density(40, 20, 1))
+    c.step(500)
+    for u, v in zip(b.moments(0), c.moments(0)):
+        assert np.array_equal(u, v)
+    with pytest.raises(LBError):
+        b.moments(1)
 
 
 def test_batch_autotune_keeps_results(torch_cuda):

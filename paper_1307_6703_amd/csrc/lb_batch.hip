@@ -25,25 +25,32 @@ struct Inst {
 
 // Shared part of the batch workspace.
 struct BatchLayout {
-  size_t descs, reds, tiles, sub_tiles, part, inst0, total;
+  size_t descs, reds, tiles, sub_tiles, part, part_off, list_all, list_sub, inst0, total;
   int max_tiles;
+  std::vector<int64_t> off;  // partial-sum block offset of each instance
 };
 
 BatchLayout batch_layout(int count, const lb_params* p, std::vector<Inst>* insts) {
   BatchLayout B;
-  int max_tiles = 0, max_red = 1;
+  int max_tiles = 0;
+  int64_t sum_red = 0;
+  B.off.resize(count);
   for (int i = 0; i < count; ++i) {
     const int strips = (p[i].Lx + 57) / 58;
     const int chunks = (p[i].Ly + 7) / 8;
     max_tiles += strips * chunks;
-    max_red = std::max(max_red, lbk::reduce_blocks((int64_t)p[i].Lx * p[i].Ly));
+    B.off[i] = sum_red;
+    sum_red += lbk::reduce_blocks((int64_t)p[i].Lx * p[i].Ly);
   }
   size_t o = 0;
   B.descs = o; o = align_up(o + sizeof(Desc) * count);
   B.reds = o; o = align_up(o + sizeof(ReduceOut) * count);
   B.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)max_tiles);
   B.sub_tiles = o; o = align_up(o + sizeof(Tile) * (size_t)max_tiles);
-  B.part = o; o = align_up(o + sizeof(double) * 6 * (size_t)max_red);
+  B.part = o; o = align_up(o + sizeof(double) * 6 * (size_t)sum_red);
+  B.part_off = o; o = align_up(o + sizeof(int64_t) * count);
+  B.list_all = o; o = align_up(o + sizeof(int32_t) * count);
+  B.list_sub = o; o = align_up(o + sizeof(int32_t) * count);
   B.inst0 = o;
   for (int i = 0; i < count; ++i) {
     Layout L = layout_for(&p[i], o);
@@ -83,6 +90,12 @@ struct lb_batch {
   bool unstable_any = false;
   std::vector<int> unstable;
   std::vector<char> dropped;  // instances taken out of the steps (lb_batch_drop_unstable)
+  // batched checks: partial-sum offsets, the list of checked instances (all
+  // live ones, or the last subset), its length and widest reduction
+  int64_t* dpoff = nullptr;
+  int32_t* dlist_all = nullptr;
+  int32_t* dlist_sub = nullptr;
+  int n_all = 0, nb_all = 1, n_sub = 0, nb_sub = 1;
   // graphs of kGraphSteps steps, keyed by the pending-shift state at entry;
   // recorded on a private stream (the caller's may be the null stream, which
   // cannot be captured) and replayed on the caller's
@@ -103,6 +116,26 @@ void drop_graphs(lb_batch* b) {
     }
 }
 
+// Upload the instances with mask[i] != 0 (all when mask is NULL) that have a
+// state and are not dropped as a check list; returns its length and the
+// widest reduction among them.
+lb_status upload_list(lb_batch* b, const int32_t* mask, int32_t* dlist, int* n, int* nb) {
+  std::vector<int32_t> l;
+  int w = 1;
+  for (int i = 0; i < b->count; ++i)
+    if ((!mask || mask[i]) && b->inst[i].has_state && !b->dropped[i]) {
+      l.push_back(i);
+      w = std::max(w, lbk::reduce_blocks(inst_nodes(b, i)));
+    }
+  if (!l.empty()) {
+    HIPCHK(hipMemcpyAsync(dlist, l.data(), l.size() * sizeof(int32_t), hipMemcpyHostToDevice, b->st));
+    HIPCHK(hipStreamSynchronize(b->st));  // l is a host temporary
+  }
+  *n = (int)l.size();
+  *nb = w;
+  return LB_OK;
+}
+
 // Tiles of the instances with mask[i] != 0 (all when mask is NULL), largest
 // instances first: the dispatcher hands out tiles in order, so the
 // long-running ones start early.
@@ -119,6 +152,26 @@ std::vector<Tile> tile_list(const lb_batch* b, int threads, int rows, const int3
     all.insert(all.end(), t.begin(), t.end());
   }
   return all;
+}
+
+// Default launch shape of a batch: 128-thread strips (64 when every instance
+// is that narrow), which measured fastest for batches of many small lattices
+// (many short tiles keep more workgroups in flight than wide strips), and a
+// chunk height that makes the tiles of all instances fill the resident
+// workgroups about once. lb_batch_autotune refines it.
+void default_batch_launch(const lb_batch* b, int* threads, int* rows) {
+  int t = 64;
+  for (int i = 0; i < b->count; ++i)
+    if (b->inst[i].p.Lx + 6 > 64) t = 128;
+  int64_t strip_rows = 0;
+  for (int i = 0; i < b->count; ++i)
+    strip_rows += (int64_t)((b->inst[i].p.Lx + t - 7) / (t - 6)) * b->inst[i].p.Ly;
+  const int slots = resident_slots(&b->inst[0].p, t);
+  const int64_t want = (strip_rows + slots - 1) / std::max(slots, 1);
+  int r = (int)std::min<int64_t>(std::max<int64_t>(want, 10), 1 << 20);
+  r = ((r - 2 + 7) / 8) * 8 + 2;
+  *threads = t;
+  *rows = r;
 }
 
 lb_status batch_tiles(lb_batch* b, int threads, int rows) {
@@ -138,6 +191,14 @@ lb_status batch_tiles(lb_batch* b, int threads, int rows) {
 }
 
 lb_status enqueue_checks(lb_batch* b, int mode, int only = -1, const int32_t* mask = nullptr) {
+  if (mode == 0 && only < 0) {
+    // periodic check of all live instances, or of the subset last uploaded
+    const bool sub = mask != nullptr;
+    HIPCHK(lbk::launch_check_batch(b->fp32, b->ddesc, b->parity, sub ? b->dlist_sub : b->dlist_all,
+                                   sub ? b->n_sub : b->n_all, sub ? b->nb_sub : b->nb_all, b->dpoff,
+                                   b->dpart, b->dred, b->drift, b->st));
+    return LB_OK;
+  }
   for (int i = 0; i < b->count; ++i) {
     if (only >= 0 && i != only) continue;
     if (mask && !mask[i]) continue;
@@ -272,6 +333,9 @@ lb_status lb_batch_create(int32_t count, const lb_params* p, void* dev_ws, size_
   b->dtiles = (Tile*)(b->ws + b->B.tiles);
   b->dsub = (Tile*)(b->ws + b->B.sub_tiles);
   b->dpart = (double*)(b->ws + b->B.part);
+  b->dpoff = (int64_t*)(b->ws + b->B.part_off);
+  b->dlist_all = (int32_t*)(b->ws + b->B.list_all);
+  b->dlist_sub = (int32_t*)(b->ws + b->B.list_sub);
   b->hdesc.resize(count);
   b->unstable.assign(count, 0);
   b->dropped.assign(count, 0);
@@ -314,11 +378,14 @@ lb_status lb_batch_create(int32_t count, const lb_params* p, void* dev_ws, size_
   }
   std::vector<ReduceOut> z(count);
   std::memset(z.data(), 0, sizeof(ReduceOut) * count);
-  if (hipMemcpyAsync(b->dred, z.data(), sizeof(ReduceOut) * count, hipMemcpyHostToDevice, b->st) != hipSuccess ||
+  if (hipMemcpyAsync(b->dpoff, b->B.off.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice, b->st) != hipSuccess ||
+      hipMemcpyAsync(b->dred, z.data(), sizeof(ReduceOut) * count, hipMemcpyHostToDevice, b->st) != hipSuccess ||
       hipMemcpyAsync(b->ddesc, b->hdesc.data(), sizeof(Desc) * count, hipMemcpyHostToDevice, b->st) != hipSuccess ||
       hipStreamSynchronize(b->st) != hipSuccess)
     return cleanup(fail(LB_EDEVICE, "uploading descriptors failed"));
-  lb_status r = batch_tiles(b, b->fp32 ? 256 : 128, 64);
+  int dt = 0, dr = 0;
+  default_batch_launch(b, &dt, &dr);
+  lb_status r = batch_tiles(b, dt, dr);
   if (r != LB_OK) return cleanup(r);
   *out = b;
   return LB_OK;
@@ -348,7 +415,9 @@ lb_status lb_batch_init(lb_batch* b, int32_t idx, const double* n0, const double
   HIPCHK(lbk::launch_init(b->fp32, b->ddesc + idx, 0, mom, ux0 ? mom + nn : nullptr,
                           uy0 ? mom + 2 * nn : nullptr, nn, b->st));
   I.has_state = true;
-  lb_status r = enqueue_checks(b, 1, idx);
+  lb_status r = upload_list(b, nullptr, b->dlist_all, &b->n_all, &b->nb_all);
+  if (r != LB_OK) return r;
+  r = enqueue_checks(b, 1, idx);
   if (r != LB_OK) return r;
   if ((r = read_batch_status(b)) != LB_OK) return r;
   if (b->unstable[idx]) return fail(LB_EUNSTABLE, "initial state of instance %d is invalid", idx);
@@ -427,8 +496,10 @@ lb_status lb_batch_status(lb_batch* b, int32_t* per_instance) {
 
 lb_status lb_batch_set_launch(lb_batch* b, int32_t threads, int32_t rows) {
   if (!b) return fail(LB_EINVAL, "batch is NULL");
-  if (threads == 0) threads = b->fp32 ? 256 : 128;
-  if (rows == 0) rows = 64;
+  int dt = 0, dr = 0;
+  default_batch_launch(b, &dt, &dr);
+  if (threads == 0) threads = dt;
+  if (rows == 0) rows = dr;
   return batch_tiles(b, threads, rows);
 }
 
@@ -533,6 +604,8 @@ lb_status lb_batch_step_subset(lb_batch* b, int64_t nsteps, const int32_t* mask)
   std::vector<Tile> t = tile_list(b, b->threads, b->rows, mask);
   HIPCHK(hipMemcpyAsync(b->dsub, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice, b->st));
   HIPCHK(hipStreamSynchronize(b->st));  // t is a host temporary
+  lb_status lr = upload_list(b, mask, b->dlist_sub, &b->n_sub, &b->nb_sub);
+  if (lr != LB_OK) return lr;
   for (int64_t s = 0; s < nsteps; ++s) {
     const int flags = (s == nsteps - 1) ? lbk::kWriteMoments : 0;
     HIPCHK(lbk::launch_step(b->fp32, b->threads, b->ddesc, b->dsub, (int)t.size(), b->parity ^ (int)(s & 1),
@@ -556,6 +629,7 @@ lb_status lb_batch_drop_unstable(lb_batch* b, int32_t* dropped) {
   }
   if (n == b->count) return fail(LB_ESTATE, "every instance is unstable");
   b->unstable_any = false;
+  if ((r = upload_list(b, nullptr, b->dlist_all, &b->n_all, &b->nb_all)) != LB_OK) return r;
   // rebuild the tile table without the dropped instances (drops the graphs)
   if ((r = batch_tiles(b, b->threads, b->rows)) != LB_OK) return r;
   if (dropped) *dropped = n;

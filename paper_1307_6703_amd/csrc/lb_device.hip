@@ -611,12 +611,14 @@ hipError_t launch_init(bool fp32, const Desc* d_desc, int parity, const double* 
 constexpr int kRedBS = 256;
 constexpr int kRedMaxBlocks = 1024;
 
-int reduce_blocks(int64_t nn) {
+__host__ __device__ inline int reduce_blocks_hd(int64_t nn) {
   int64_t g = (nn + kRedBS * 8 - 1) / (kRedBS * 8);
   if (g < 1) g = 1;
   if (g > kRedMaxBlocks) g = kRedMaxBlocks;
   return (int)g;
 }
+
+int reduce_blocks(int64_t nn) { return reduce_blocks_hd(nn); }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -634,18 +636,17 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Partial sums of workgroup blk of nblk over the nodes of one lattice.
 template <typename R>
-__global__ __launch_bounds__(kRedBS) void reduce_kernel(const Desc* __restrict__ desc, int parity,
-                                                        int64_t nn, double* __restrict__ part,
-                                                        int add_shift) {
-  const Desc& d = *desc;
+__device__ __forceinline__ void reduce_partial(const Desc& d, int parity, int64_t nn, int blk,
+                                               int nblk, int add_shift, double* __restrict__ part) {
   const R* S = (const R*)d.S[parity];
   double m = 0, jx = 0, jy = 0, mn = 1e300, mx = -1e300, bad = 0;
   const double base = d.nbar + ((add_shift && d.shift) ? *d.shift : 0.0);
   double wr[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) wr[i] = rest_weight_hd(i, d.T) * base;
-  for (int64_t k = blockIdx.x * (int64_t)kRedBS + threadIdx.x; k < nn; k += (int64_t)gridDim.x * kRedBS) {
+  for (int64_t k = blk * (int64_t)kRedBS + threadIdx.x; k < nn; k += (int64_t)nblk * kRedBS) {
     double rho = 0, px = 0, py = 0;
     const int64_t y = k / d.Lx;
 #pragma unroll
@@ -679,9 +680,33 @@ __global__ __launch_bounds__(kRedBS) void reduce_kernel(const Desc* __restrict__
       a0 += red[0][w]; a1 += red[1][w]; a2 += red[2][w];
       a3 = fmin(a3, red[3][w]); a4 = fmax(a4, red[4][w]); a5 += red[5][w];
     }
-    double* o = part + blockIdx.x * 6;
+    double* o = part + blk * 6;
     o[0] = a0; o[1] = a1; o[2] = a2; o[3] = a3; o[4] = a4; o[5] = a5;
   }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kRedBS) void reduce_kernel(const Desc* __restrict__ desc, int parity,
+                                                        int64_t nn, double* __restrict__ part,
+                                                        int add_shift) {
+  reduce_partial<R>(*desc, parity, nn, blockIdx.x, gridDim.x, add_shift, part);
+}
+
+// The same for the lattices list[0 .. gridDim.y): workgroup (b, j) computes
+// partial b of lattice list[j] into part + 6 part_off[list[j]] (the grid is
+// as wide as the largest lattice needs; the others exit early).
+template <typename R>
+__global__ __launch_bounds__(kRedBS) void reduce_batch_kernel(const Desc* __restrict__ descs,
+                                                              int parity,
+                                                              const int32_t* __restrict__ list,
+                                                              const int64_t* __restrict__ part_off,
+                                                              double* __restrict__ part) {
+  const int i = list[blockIdx.y];
+  const Desc& d = descs[i];
+  const int64_t nn = (int64_t)d.Lx * d.Ly;
+  const int nb = reduce_blocks_hd(nn);
+  if ((int)blockIdx.x >= nb) return;  // uniform per workgroup
+  reduce_partial<R>(d, parity, nn, blockIdx.x, nb, 0, part + 6 * part_off[i]);
 }
 
 hipError_t launch_reduce(bool fp32, const Desc* d_desc, int parity, int64_t nn, double* d_part,
@@ -701,9 +726,9 @@ hipError_t launch_reduce(bool fp32, const Desc* d_desc, int parity, int64_t nn, 
 // wavefront and workgroup reductions run in a fixed tree. mode 0: check
 // (update the sticky status and the drift shift); 1: set the reference
 // mass; 2: report only.
-__global__ __launch_bounds__(256) void reduce_final_kernel(const double* __restrict__ part, int nb,
-                                                           int64_t nn, ReduceOut* __restrict__ out,
-                                                           int mode, int drift) {
+__device__ __forceinline__ void reduce_final_body(const double* __restrict__ part, int nb,
+                                                  int64_t nn, ReduceOut* __restrict__ out,
+                                                  int mode, int drift) {
   double m = 0, jx = 0, jy = 0, mn = 1e300, mx = -1e300, bad = 0;
   for (int b = threadIdx.x; b < nb; b += 256) {
     const double* q = part + 6 * b;
@@ -736,6 +761,37 @@ __global__ __launch_bounds__(256) void reduce_final_kernel(const double* __restr
     if (fail) out->status |= 1u;
     out->shift = (drift && out->has_ref && !fail) ? (out->mass_ref - m) / (double)nn : 0.0;
   }
+}
+
+__global__ __launch_bounds__(256) void reduce_final_kernel(const double* __restrict__ part, int nb,
+                                                           int64_t nn, ReduceOut* __restrict__ out,
+                                                           int mode, int drift) {
+  reduce_final_body(part, nb, nn, out, mode, drift);
+}
+
+// One workgroup per lattice of the list (the periodic check, mode 0).
+__global__ __launch_bounds__(256) void reduce_final_batch_kernel(
+    const Desc* __restrict__ descs, const int32_t* __restrict__ list,
+    const int64_t* __restrict__ part_off, const double* __restrict__ part,
+    ReduceOut* __restrict__ reds, int drift) {
+  const int i = list[blockIdx.x];
+  const int64_t nn = (int64_t)descs[i].Lx * descs[i].Ly;
+  reduce_final_body(part + 6 * part_off[i], reduce_blocks_hd(nn), nn, reds + i, 0, drift);
+}
+
+hipError_t launch_check_batch(bool fp32, const Desc* d_descs, int parity, const int32_t* d_list,
+                              int n, int max_blocks, const int64_t* d_part_off, double* d_part,
+                              ReduceOut* d_reds, int drift, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(reduce_batch_kernel<float>, dim3(max_blocks, n), dim3(kRedBS), 0, st, d_descs,
+                       parity, d_list, d_part_off, d_part);
+  else
+    hipLaunchKernelGGL(reduce_batch_kernel<double>, dim3(max_blocks, n), dim3(kRedBS), 0, st, d_descs,
+                       parity, d_list, d_part_off, d_part);
+  hipLaunchKernelGGL(reduce_final_batch_kernel, dim3(n), dim3(256), 0, st, d_descs, d_list,
+                     d_part_off, d_part, d_reds, drift);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_final(const double* d_part, int nb, int64_t nn, ReduceOut* d_out,

@@ -50,6 +50,13 @@ hipError_t launch_reduce(bool fp32, const Desc* d_desc, int parity, int64_t nn, 
                          int add_shift, hipStream_t stream);
 // Fixed-order final reduction of `nb` partials; mode: 0 check (sticky status,
 // drift shift), 1 set the reference mass, 2 report only.
+// The periodic check (mode 0) of the lattices d_list[0 .. n) of a batch in two
+// launches; partials of lattice i at d_part + 6 d_part_off[i]; max_blocks =
+// the largest reduce_blocks of the listed lattices. Same bits as checking
+// them one by one.
+hipError_t launch_check_batch(bool fp32, const Desc* d_descs, int parity, const int32_t* d_list,
+                              int n, int max_blocks, const int64_t* d_part_off, double* d_part,
+                              ReduceOut* d_reds, int drift, hipStream_t st);
 hipError_t launch_reduce_final(const double* d_part, int nb, int64_t nn, ReduceOut* d_out,
                                int mode, int drift, hipStream_t stream);
 // Full FP64 populations planes [p0, p1) of S[parity] into d_f (plane-major),

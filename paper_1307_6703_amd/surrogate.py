@@ -389,6 +389,17 @@ def train(net: Net, x, tgt, iters: int, batch: int = 16, lr: float = 1e-3, seed:
     return hist
 
 
+def dataset_loss(net: Net, x, tgt, batch: int) -> float:
+    """Mean loss of the network over every sample of (x, tgt), in minibatches
+    of at most `batch` (forward passes only)."""
+    n, tot = x.shape[0], 0.0
+    for s in range(0, n, batch):
+        e = min(n, s + batch)
+        loss, _ = mse(net.forward(x[s:e]), tgt[s:e])
+        tot += float(loss.item()) * (e - s)
+    return tot / n
+
+
 @dataclass
 class RunStats:
     chunks: int = 0
@@ -515,16 +526,20 @@ def experiment(H: int = 128, W: int = 256, train_count: int = 256, train_seed: i
     say(f"data: {x.shape[0]} samples in {time.perf_counter() - t0:.1f} s")
     net_t = Net(batch, H, W, train=True)
     net_t.set_params(init_params(0))
+    loss0 = dataset_loss(net_t, x, tgt, batch)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     hist = train(net_t, x, tgt, iters, batch, lr, log_every=200, time_limit=train_seconds)
     t_train = time.perf_counter() - t1
     its = hist[-1][0] + 1
-    tail = [l for _, l in hist[-10:]]
+    loss1 = dataset_loss(net_t, x, tgt, batch)
     out["train"] = {"iterations": its, "batch": batch, "seconds": round(t_train, 1),
-                    "loss_first": hist[0][1], "loss_last10_mean": float(np.mean(tail)),
+                    "dataset_loss_before": loss0, "dataset_loss_after": loss1,
+                    "minibatch_loss_curve": [(it, round(l, 7))
+                                             for it, l in hist[:: max(1, len(hist) // 20)]],
                     "train_tflops": round(3 * FLOPS_PER_NODE * H * W * batch * its / t_train / 1e12, 1)}
-    say(f"train: {its} iterations in {t_train:.1f} s, loss {hist[0][1]:.3e} -> {np.mean(tail):.3e}")
+    say(f"train: {its} iterations in {t_train:.1f} s, loss over the {x.shape[0]} samples "
+        f"{loss0:.3e} -> {loss1:.3e}")
     params = net_t.params().clone()
     net_t.close()
     del x, tgt, net_t

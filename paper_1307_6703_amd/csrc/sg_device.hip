@@ -510,13 +510,16 @@ __global__ void mse_kernel(const float* __restrict__ pred, const float* __restri
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// One wave: lane l adds part[l], part[l + 64], ... in order, then the 64 lane
+// sums are added pairwise in a fixed tree, so the result does not vary from
+// run to run.
 __global__ void sum_partials_kernel(const double* __restrict__ part, int n, double scale,
                                     double* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = s * scale;
-  }
+  const int l = threadIdx.x;
+  double s = 0.0;
+  for (int i = l; i < n; i += 64) s += part[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (l == 0) *out = s * scale;
 }
 
 hipError_t launch_mse(const float* pred, const float* target, int64_t npix, int nout, int CO,

@@ -8,6 +8,13 @@ drift correction every 100 steps. One step = one full time step of the lattice
 (stream, density, stencils, force, walls, collision, store) plus its share of
 the checks.
 
+The default launch runs two steps per launch (the two-step kernel keeps the
+first step's populations on chip). The roofline counts 72 algorithmic bytes
+per node update (nine populations read and written in FP32), times the
+updates of one launch, over the launch's duration; with two steps per launch
+the populations cross HBM once per two updates, so that figure is an
+effective rate and hbm_gbs_min the rate of the bytes that must cross HBM.
+
 Prints one JSON line: MLUPS (million lattice-node updates per second), the
 roofline of the step kernel against the HBM peak, and the FP64 CPU oracle
 timed on the host cores on a bounded sample of the same workload.
@@ -41,14 +48,15 @@ def tuned_launch(key: str):
         return None
 
 
-def measured_traffic(nodes: int):
+def measured_traffic(nodes: int, steps_per_launch: int):
     """HBM bytes per launch from committed rocprofv3 counters, if they were
-    taken on the current kernel source."""
+    taken on the current kernel source for the kernel that runs."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256") != kernel_hash() or t.get("nodes") != nodes:
+    if (t.get("kernel_source_sha256") != kernel_hash() or t.get("nodes") != nodes
+            or t.get("steps_per_launch", 1) != steps_per_launch):
         return None
     return t.get("traffic_bytes_per_launch")
 
@@ -123,7 +131,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--launch", default=None, help="threads,rows of the step kernel")
+    ap.add_argument("--launch", default=None,
+                    help="threads,rows[,steps per launch] of the step kernel (steps 2: the "
+                         "two-step kernel)")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape first")
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -171,15 +181,15 @@ def main():
     lat.init(n0)
     key = f"{w.Lx}x{w.Ly}-fp32-gfx950"
     if args.launch:
-        th, rw = (int(v) for v in args.launch.split(","))
-        lat.set_launch(th, rw)
+        lat.set_launch(*(int(v) for v in args.launch.split(",")))
     elif args.autotune:
         lat.autotune(nsteps=10)
     elif tuned_launch(key):
         lat.set_launch(*tuned_launch(key))
     threads, rows, blocks = lat.get_launch()
+    spl = lat.steps_per_launch()
     print(f"[bench] {w.name}: {w.nodes} nodes, launch {threads} threads x {rows} rows, "
-          f"{blocks} workgroups", file=sys.stderr, flush=True)
+          f"{blocks} workgroups, {spl} step(s) per launch", file=sys.stderr, flush=True)
 
     m0 = lat.reduce()["mass"]
     lat.step(args.warmup)
@@ -201,18 +211,19 @@ def main():
 
     # the step kernel alone (checks off), same stream, for the roofline
     lat.set_checks(0, False)
-    k_steps = max(50, args.steps // 2)
+    k_steps = max(50, args.steps // 2) // spl * spl
     e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e2.record()
     lat.step(k_steps)
     e3.record()
     torch.cuda.synchronize()
-    k_ms = e2.elapsed_time(e3) / k_steps
-    alg_bytes = BYTES_PER_UPDATE_FP32 * w.nodes
+    k_ms = e2.elapsed_time(e3) / (k_steps // spl)  # per launch
+    # algorithmic bytes: 72 B per node update, times the updates of a launch
+    alg_bytes = BYTES_PER_UPDATE_FP32 * w.nodes * spl
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    print(f"[bench] step kernel {k_ms * 1e3:.1f} us/launch, {achieved:.0f} GB/s algorithmic",
-          file=sys.stderr, flush=True)
+    print(f"[bench] step kernel {k_ms * 1e3:.1f} us/launch ({spl} step(s)), {achieved:.0f} GB/s "
+          f"algorithmic", file=sys.stderr, flush=True)
 
     # the same bytes moved by a plain device copy: the streaming rate this
     # GPU reaches in practice (read + write), for context beside the peak
@@ -245,13 +256,19 @@ def main():
                    "T": w.T, "tau": w.tau, "kappa": w.kappa, "N": w.N, "Q": w.Q, "U": w.U,
                    "V0": w.V0, "stripes": w.k, "seed": w.seed, "storage": "fp32-deviation",
                    "checks": f"fp64 every {args.check_every} steps + drift correction",
-                   "launch": {"threads": threads, "rows": rows, "workgroups": blocks}},
+                   "launch": {"threads": threads, "rows": rows, "workgroups": blocks,
+                              "steps_per_launch": spl}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(w.nodes),
-                     "kernel": "step_kernel<float,%d>" % threads,
+                     "traffic": measured_traffic(w.nodes, spl),
+                     "kernel": ("step2_kernel<%d>" if spl == 2 else "step_kernel<float,%d>") % threads,
                      "us_per_launch": round(k_ms * 1e3, 2),
+                     "node_updates_per_launch": w.nodes * spl,
                      "algorithmic_bytes_per_launch": alg_bytes,
+                     # the bytes a launch must move through HBM: each population
+                     # is read and written once per launch, whatever its steps
+                     "hbm_bytes_per_launch_min": BYTES_PER_UPDATE_FP32 * w.nodes,
+                     "hbm_gbs_min": round(BYTES_PER_UPDATE_FP32 * w.nodes / (k_ms * 1e-3) / 1e9, 1),
                      "copy_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
         "hbm_frac_of_peak": round(mlups * 1e6 * BYTES_PER_UPDATE_FP32 / 1e9 / HBM_PEAK_GBS, 4),

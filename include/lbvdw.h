@@ -209,11 +209,26 @@ lb_status lb_set_launch(lb_handle* h, int32_t threads, int32_t rows);
 lb_status lb_get_launch(lb_handle* h, int32_t* threads, int32_t* rows, int32_t* blocks);
 lb_status lb_batch_set_launch(lb_batch* b, int32_t threads, int32_t rows);
 
-/* Time nsteps steps of each candidate launch shape, pick the fastest and
- * apply it; return it (ms_per_step may be NULL). The timed steps are real
- * steps: the lattice advances by (number of candidates) * nsteps steps. The
- * launch shape never changes results (every node runs the same arithmetic
- * on the same inputs whatever the tiling). Synchronises. */
+/* Two time steps per launch (FP32 populations only; LB_EINVAL otherwise).
+ * A workgroup of threads (128, 192 or 256; 0: 128) runs the step of
+ * Eq.(evoleq) twice over a strip of threads - 14 columns and a y-chunk of
+ * rows (0: a default height), keeping the first step's populations in LDS,
+ * so the populations cross HBM once per two steps. Every node runs the same
+ * arithmetic as with one step per launch, so results are the same bits.
+ * Pairs of steps never straddle a check (check_every): a step before a
+ * check, and the last of an odd count, runs alone in the default one-step
+ * shape. lb_set_launch returns to one step per launch. Applies to the next
+ * step. lb_get_steps_per_launch reports 1 or 2 for the current shape. */
+lb_status lb_set_launch_fused(lb_handle* h, int32_t threads, int32_t rows);
+lb_status lb_get_steps_per_launch(lb_handle* h, int32_t* steps);
+
+/* Time nsteps steps of each candidate launch shape (one step per launch
+ * and, with FP32 populations, two), pick the fastest and apply it; return
+ * it (ms_per_step may be NULL; lb_get_steps_per_launch tells which kernel
+ * won). The timed steps are real steps: the lattice advances by nsteps plus
+ * one or two warm-up steps per candidate. The launch shape never changes
+ * results (every node runs the same arithmetic on the same inputs whatever
+ * the tiling). Synchronises. */
 lb_status lb_autotune(lb_handle* h, int32_t nsteps, int32_t* threads, int32_t* rows,
                       double* ms_per_step);
 

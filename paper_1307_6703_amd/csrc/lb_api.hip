@@ -23,7 +23,8 @@ struct lb_handle {
   Desc hdesc{};  // host mirror of the device descriptor
   Desc* ddesc = nullptr;
   ReduceOut* dred = nullptr;
-  Tile* dtiles = nullptr;
+  Tile* dtiles = nullptr;   // tiles of the current launch shape
+  Tile* dtiles1 = nullptr;  // one-step tiles for single steps of a two-step shape
   double* dpart = nullptr;
   double* dmom = nullptr;
   double* dstage = nullptr;
@@ -34,6 +35,8 @@ struct lb_handle {
   bool unstable = false;
   bool pending_shift = false;
   int threads = 128, rows = 16, ntiles = 0;
+  int fuse = 1;  // steps per launch of the current shape
+  int threads1 = 128, ntiles1 = 0;
 };
 
 namespace {
@@ -47,19 +50,40 @@ lb_status upload_desc(lb_handle* h) {
   return LB_OK;
 }
 
-lb_status set_tiles(lb_handle* h, int threads, int rows) {
-  if (threads != 64 && threads != 128 && threads != 256 && threads != 320 &&
-      !(threads == 512 && h->p.fp32))
+// Upload the tiles of a shape; fuse = steps per launch (1 or 2).
+lb_status upload_tiles(lb_handle* h, Tile* dst, int threads, int rows, int fuse, int* ntiles) {
+  std::vector<Tile> t = make_tiles(0, h->p.Lx, h->p.Ly, threads, rows, fuse == 2 ? 7 : 3);
+  if ((int)t.size() > h->L.max_tiles) return fail(LB_EINVAL, "too many tiles for the workspace");
+  HIPCHK(hipMemcpyAsync(dst, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  *ntiles = (int)t.size();
+  return LB_OK;
+}
+
+lb_status set_tiles(lb_handle* h, int threads, int rows, int fuse = 1) {
+  if (fuse == 2) {
+    if (!h->p.fp32) return fail(LB_EINVAL, "two steps per launch need FP32 storage");
+    if (!fused_threads_ok(threads))
+      return fail(LB_EINVAL, "two steps per launch: threads must be 128, 192 or 256 (got %d)", threads);
+  } else if (threads != 64 && threads != 128 && threads != 256 && threads != 320 &&
+             !(threads == 512 && h->p.fp32)) {
     return fail(LB_EINVAL, "threads must be 64, 128, 256, 320 or 512 (FP32 only) (got %d)", threads);
+  }
   if (rows < 1) return fail(LB_EINVAL, "rows must be >= 1");
   rows = std::max(std::min(rows, h->p.Ly), std::min(kMinRows, h->p.Ly));
-  std::vector<Tile> t = make_tiles(0, h->p.Lx, h->p.Ly, threads, rows);
-  if ((int)t.size() > h->L.max_tiles) return fail(LB_EINVAL, "too many tiles for the workspace");
-  HIPCHK(hipMemcpyAsync(h->dtiles, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice, h->st));
-  HIPCHK(hipStreamSynchronize(h->st));
+  int nt = 0;
+  lb_status r = upload_tiles(h, h->dtiles, threads, rows, fuse, &nt);
+  if (r != LB_OK) return r;
+  if (fuse == 2) {  // single steps (odd counts, steps before a check) use the default shape
+    const int t1 = default_threads(&h->p);
+    if ((r = upload_tiles(h, h->dtiles1, t1, default_rows(&h->p, t1), 1, &h->ntiles1)) != LB_OK)
+      return r;
+    h->threads1 = t1;
+  }
   h->threads = threads;
   h->rows = rows;
-  h->ntiles = (int)t.size();
+  h->ntiles = nt;
+  h->fuse = fuse;
   return LB_OK;
 }
 
@@ -94,16 +118,28 @@ lb_status after_restart(lb_handle* h) {
   return LB_OK;
 }
 
+// With a two-step shape, pairs of steps run as one launch unless a check
+// falls after the first of them or one step is left; those run alone.
 lb_status step_impl(lb_handle* h, int64_t nsteps, bool moments_last) {
-  for (int64_t s = 0; s < nsteps; ++s) {
+  const int ce = h->p.check_every;
+  for (int64_t s = 0; s < nsteps;) {
+    const bool pair = h->fuse == 2 && nsteps - s >= 2 && !(ce > 0 && (h->step + 1) % ce == 0);
+    const int n = pair ? 2 : 1;
     int flags = 0;
-    if (moments_last && s == nsteps - 1) flags |= lbk::kWriteMoments;
+    if (moments_last && s + n == nsteps) flags |= lbk::kWriteMoments;
     if (h->pending_shift) flags |= lbk::kApplyShift;
-    HIPCHK(lbk::launch_step(fp32_of(h), h->threads, h->ddesc, h->dtiles, h->ntiles, h->parity,
-                            flags, h->st));
+    if (pair)
+      HIPCHK(lbk::launch_step2(h->threads, h->ddesc, h->dtiles, h->ntiles, h->parity, flags, h->st));
+    else if (h->fuse == 2)
+      HIPCHK(lbk::launch_step(fp32_of(h), h->threads1, h->ddesc, h->dtiles1, h->ntiles1, h->parity,
+                              flags, h->st));
+    else
+      HIPCHK(lbk::launch_step(fp32_of(h), h->threads, h->ddesc, h->dtiles, h->ntiles, h->parity,
+                              flags, h->st));
     h->pending_shift = false;
     h->parity ^= 1;
-    h->step += 1;
+    h->step += n;
+    s += n;
     if (h->p.check_every > 0 && h->step % h->p.check_every == 0) {
       lb_status r = enqueue_check(h, 0);
       if (r != LB_OK) return r;
@@ -150,6 +186,7 @@ lb_status lb_create(const lb_params* p, void* dev_ws, size_t ws_bytes, void* hip
   h->ddesc = (Desc*)(h->ws + L.desc);
   h->dred = (ReduceOut*)(h->ws + L.red);
   h->dtiles = (Tile*)(h->ws + L.tiles);
+  h->dtiles1 = (Tile*)(h->ws + L.tiles1);
   h->dpart = (double*)(h->ws + L.part);
   h->dmom = (double*)(h->ws + L.mom);
   h->dstage = (double*)(h->ws + L.stage);
@@ -370,7 +407,20 @@ lb_status lb_set_launch(lb_handle* h, int32_t threads, int32_t rows) {
   if (!h) return fail(LB_EINVAL, "handle is NULL");
   if (threads == 0) threads = default_threads(&h->p);
   if (rows == 0) rows = default_rows(&h->p, threads);
-  return set_tiles(h, threads, rows);
+  return set_tiles(h, threads, rows, 1);
+}
+
+lb_status lb_set_launch_fused(lb_handle* h, int32_t threads, int32_t rows) {
+  if (!h) return fail(LB_EINVAL, "handle is NULL");
+  if (threads == 0) threads = 128;
+  if (rows == 0) rows = fused_default_rows(&h->p, threads);
+  return set_tiles(h, threads, rows, 2);
+}
+
+lb_status lb_get_steps_per_launch(lb_handle* h, int32_t* steps) {
+  if (!h || !steps) return fail(LB_EINVAL, "NULL argument");
+  *steps = h->fuse;
+  return LB_OK;
 }
 
 lb_status lb_get_launch(lb_handle* h, int32_t* threads, int32_t* rows, int32_t* blocks) {
@@ -387,10 +437,14 @@ lb_status lb_autotune(lb_handle* h, int32_t nsteps, int32_t* threads, int32_t* r
   if (nsteps < 1) return fail(LB_EINVAL, "nsteps must be >= 1");
   if (!h->has_state) return fail(LB_ESTATE, "lattice has no state");
   if (h->unstable) return fail(LB_ESTATE, "lattice was flagged unstable");
-  // candidate shapes: strip widths up to one strip per row, and for each the
-  // chunk heights that fill the resident workgroups once or twice, plus a
-  // few fixed heights
-  std::vector<std::pair<int, int>> cand;
+  // candidate shapes (threads, rows, steps per launch): strip widths up to
+  // one strip per row, and for each the chunk heights that fill the resident
+  // workgroups once or twice, plus a few fixed heights; with FP32 storage the
+  // two-step kernel's shapes too
+  struct Cand {
+    int t, rw, fuse;
+  };
+  std::vector<Cand> cand;
   for (int t : {128, 256, 512}) {
     if (t == 512 && !h->p.fp32) continue;
     if (t > 128 && h->p.Lx + 6 <= t / 2) continue;
@@ -398,19 +452,28 @@ lb_status lb_autotune(lb_handle* h, int32_t nsteps, int32_t* threads, int32_t* r
     std::sort(rs.begin(), rs.end());
     rs.erase(std::unique(rs.begin(), rs.end()), rs.end());
     for (int rw : rs)
-      if (rw <= h->p.Ly) cand.push_back({t, rw});
+      if (rw <= h->p.Ly) cand.push_back({t, rw, 1});
   }
+  if (h->p.fp32)
+    for (int t : {128, 192, 256}) {
+      if (t > 128 && h->p.Lx + 14 <= t / 2) continue;
+      std::vector<int> rs = {fused_default_rows(&h->p, t, 1), fused_default_rows(&h->p, t, 2), 33};
+      std::sort(rs.begin(), rs.end());
+      rs.erase(std::unique(rs.begin(), rs.end()), rs.end());
+      for (int rw : rs)
+        if (rw <= h->p.Ly) cand.push_back({t, rw, 2});
+    }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   double best = 1e300;
-  int bt = h->threads, br = h->rows;
+  int bt = h->threads, br = h->rows, bf = h->fuse;
   lb_status r = LB_OK;
   for (const auto& c : cand) {
-    const int t = c.first, rw = c.second;
+    const int t = c.t, rw = c.rw;
     {
-      if ((r = set_tiles(h, t, rw)) != LB_OK) break;
-      if ((r = step_impl(h, 1, false)) != LB_OK) break;  // warm-up
+      if ((r = set_tiles(h, t, rw, c.fuse)) != LB_OK) break;
+      if ((r = step_impl(h, c.fuse, false)) != LB_OK) break;  // warm-up
       if (hipEventRecord(e0, h->st) != hipSuccess) { r = fail(LB_EDEVICE, "event record failed"); break; }
       if ((r = step_impl(h, nsteps, false)) != LB_OK) break;
       if (hipEventRecord(e1, h->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
@@ -420,7 +483,7 @@ lb_status lb_autotune(lb_handle* h, int32_t nsteps, int32_t* threads, int32_t* r
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, e0, e1);
       const double per = ms / nsteps;
-      if (per < best) { best = per; bt = t; br = h->rows; }
+      if (per < best) { best = per; bt = t; br = h->rows; bf = c.fuse; }
     }
     if (r != LB_OK) break;
   }
@@ -428,7 +491,7 @@ lb_status lb_autotune(lb_handle* h, int32_t nsteps, int32_t* threads, int32_t* r
   (void)hipEventDestroy(e1);
   if (r != LB_OK) return r;
   h->moments_valid = false;
-  if ((r = set_tiles(h, bt, br)) != LB_OK) return r;
+  if ((r = set_tiles(h, bt, br, bf)) != LB_OK) return r;
   if (threads) *threads = bt;
   if (rows) *rows = br;
   if (ms_per_step) *ms_per_step = best;

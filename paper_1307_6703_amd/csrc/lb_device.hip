@@ -56,39 +56,31 @@ __device__ __forceinline__ int64_t pidx(int i, int64_t k, int64_t y, int Lx) {
   return k + (8 * y + i) * (int64_t)Lx;
 }
 
+// Per-lattice constants of the stages in the storage precision. The y
+// stencils are taken along the march ("ahead" minus "behind"); Ny and My
+// carry the march direction's sign, so the results are d/dy.
 template <typename R>
-struct Par {
-  R nbar, T, omega, sF, kappa3, third, N, M, Q, Rw, Ub, Ut;
-  R wr0, wra, wrd;  // rest weights: centre, axis, diagonal
-  R shift;
+struct Sten {
+  R nbar, T, kap3, third, N, M, Q, Rw, Q4R, Ny, My, Ub, Ut;
 };
 
 template <typename R>
-__device__ __forceinline__ Par<R> load_par(const Desc& d, int flags) {
-  Par<R> p;
-  p.nbar = (R)d.nbar;
-  p.T = (R)d.T;
-  p.omega = (R)d.omega;
-  p.sF = (R)(1.0 - 0.5 * d.omega);
-  p.kappa3 = (R)d.kappa3;
-  p.third = (R)(1.0 / 3.0);
-  p.N = (R)d.N;
-  p.M = (R)d.M;
-  p.Q = (R)d.Q;
-  p.Rw = (R)d.R;
-  p.Ub = (R)(-d.U);
-  p.Ut = (R)d.U;
-  p.wr0 = (R)(4.0 / 9.0 * (2.0 - d.T));
-  p.wra = (R)((d.T + 1.0) / 18.0);
-  p.wrd = (R)((2.0 * d.T - 1.0) / 36.0);
-  p.shift = (R)0;
-  if ((flags & kApplyShift) && d.shift) p.shift = (R)(*d.shift);
-  return p;
-}
-
-template <typename R>
-__device__ __forceinline__ R restw(const Par<R>& p, int i) {
-  return i == 0 ? p.wr0 : (i <= 4 ? p.wra : p.wrd);
+__device__ __forceinline__ Sten<R> make_sten(const Desc& d, int dir) {
+  Sten<R> c;
+  c.nbar = (R)d.nbar;
+  c.T = (R)d.T;
+  c.kap3 = (R)d.kappa3;
+  c.third = (R)(1.0 / 3.0);
+  c.N = (R)d.N;
+  c.M = (R)d.M;
+  c.Q = (R)d.Q;
+  c.Rw = (R)d.R;
+  c.Q4R = (R)(4.0 * (d.Q + d.R));
+  c.Ny = (R)(dir * d.N);
+  c.My = (R)(dir * d.M);
+  c.Ub = (R)(-d.U);
+  c.Ut = (R)d.U;
+  return c;
 }
 
 // Equilibrium (Eq.(eqfunc)) and forcing (Eq.(forceterm), Eq.(coeff)) in
@@ -223,14 +215,15 @@ __device__ __forceinline__ R fast_rcp(R x) { return (R)1 / x; }
 template <>
 __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Pull the nine values a node of physical row `m.phys` needs (Eq.(evoleq)):
-// slot i holds S_i(x - c_i). At a wall node the three slots whose source lies
-// outside the lattice hold instead the node's own post-collision populations
-// that would leave it (lower wall: S4, S7, S8 in slots 2, 5, 6; upper wall:
-// S2, S5, S6 in slots 4, 7, 8), so that the sum of the slots is n-hat.
+// Values the stages pass to each other through LDS.
 template <typename R>
 struct Pair {
   R x, y;
+};
+
+template <typename R>
+struct Mom {
+  R jx, jy;
 };
 
 template <typename R>
@@ -243,8 +236,9 @@ struct Quad {
 // outside the lattice hold instead the node's own post-collision populations
 // that would leave it (lower wall: S4, S7, S8 in slots 2, 5, 6; upper wall:
 // S2, S5, S6 in slots 4, 7, 8), so that the sum of the slots is n-hat.
-// Full reflection for rows beyond the tile's ghost range (rows that are
-// loaded but never stored), so every row index maps into the lattice.
+// Row map for loads: full reflection for rows beyond the tile's ghost range
+// (rows that are loaded but never stored), so every row index maps into the
+// lattice.
 __device__ __forceinline__ RowMap map_row_any(int a, int Ly, int periodic) {
   if (periodic || (a >= -3 && a <= Ly + 2)) return map_row(a, Ly, periodic);
   RowMap m;
@@ -288,6 +282,110 @@ __device__ __forceinline__ void pull_row(R v[9], __amdgpu_buffer_rsrc_t S, uint3
   v[8] = buf_ld((R*)nullptr, S, v8, (int)(p8 * pbytes + o_n));
 }
 
+// ---- stage arithmetic, shared by the one-step and two-step kernels --------
+
+// Stage B at one node: the Laplacian of n (Eq.(laplstencil)) and the pressure
+// term p^i - p^w = n T - 3 n T / (3 - n) + 9 n^2 / 8 = n^2 (9/8 - T / (3 - n))
+// (Eq.(eqstate)), from the density deviations of the rows behind the node
+// (nb), at it (n0) and ahead of it (na) in the march.
+template <typename R>
+__device__ __forceinline__ Pair<R> stage_lp(const R* nb, const R* n0, const R* na, int u,
+                                            const Sten<R>& c) {
+  const R dn = n0[u];
+  const R L = c.Q * ((n0[u + 1] + n0[u - 1]) + (na[u] + nb[u])) +
+              c.Rw * ((na[u + 1] + na[u - 1]) + (nb[u + 1] + nb[u - 1])) - c.Q4R * dn;
+  const R n = c.nbar + dn;
+  const R P = n * n * ((R)1.125 - c.T * fast_rcp<R>((R)3 - n));
+  return Pair<R>{L, P};
+}
+
+// Stage C force at one node in lattice units (Eq.(force2), Eq.(periodicforce)):
+// F = [grad(p^i - p^w) + kappa n grad(Laplacian n) + F_ext] / 3, from the
+// (Laplacian, pressure term) rows behind (Bk), at (Md) and ahead (Ah). The
+// gradient stencil (Eq.(xstencil)): d/dx = N (E - W) + M (d1 + d2),
+// d/dy = dir [N (A - B) + M (d1 - d2)], d1 = AE - BW, d2 = BE - AW.
+template <typename R>
+__device__ __forceinline__ void stage_force(const Pair<R>* Bk, const Pair<R>* Md,
+                                            const Pair<R>* Ah, int u, R n, R fx3,
+                                            const Sten<R>& c, R& Fx, R& Fy) {
+  const Pair<R> aE = Ah[u + 1], aW = Ah[u - 1], aC = Ah[u];
+  const Pair<R> bE = Bk[u + 1], bW = Bk[u - 1], bC = Bk[u];
+  const Pair<R> mE = Md[u + 1], mW = Md[u - 1];
+  const R Ld1 = aE.x - bW.x, Ld2 = bE.x - aW.x;
+  const R Pd1 = aE.y - bW.y, Pd2 = bE.y - aW.y;
+  const R gLx = c.N * (mE.x - mW.x) + c.M * (Ld1 + Ld2);
+  const R gLy = c.Ny * (aC.x - bC.x) + c.My * (Ld1 - Ld2);
+  const R gPx = c.N * (mE.y - mW.y) + c.M * (Pd1 + Pd2);
+  const R gPy = c.Ny * (aC.y - bC.y) + c.My * (Pd1 - Pd2);
+  const R kn = c.kap3 * n;
+  Fx = c.third * gPx + kn * gLx + fx3;
+  Fy = c.third * gPy + kn * gLy;
+}
+
+// Stage C momentum j* = sum_i f_i c_i + F/2 (Eq.(newvel)) of the pulled
+// populations v of a node; a wall node carries the wall's momentum n U.
+// ysgn = -1 on a mirrored ghost row (y-components odd).
+template <typename R>
+__device__ __forceinline__ void stage_mom(const R v[9], int wall, int ysgn, R n, R Fx, R Fy,
+                                          const Sten<R>& c, R& jx, R& jy) {
+  if (wall) {
+    jx = n * (wall == 1 ? c.Ub : c.Ut);
+    jy = (R)0;
+  } else {
+    jx = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]) + (R)0.5 * Fx;
+    R py = (v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]);
+    if (ysgn < 0) py = -py;
+    jy = py + (R)0.5 * Fy;
+  }
+}
+
+// Stage D gradients (Eq.(coeff)): grad n and D = d/dx j*_x + d/dy j*_y, from
+// the density rows behind / at / ahead of the node and the j* rows behind (Jb),
+// at (J0) and ahead (Ja). sb and sa multiply the y-components read from Jb and
+// Ja: -1 where that row stands for the mirror image of the other across a
+// wall, else 1.
+template <typename R, typename J>
+__device__ __forceinline__ void stage_grad(const R* nb, const R* n0, const R* na, const J* Jb,
+                                           const J* J0, const J* Ja, int u, R sb, R sa,
+                                           const Sten<R>& c, R& dnx, R& dny, R& D) {
+  const R nd1 = na[u + 1] - nb[u - 1], nd2 = nb[u + 1] - na[u - 1];
+  dnx = c.N * (n0[u + 1] - n0[u - 1]) + c.M * (nd1 + nd2);
+  dny = c.Ny * (na[u] - nb[u]) + c.My * (nd1 - nd2);
+  const Pair<R> aE = {Ja[u + 1].jx, sa * Ja[u + 1].jy}, aW = {Ja[u - 1].jx, sa * Ja[u - 1].jy};
+  const Pair<R> bE = {Jb[u + 1].jx, sb * Jb[u + 1].jy}, bW = {Jb[u - 1].jx, sb * Jb[u - 1].jy};
+  const R aCy = sa * Ja[u].jy, bCy = sb * Jb[u].jy;
+  const R mEx = J0[u + 1].jx, mWx = J0[u - 1].jx;
+  D = c.N * (mEx - mWx) + c.M * ((aE.x - aW.x) + (bE.x - bW.x)) + c.Ny * (aCy - bCy) +
+      c.My * ((aE.y - bE.y) + (aW.y - bW.y));
+}
+
+// Moving-wall rule (Sec. II) for the populations of a wall node whose source
+// lies outside the lattice: lower wall (wall 1, speed Ub) as printed, upper
+// wall (2, speed Ut) by mirror.
+template <typename R>
+__device__ __forceinline__ void stage_wall(R g[9], int wall, R dn, R n, R Fx, R Fy,
+                                           const Sten<R>& c) {
+  if (wall == 1) {
+    const R h = (R)0.5 * (g[1] - g[3]);
+    g[2] = g[4];
+    g[5] = g[7] - h - (R)0.25 * (Fx + Fy) + (R)0.5 * n * c.Ub;
+    g[6] = g[8] + h + (R)0.25 * (Fx - Fy) - (R)0.5 * n * c.Ub;
+    g[0] = dn - (g[1] + g[3]) - (R)2 * (g[4] + g[7] + g[8]) + (R)0.5 * Fy;
+  } else if (wall == 2) {
+    const R h = (R)0.5 * (g[1] - g[3]);
+    g[4] = g[2];
+    g[7] = g[5] + h + (R)0.25 * (Fx + Fy) - (R)0.5 * n * c.Ut;
+    g[8] = g[6] - h - (R)0.25 * (Fx - Fy) + (R)0.5 * n * c.Ut;
+    g[0] = dn - (g[1] + g[3]) - (R)2 * (g[2] + g[5] + g[6]) - (R)0.5 * Fy;
+  }
+}
+
+// Density deviation of a node: the sum of its pulled slots (n-hat at walls).
+template <typename R>
+__device__ __forceinline__ R slot_sum(const R v[9]) {
+  return ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])) + v[8];
+}
+
 // Rows of populations in flight ahead of stage A, and the waves per SIMD the
 // register budget is sized for (FP32; FP64 always sizes for one wave). Two
 // rows at 3 waves per SIMD (about 140 VGPRs, no spills) measured fastest on
@@ -324,12 +422,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
   const __amdgpu_buffer_rsrc_t Snone = make_rsrc(d.S[parity ^ 1], 0);  // drops every access
   const R* __restrict__ fext3 = (const R*)d.fext3;
   const Coll<R> cl = make_coll<R>(d);
-  const R nbar = (R)d.nbar, T = (R)d.T, kap3 = (R)d.kappa3, third = (R)(1.0 / 3.0);
-  const R N = (R)d.N, M = (R)d.M, Q = (R)d.Q, Rw = (R)d.R, Q4R = (R)(4.0 * (d.Q + d.R));
-  // y stencils are taken along the march ("ahead" minus "behind"); the sign
-  // of the march turns them into d/dy
-  const R Ny = (R)(dir * d.N), My = (R)(dir * d.M);
-  const R Ub = (R)(-d.U), Ut = (R)d.U;
+  const Sten<R> c = make_sten<R>(d, dir);
   R shift = (R)0;
   if ((flags & kApplyShift) && d.shift) shift = (R)(*d.shift);
   const R sh0 = shift * (R)rest_weight_hd(0, d.T), sha = shift * (R)rest_weight_hd(1, d.T),
@@ -402,8 +495,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
 #pragma unroll
           for (int i = 5; i <= 8; ++i) v[i] += shd;
         }
-        const R dn = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])) + v[8];
-        nR[s][u] = dn;
+        nR[s][u] = slot_sum<R>(v);
       }
       // prefetch row a + P dir into the slot just consumed (dropped past the
       // last pipeline row)
@@ -411,52 +503,17 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
                   map_row_any(a + P * dir, Ly, periodic), vc, vm, vp);
       __syncthreads();
       // ---- stage B: row a - dir: Laplacian and pressure term -----------------
-      if (k >= 2 && k < K && actB) {
-        const R* nb_ = nR[(s + 6) & 7];  // behind
-        const R* n0 = nR[(s + 7) & 7];
-        const R* na_ = nR[s];            // ahead
-        const R c = n0[u];
-        const R L = Q * ((n0[u + 1] + n0[u - 1]) + (na_[u] + nb_[u])) +
-                    Rw * ((na_[u + 1] + na_[u - 1]) + (nb_[u + 1] + nb_[u - 1])) - Q4R * c;
-        const R n = nbar + c;
-        // p^i - p^w = n T - 3 n T / (3 - n) + 9 n^2 / 8 = n^2 (9/8 - T / (3 - n))
-        const R P = n * n * ((R)1.125 - T * fast_rcp<R>((R)3 - n));
-        LP[(s + 3) & 3][u] = Pair<R>{L, P};
-      }
+      if (k >= 2 && k < K && actB)
+        LP[(s + 3) & 3][u] = stage_lp<R>(nR[(s + 6) & 7], nR[(s + 7) & 7], nR[s], u, c);
       __syncthreads();
       // ---- stage C: row a - 2 dir: force and j* ------------------------------
       if (k >= 4 && k < K && actC) {
-        const Pair<R>* Bk = LP[(s + 1) & 3];  // behind
-        const Pair<R>* Md = LP[(s + 2) & 3];
-        const Pair<R>* Ah = LP[(s + 3) & 3];  // ahead
-        const Pair<R> aE = Ah[u + 1], aW = Ah[u - 1], aC = Ah[u];
-        const Pair<R> bE = Bk[u + 1], bW = Bk[u - 1], bC = Bk[u];
-        const Pair<R> mE = Md[u + 1], mW = Md[u - 1];
-        // gradient: d/dx = N (E - W) + M (d1 + d2), d/dy = dir [N (A - B) + M (d1 - d2)],
-        // d1 = AE - BW, d2 = BE - AW (A ahead, B behind in the march)
-        const R Ld1 = aE.x - bW.x, Ld2 = bE.x - aW.x;
-        const R Pd1 = aE.y - bW.y, Pd2 = bE.y - aW.y;
-        const R gLx = N * (mE.x - mW.x) + M * (Ld1 + Ld2);
-        const R gLy = Ny * (aC.x - bC.x) + My * (Ld1 - Ld2);
-        const R gPx = N * (mE.y - mW.y) + M * (Pd1 + Pd2);
-        const R gPy = Ny * (aC.y - bC.y) + My * (Pd1 - Pd2);
-        const R n = nbar + nR[(s + 6) & 7][u];
-        const R kn = kap3 * n;
-        const R Fx = third * gPx + kn * gLx + fx3;
-        const R Fy = third * gPy + kn * gLy;
+        const R n = c.nbar + nR[(s + 6) & 7][u];
+        R Fx, Fy, jx, jy;
+        stage_force<R>(LP[(s + 1) & 3], LP[(s + 2) & 3], LP[(s + 3) & 3], u, n, fx3, c, Fx, Fy);
+        // momentum of the pulled populations of this row, still in the ring
         const RowMap m = map_row(a - 2 * dir, Ly, periodic);
-        R jx, jy;
-        if (m.wall) {
-          jx = n * (m.wall == 1 ? Ub : Ut);
-          jy = (R)0;
-        } else {
-          // momentum of the pulled populations of this row, still in the ring
-          const R* v = f[(s + 2) & 3];
-          jx = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]) + (R)0.5 * Fx;
-          R py = (v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]);
-          if (m.ysgn < 0) py = -py;  // mirrored ghost row: y-components odd
-          jy = py + (R)0.5 * Fy;
-        }
+        stage_mom<R>(f[(s + 2) & 3], m.wall, m.ysgn, n, Fx, Fy, c, jx, jy);
         JR[(s + 2) & 3][u] = Quad<R>{jx, jy, Fx, Fy};
       }
       __syncthreads();
@@ -469,45 +526,18 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
       for (int i = 0; i < 9; ++i) g[i] = f[(s + 1) & 3][i];
       R n = (R)1, ux = (R)0, uy = (R)0;
       if (validD) {
-        const R* nb_ = nR[(s + 4) & 7];  // behind
-        const R* n0 = nR[(s + 5) & 7];
-        const R* na_ = nR[(s + 6) & 7];  // ahead
-        const R nd1 = na_[u + 1] - nb_[u - 1], nd2 = nb_[u + 1] - na_[u - 1];
-        const R dnx = N * (n0[u + 1] - n0[u - 1]) + M * (nd1 + nd2);
-        const R dny = Ny * (na_[u] - nb_[u]) + My * (nd1 - nd2);
-        const Quad<R>* Jb = JR[s & 3];
-        const Quad<R>* J0 = JR[(s + 1) & 3];
-        const Quad<R>* Ja = JR[(s + 2) & 3];
-        const Pair<R> aE = {Ja[u + 1].jx, Ja[u + 1].jy}, aW = {Ja[u - 1].jx, Ja[u - 1].jy};
-        const Pair<R> bE = {Jb[u + 1].jx, Jb[u + 1].jy}, bW = {Jb[u - 1].jx, Jb[u - 1].jy};
-        const R aCy = Ja[u].jy, bCy = Jb[u].jy;
-        const R mEx = J0[u + 1].jx, mWx = J0[u - 1].jx;
-        const Quad<R> mC = J0[u];
-        // D = d/dx j*_x + d/dy j*_y
-        const R D = N * (mEx - mWx) + M * ((aE.x - aW.x) + (bE.x - bW.x)) +
-                    Ny * (aCy - bCy) + My * ((aE.y - bE.y) + (aW.y - bW.y));
-        const R dn = n0[u];
-        n = nbar + dn;
+        R dnx, dny, D;
+        stage_grad<R>(nR[(s + 4) & 7], nR[(s + 5) & 7], nR[(s + 6) & 7], JR[s & 3],
+                      JR[(s + 1) & 3], JR[(s + 2) & 3], u, (R)1, (R)1, c, dnx, dny, D);
+        const Quad<R> mC = JR[(s + 1) & 3][u];
+        const R dn = nR[(s + 5) & 7][u];
+        n = c.nbar + dn;
         const R rn = fast_rcp<R>(n);
-        const R jx = mC.jx, jy = mC.jy;
-        ux = jx * rn;
-        uy = jy * rn;
-        const R Fx = mC.Fx, Fy = mC.Fy;
+        ux = mC.jx * rn;
+        uy = mC.jy * rn;
         const int wall = periodic ? 0 : (dd == 0 ? 1 : (dd == Ly - 1 ? 2 : 0));
-        if (wall == 1) {  // lower wall, speed Ub (Sec. II)
-          const R h = (R)0.5 * (g[1] - g[3]);
-          g[2] = g[4];
-          g[5] = g[7] - h - (R)0.25 * (Fx + Fy) + (R)0.5 * n * Ub;
-          g[6] = g[8] + h + (R)0.25 * (Fx - Fy) - (R)0.5 * n * Ub;
-          g[0] = dn - (g[1] + g[3]) - (R)2 * (g[4] + g[7] + g[8]) + (R)0.5 * Fy;
-        } else if (wall == 2) {  // upper wall: mirror image, speed Ut
-          const R h = (R)0.5 * (g[1] - g[3]);
-          g[4] = g[2];
-          g[7] = g[5] + h + (R)0.25 * (Fx + Fy) - (R)0.5 * n * Ut;
-          g[8] = g[6] - h - (R)0.25 * (Fx - Fy) + (R)0.5 * n * Ut;
-          g[0] = dn - (g[1] + g[3]) - (R)2 * (g[2] + g[5] + g[6]) - (R)0.5 * Fy;
-        }
-        collide<R>(g, cl, n, dn, jx, jy, rn, Fx, Fy, dnx, dny, D);
+        stage_wall<R>(g, wall, dn, n, mC.Fx, mC.Fy, c);
+        collide<R>(g, cl, n, dn, mC.jx, mC.jy, rn, mC.Fx, mC.Fy, dnx, dny, D);
       }
       {
         const __amdgpu_buffer_rsrc_t so = validD ? Sout : Snone;
@@ -527,6 +557,354 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Two time steps per launch (FP32). A workgroup of NT threads owns a strip of
+// NT-14 columns; thread t works on column x0-7+t. The first step runs the
+// pipeline of step_kernel over the columns and rows the second step needs (4
+// more on each side) and keeps its post-collision populations in an LDS ring
+// of four rows instead of storing them; the second step pulls from that ring,
+// runs the same four stages 8 rows behind the first, and stores. Each
+// population in HBM is read and written once per two steps.
+//
+// The second step has no ghost rows: at a wall row its stages read the
+// mirror image of the row inside the lattice where the first step reads a
+// ghost row (the same values, y-components negated), so both kernels give
+// the same bits. Its rows run from S2 to E2 in march order, its outputs plus
+// three rows on each side, cut at a wall; the first step's outputs run one
+// row further on each side that is not a wall.
+//
+// Per iteration k, four phases separated by barriers:
+//   1: A1 (row k of the first step's pipeline), A2 (second step row k-8);
+//   2: B1, B2;  3: C1, C2;  4: D1 (to the LDS ring), D2 (to HBM).
+// The second step's rings are indexed like the first's (8 rows behind, 8 is
+// 0 mod the ring sizes); A2 reads ring rows that D1 wrote in earlier
+// iterations.
+// ---------------------------------------------------------------------------
+template <int NT, bool MOM>
+__global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ descs,
+                                                      const Tile* __restrict__ tiles, int ntiles,
+                                                      int parity, int flags) {
+  using R = float;
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb >> 3, rm = nb & 7, xcd = b & 7;
+  const int logical = xcd * q + (xcd < rm ? xcd : rm) + (b >> 3);
+  if (logical >= ntiles) return;  // uniform per block
+  const Tile tile = tiles[logical];
+  const int inst = tile.inst & 0x7fffffff;
+  const int dir = (tile.inst < 0) ? -1 : 1;
+  const Desc& d = descs[inst];
+  const int Lx = d.Lx, Ly = d.Ly, periodic = d.periodic;
+  const int64_t nn = (int64_t)Lx * Ly;
+  const int rowb = 9 * Lx * (int)sizeof(R);
+  const int arrb = (int)(9 * nn * (int64_t)sizeof(R));
+  const __amdgpu_buffer_rsrc_t Sin = make_rsrc(d.S[parity], arrb);
+  const __amdgpu_buffer_rsrc_t Sout = make_rsrc(d.S[parity ^ 1], arrb);
+  const __amdgpu_buffer_rsrc_t Snone = make_rsrc(d.S[parity ^ 1], 0);
+  const R* __restrict__ fext3 = (const R*)d.fext3;
+  const Coll<R> cl = make_coll<R>(d);
+  const Sten<R> c = make_sten<R>(d, dir);
+  R shift = (R)0;
+  if ((flags & kApplyShift) && d.shift) shift = (R)(*d.shift);
+  const R sh0 = shift * (R)rest_weight_hd(0, d.T), sha = shift * (R)rest_weight_hd(1, d.T),
+          shd = shift * (R)rest_weight_hd(5, d.T);
+
+  const int t = threadIdx.x;
+  const int W = min(NT - 14, Lx - tile.x0);  // columns this strip updates
+  int xc = (tile.x0 - 7 + t) % Lx;
+  if (xc < 0) xc += Lx;
+  const int xm = xc == 0 ? Lx - 1 : xc - 1;
+  const int xp = xc == Lx - 1 ? 0 : xc + 1;
+  const bool actA = t < W + 14;
+  const bool actB = t >= 1 && t < W + 13;
+  const bool actC = t >= 2 && t < W + 12;
+  const bool actD = t >= 3 && t < W + 11;
+  const bool act2A = t >= 4 && t < W + 10;
+  const bool act2B = t >= 5 && t < W + 9;
+  const bool act2C = t >= 6 && t < W + 8;
+  const bool act2D = t >= 7 && t < W + 7;
+  const int vc = actA ? xc * (int)sizeof(R) : arrb;
+  const int vm = actA ? xm * (int)sizeof(R) : arrb;
+  const int vp = actA ? xp * (int)sizeof(R) : arrb;
+  const R fx3 = actC ? fext3[xc] : (R)0;
+  const uint32_t pbytes = (uint32_t)Lx * (uint32_t)sizeof(R);
+
+  // Rows in march order. S1 is the first step's first output row (relative
+  // index 0); rel(y) = dir (y - S1).
+  int S2, E2, ofirst, olast;
+  bool ws = false, we = false;
+  if (dir > 0) {
+    S2 = tile.y0 - 3;
+    E2 = tile.y1 + 2;
+    if (!periodic) {
+      S2 = max(S2, 0);
+      E2 = min(E2, Ly - 1);
+      ws = S2 == 0;
+      we = E2 == Ly - 1;
+    }
+    ofirst = tile.y0;
+    olast = tile.y1 - 1;
+  } else {
+    S2 = tile.y1 + 2;
+    E2 = tile.y0 - 3;
+    if (!periodic) {
+      S2 = min(S2, Ly - 1);
+      E2 = max(E2, 0);
+      ws = S2 == Ly - 1;
+      we = E2 == 0;
+    }
+    ofirst = tile.y1 - 1;
+    olast = tile.y0;
+  }
+  const int S1 = ws ? S2 : S2 - dir;
+  const int E1 = we ? E2 : E2 + dir;
+  const int K1 = dir * (E1 - S1) + 1 + 6;  // first step: pipeline rows S1-3 .. E1+3
+  const int a0 = S1 - 3 * dir;
+  // second step, relative rows of each stage (first, last)
+  const int r2s = dir * (S2 - S1), r2e = dir * (E2 - S1);
+  const int rbs = r2s + (ws ? 0 : 1), rbe = r2e - (we ? 0 : 1);
+  const int rcs = r2s + (ws ? 0 : 2), rce = r2e - (we ? 0 : 2);
+  const int rds = dir * (ofirst - S1), rde = dir * (olast - S1);
+  const int K = rde + 12;  // D2 runs on relative row k - 11
+
+  // LDS: 288 (NT + 2) bytes, so four 128-thread or two 256-thread
+  // workgroups fit on a CU. The force F goes from stage C to stage D of the
+  // next iteration in registers (Fr); of the first step's post-collision
+  // populations only those that move along x (1, 3, 5, 6, 7, 8) go through
+  // LDS (O, planes in that order), populations 0, 2 and 4 stay in the
+  // thread's registers (Or).
+  __shared__ R nR[8][NT + 2];
+  __shared__ Pair<R> LP[4][NT + 2];
+  __shared__ Mom<R> JR[4][NT + 2];
+  __shared__ R nR2[8][NT + 2];
+  __shared__ Pair<R> LP2[4][NT + 2];
+  __shared__ Mom<R> JR2[4][NT + 2];
+  __shared__ R O[4][6][NT + 2];
+  const int u = t + 1;
+
+  constexpr int P = kPrefetch;
+  R f[4][9], f2[4][9], pf[P][9];
+  R Fr[2][2], Fr2[2][2];  // (F_x, F_y) of the row stage C last finished
+  R Or[4][3];             // populations 0, 2, 4 of the ring rows
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      f[s][i] = (R)0;
+      f2[s][i] = (R)0;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Or[s][i] = (R)0;
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      Fr[s][i] = (R)0;
+      Fr2[s][i] = (R)0;
+    }
+
+#pragma unroll
+  for (int j = 0; j < P; ++j)
+    pull_row<R>(pf[j], j < K1 ? Sin : Snone, pbytes, (uint32_t)rowb, Ly, periodic,
+                map_row_any(a0 + dir * j, Ly, periodic), vc, vm, vp);
+
+  for (int kb = 0; kb < K; kb += 8) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = kb + s;
+      const int a = a0 + dir * k;
+      // ---- phase 1 -------------------------------------------------------------
+      if (k < K1) {  // A1 on row a
+        R* v = f[s & 3];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) v[i] = pf[s % P][i];
+        if (shift != (R)0) {
+          v[0] += sh0;
+#pragma unroll
+          for (int i = 1; i <= 4; ++i) v[i] += sha;
+#pragma unroll
+          for (int i = 5; i <= 8; ++i) v[i] += shd;
+        }
+        nR[s][u] = slot_sum<R>(v);
+      }
+      pull_row<R>(pf[s % P], (k + P < K1) ? Sin : Snone, pbytes, (uint32_t)rowb, Ly, periodic,
+                  map_row_any(a + P * dir, Ly, periodic), vc, vm, vp);
+      {  // A2 on relative row k - 8: pull from the ring (rows k-9, k-8, k-7)
+        const int r = k - 8;
+        if (r >= r2s && r <= r2e && act2A) {
+          const int y = S1 + dir * r;
+          const bool lo = !periodic && y == 0, hi = !periodic && y == Ly - 1;
+          constexpr int ps = NT + 2;  // plane stride; planes 0..5 hold populations 1, 3, 5, 6, 7, 8
+          const R* Ob = &O[(s + 3) & 3][0][0];
+          const R* Oc = &O[s & 3][0][0];
+          const R* Oa = &O[(s + 1) & 3][0][0];
+          const R* Os = dir > 0 ? Ob : Oa;  // row y - 1 (sources with c_y = +1)
+          const R* On = dir > 0 ? Oa : Ob;  // row y + 1 (sources with c_y = -1)
+          const R* rb = Or[(s + 3) & 3];
+          const R* rc = Or[s & 3];
+          const R* ra = Or[(s + 1) & 3];
+          const R s2 = dir > 0 ? rb[1] : ra[1];  // population 2 of row y - 1
+          const R n4 = dir > 0 ? ra[2] : rb[2];  // population 4 of row y + 1
+          R* v = f2[s & 3];
+          v[0] = rc[0];
+          v[1] = Oc[0 * ps + u - 1];
+          v[3] = Oc[1 * ps + u + 1];
+          v[2] = lo ? rc[2] : s2;
+          v[5] = lo ? Oc[4 * ps + u] : Os[2 * ps + u - 1];
+          v[6] = lo ? Oc[5 * ps + u] : Os[3 * ps + u + 1];
+          v[4] = hi ? rc[1] : n4;
+          v[7] = hi ? Oc[2 * ps + u] : On[4 * ps + u + 1];
+          v[8] = hi ? Oc[3 * ps + u] : On[5 * ps + u - 1];
+          nR2[s][u] = slot_sum<R>(v);
+        }
+      }
+      __syncthreads();
+      // ---- phase 2 -------------------------------------------------------------
+      if (k >= 2 && k < K1 && actB)
+        LP[(s + 3) & 3][u] = stage_lp<R>(nR[(s + 6) & 7], nR[(s + 7) & 7], nR[s], u, c);
+      {
+        const int r = k - 9;
+        if (r >= rbs && r <= rbe && act2B) {
+          const R* bh = nR2[(s + 6) & 7];
+          const R* ah = nR2[s];
+          if (ws && r == r2s) bh = ah;  // behind the first row: its mirror
+          if (we && r == r2e) ah = bh;
+          LP2[(s + 3) & 3][u] = stage_lp<R>(bh, nR2[(s + 7) & 7], ah, u, c);
+        }
+      }
+      __syncthreads();
+      // ---- phase 3 -------------------------------------------------------------
+      if (k >= 4 && k < K1 && actC) {
+        const R n = c.nbar + nR[(s + 6) & 7][u];
+        R Fx, Fy, jx, jy;
+        stage_force<R>(LP[(s + 1) & 3], LP[(s + 2) & 3], LP[(s + 3) & 3], u, n, fx3, c, Fx, Fy);
+        const RowMap m = map_row(a - 2 * dir, Ly, periodic);
+        stage_mom<R>(f[(s + 2) & 3], m.wall, m.ysgn, n, Fx, Fy, c, jx, jy);
+        JR[(s + 2) & 3][u] = Mom<R>{jx, jy};
+        Fr[s & 1][0] = Fx;
+        Fr[s & 1][1] = Fy;
+      }
+      {
+        const int r = k - 10;
+        if (r >= rcs && r <= rce && act2C) {
+          const Pair<R>* bh = LP2[(s + 1) & 3];
+          const Pair<R>* ah = LP2[(s + 3) & 3];
+          if (ws && r == r2s) bh = ah;
+          if (we && r == r2e) ah = bh;
+          const R n = c.nbar + nR2[(s + 6) & 7][u];
+          R Fx, Fy, jx, jy;
+          stage_force<R>(bh, LP2[(s + 2) & 3], ah, u, n, fx3, c, Fx, Fy);
+          const int y = S1 + dir * r;
+          const int wall = periodic ? 0 : (y == 0 ? 1 : (y == Ly - 1 ? 2 : 0));
+          stage_mom<R>(f2[(s + 2) & 3], wall, 1, n, Fx, Fy, c, jx, jy);
+          JR2[(s + 2) & 3][u] = Mom<R>{jx, jy};
+          Fr2[s & 1][0] = Fx;
+          Fr2[s & 1][1] = Fy;
+        }
+      }
+      __syncthreads();
+      // ---- phase 4 -------------------------------------------------------------
+      if (k >= 6 && k < K1 && actD) {  // D1 on row a - 3 dir, into the ring
+        const int dd = a - 3 * dir;
+        R g[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = f[(s + 1) & 3][i];
+        R dnx, dny, D;
+        stage_grad<R>(nR[(s + 4) & 7], nR[(s + 5) & 7], nR[(s + 6) & 7], JR[s & 3],
+                      JR[(s + 1) & 3], JR[(s + 2) & 3], u, (R)1, (R)1, c, dnx, dny, D);
+        const Mom<R> mC = JR[(s + 1) & 3][u];
+        const R Fx = Fr[(s + 1) & 1][0], Fy = Fr[(s + 1) & 1][1];
+        const R dn = nR[(s + 5) & 7][u];
+        const R n = c.nbar + dn;
+        const R rn = fast_rcp<R>(n);
+        const int wall = periodic ? 0 : (dd == 0 ? 1 : (dd == Ly - 1 ? 2 : 0));
+        stage_wall<R>(g, wall, dn, n, Fx, Fy, c);
+        collide<R>(g, cl, n, dn, mC.jx, mC.jy, rn, Fx, Fy, dnx, dny, D);
+        R* o = &O[(s + 2) & 3][0][0];
+        constexpr int ps = NT + 2;
+        o[0 * ps + u] = g[1];
+        o[1 * ps + u] = g[3];
+        o[2 * ps + u] = g[5];
+        o[3 * ps + u] = g[6];
+        o[4 * ps + u] = g[7];
+        o[5 * ps + u] = g[8];
+        Or[(s + 2) & 3][0] = g[0];
+        Or[(s + 2) & 3][1] = g[2];
+        Or[(s + 2) & 3][2] = g[4];
+      }
+      {  // D2 on relative row k - 11, to HBM
+        const int r = k - 11;
+        const bool validD = r >= rds && r <= rde;
+        const int dd = S1 + dir * r;
+        R g[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = f2[(s + 1) & 3][i];
+        R n = (R)1, ux = (R)0, uy = (R)0;
+        if (validD && act2D) {
+          const R* bh = nR2[(s + 4) & 7];
+          const R* ah = nR2[(s + 6) & 7];
+          const Mom<R>* Jb = JR2[s & 3];
+          const Mom<R>* Ja = JR2[(s + 2) & 3];
+          R sb = (R)1, sa = (R)1;
+          if (ws && r == r2s) { bh = ah; Jb = Ja; sb = (R)-1; }
+          if (we && r == r2e) { ah = bh; Ja = Jb; sa = (R)-1; }
+          R dnx, dny, D;
+          stage_grad<R>(bh, nR2[(s + 5) & 7], ah, Jb, JR2[(s + 1) & 3], Ja, u, sb, sa, c, dnx,
+                        dny, D);
+          const Mom<R> mC = JR2[(s + 1) & 3][u];
+          const R Fx = Fr2[(s + 1) & 1][0], Fy = Fr2[(s + 1) & 1][1];
+          const R dn = nR2[(s + 5) & 7][u];
+          n = c.nbar + dn;
+          const R rn = fast_rcp<R>(n);
+          ux = mC.jx * rn;
+          uy = mC.jy * rn;
+          const int wall = periodic ? 0 : (dd == 0 ? 1 : (dd == Ly - 1 ? 2 : 0));
+          stage_wall<R>(g, wall, dn, n, Fx, Fy, c);
+          collide<R>(g, cl, n, dn, mC.jx, mC.jy, rn, Fx, Fy, dnx, dny, D);
+        }
+        const __amdgpu_buffer_rsrc_t so = validD ? Sout : Snone;
+        int yy = dd % Ly;
+        if (yy < 0) yy += Ly;
+        const uint32_t roff = validD ? (uint32_t)yy * (uint32_t)rowb : 0u;
+        const int vst = act2D ? vc : arrb;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) buf_st(g[i], so, vst, (int)((uint32_t)i * pbytes + roff));
+        if (MOM) {
+          const int momb = (int)(3 * nn * 8);
+          const __amdgpu_buffer_rsrc_t mo = make_rsrc(d.mom, validD ? momb : 0);
+          const int vo = act2D ? xc * 8 : momb;
+          const int ro = validD ? yy * Lx * 8 : 0;
+          buf_st((double)n, mo, vo, ro);
+          buf_st((double)ux, mo, vo, (int)(nn * 8) + ro);
+          buf_st((double)uy, mo, vo, (int)(2 * nn * 8) + ro);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int NT>
+static hipError_t launch_step2_t(const Desc* dd, const Tile* dt, int ntiles, int parity,
+                                 int flags, hipStream_t st) {
+  if (flags & kWriteMoments)
+    hipLaunchKernelGGL((step2_kernel<NT, true>), dim3(ntiles), dim3(NT), 0, st, dd, dt, ntiles,
+                       parity, flags);
+  else
+    hipLaunchKernelGGL((step2_kernel<NT, false>), dim3(ntiles), dim3(NT), 0, st, dd, dt, ntiles,
+                       parity, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_step2(int threads, const Desc* d_descs, const Tile* d_tiles, int ntiles,
+                        int parity, int flags, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  if (threads == 128) return launch_step2_t<128>(d_descs, d_tiles, ntiles, parity, flags, stream);
+  if (threads == 192) return launch_step2_t<192>(d_descs, d_tiles, ntiles, parity, flags, stream);
+  if (threads == 256) return launch_step2_t<256>(d_descs, d_tiles, ntiles, parity, flags, stream);
+  return hipErrorInvalidValue;
 }
 
 template <typename R, int NT>

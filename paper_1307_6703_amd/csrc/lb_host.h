@@ -67,7 +67,7 @@ inline lb_status validate(const lb_params* p) {
 
 // Workspace layout of one lattice, all offsets 256-byte aligned.
 struct Layout {
-  size_t desc, red, tiles, fext, part, mom, stage, S0, S1, total;
+  size_t desc, red, tiles, tiles1, fext, part, mom, stage, S0, S1, total;
   int max_tiles;
 };
 
@@ -84,6 +84,7 @@ inline Layout layout_for(const lb_params* p, size_t base = 0) {
   L.desc = o; o = align_up(o + sizeof(Desc));
   L.red = o; o = align_up(o + sizeof(ReduceOut));
   L.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)L.max_tiles);
+  L.tiles1 = o; o = align_up(o + sizeof(Tile) * (size_t)L.max_tiles);
   L.fext = o; o = align_up(o + rs * (size_t)p->Lx);
   L.part = o; o = align_up(o + sizeof(double) * 6 * (size_t)lbk::reduce_blocks((int64_t)nn));
   L.mom = o; o = align_up(o + sizeof(double) * 3 * nn);
@@ -120,11 +121,12 @@ inline int resident_slots(const lb_params* p, int threads) {
   return cus * std::max(1, waves_per_cu / ((threads + 63) / 64));
 }
 
-// Rows per chunk for a target number of chunks: a height of 2 mod 8 so the
-// kernel's 8-row unrolled march has no idle tail.
-inline int rows_for_chunks(int Ly, int chunks) {
+// Rows per chunk for a target number of chunks: a height of `mod` mod 8 so
+// the kernel's 8-row unrolled march has no idle tail (2 for the one-step
+// kernel, whose march is rows + 6 long; 1 for the two-step kernel, rows + 15).
+inline int rows_for_chunks(int Ly, int chunks, int mod = 2) {
   int rows = (Ly + std::max(chunks, 1) - 1) / std::max(chunks, 1);
-  rows = ((std::max(rows, 10) - 2 + 7) / 8) * 8 + 2;
+  rows = ((std::max(rows, 8 + mod) - mod + 7) / 8) * 8 + mod;
   return std::min(rows, Ly);
 }
 
@@ -135,13 +137,40 @@ inline int default_rows(const lb_params* p, int threads, int rounds = 1) {
   return rows_for_chunks(p->Ly, rounds * resident_slots(p, threads) / strips);
 }
 
-// Tiles of one lattice: strips of threads-6 columns, chunks of `rows` rows,
+// Two-step kernel (FP32): strips of threads-14 columns. One workgroup's LDS
+// rings take 288 (threads + 2) bytes, so 4, 2 or 2 workgroups of 128, 192 or
+// 256 threads fit on a CU (160 KB of LDS); at most 256 VGPRs allow 2 waves
+// per SIMD.
+inline bool fused_threads_ok(int threads) {
+  return threads == 128 || threads == 192 || threads == 256;
+}
+
+inline int fused_resident_slots(int threads) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  const int by_lds = (160 * 1024) / (288 * (threads + 2));
+  const int by_vgpr = 8 / (threads / 64);
+  return cus * std::max(1, std::min(by_lds, by_vgpr));
+}
+
+inline int fused_default_rows(const lb_params* p, int threads, int rounds = 1) {
+  const int strips = (p->Lx + threads - 15) / (threads - 14);
+  return rows_for_chunks(p->Ly, rounds * fused_resident_slots(threads) / strips, 1);
+}
+
+// Tiles of one lattice: strips of `threads - 2 halo` columns (halo 3 for the
+// one-step kernel, 7 for the two-step kernel), chunks of `rows` rows,
 // strip-major so consecutive tiles are vertical neighbours. Odd chunks march
 // downwards (sign bit of inst), so two neighbouring chunks reach their
 // shared boundary rows at the same time and share those loads in L2.
-inline std::vector<Tile> make_tiles(int inst, int Lx, int Ly, int threads, int rows) {
+inline std::vector<Tile> make_tiles(int inst, int Lx, int Ly, int threads, int rows,
+                                    int halo = 3) {
   std::vector<Tile> t;
-  const int w = threads - 6;
+  const int w = threads - 2 * halo;
   for (int x0 = 0; x0 < Lx; x0 += w) {
     int j = 0;
     for (int y0 = 0; y0 < Ly; y0 += rows, ++j) {

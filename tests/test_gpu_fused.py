@@ -1,0 +1,126 @@
+"""The two-step kernel (lb_set_launch_fused) against the one-step kernel and
+the oracle.
+
+Every node of the two-step kernel runs the arithmetic of two single steps
+on the same inputs, with mirror reads at the walls standing in for the
+one-step kernel's ghost rows, so populations and moments must agree bit for
+bit with one step per launch: walls and periodic y, ragged strips and
+chunks, chunks that start within three rows of a wall, both march
+directions, odd step counts, checks that split pairs, the drift shift, and
+the moments written by the last launch."""
+import sys
+
+import numpy as np
+import pytest
+
+import lbsynth as ls
+from oracle.lb_oracle import OracleLB, Params
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _lattice(Lx, Ly, periodic, seed, check_every=0, drift=False, U=0.03, V0=0.1, k=2, T=0.95):
+    from paper_1307_6703_amd import Lattice
+    N, Q = ls.table1_nq(T)
+    g = Lattice(Lx, Ly, T=T, tau=1.0, kappa=0.3, N=N, Q=Q, U=0.0 if periodic else U,
+                fext=ls.potential_force(Lx, V0, k), y_periodic=periodic, fp32=True,
+                check_every=check_every, drift_correct=drift)
+    g.init(ls.noisy_density(Lx, Ly, seed))
+    return g
+
+
+CASES = [
+    # Lx, Ly, periodic, (threads, rows), steps
+    (300, 70, False, (128, 8), 41),
+    (300, 70, True, (128, 9), 40),
+    (300, 70, False, (192, 17), 40),
+    (300, 70, False, (256, 70), 40),
+    (129, 37, False, (128, 33), 23),     # chunk of 4 rows at the upper wall
+    (100, 4, False, (128, 8), 20),       # smallest Ly: one chunk between two walls
+    (100, 5, True, (128, 8), 21),
+    (57, 12, False, (256, 8), 30),       # one strip wider than the lattice
+    (514, 40, True, (192, 8), 12),
+]
+
+
+@pytest.mark.parametrize("Lx,Ly,periodic,launch,steps", CASES)
+def test_fused_equals_one_step_bitwise(torch_cuda, Lx, Ly, periodic, launch, steps):
+    _say("fused vs one-step", Lx, Ly, periodic, launch, steps)
+    a = _lattice(Lx, Ly, periodic, seed=Lx + 7 * Ly)
+    b = _lattice(Lx, Ly, periodic, seed=Lx + 7 * Ly)
+    b.set_launch(*launch, steps_per_launch=2)
+    assert b.steps_per_launch() == 2
+    a.step(steps)
+    b.step(steps)
+    assert a.step_count == b.step_count == steps
+    for x, y in zip(a.moments(), b.moments()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+def test_fused_with_checks_and_drift_shift(torch_cuda):
+    # check_every = 7: pairs never straddle a check, so single steps appear
+    # before every check; the drift shift is applied by whichever kernel
+    # takes the next step
+    _say("fused with checks every 7 and drift correction")
+    a = _lattice(260, 48, False, seed=5, check_every=7, drift=True)
+    b = _lattice(260, 48, False, seed=5, check_every=7, drift=True)
+    b.set_launch(128, 17, steps_per_launch=2)
+    for n in (1, 6, 13, 30):
+        a.step(n)
+        b.step(n)
+        assert np.array_equal(a.populations(), b.populations()), n
+        for x, y in zip(a.moments(), b.moments()):
+            assert np.array_equal(x, y)
+    ra, rb = a.reduce(), b.reduce()
+    assert ra == rb
+
+
+def test_fused_matches_oracle(torch_cuda):
+    w = ls.PARITY_FP64
+    _say("fused fp32 vs oracle", w.name)
+    N, Q = ls.table1_nq(w.T)
+    from paper_1307_6703_amd import Lattice
+    fext = ls.potential_force(w.Lx, w.V0, w.k)
+    n0 = ls.noisy_density(w.Lx, w.Ly, w.seed)
+    g = Lattice(w.Lx, w.Ly, T=w.T, tau=1.0, kappa=0.3, N=N, Q=Q, U=w.U, fext=fext, fp32=True,
+                check_every=100, drift_correct=True)
+    g.set_launch(128, 0, steps_per_launch=2)
+    g.init(n0)
+    o = OracleLB(Params(w.Lx, w.Ly, T=w.T, tau=1.0, kappa=0.3, N=N, Q=Q, U=w.U), n0, fext=fext)
+    g.step(200)
+    o.run(200, threads=8)
+    n, ux, uy = g.moments()
+    rel = (np.abs(n - o.n) / o.n).max()
+    du = max(np.abs(ux - o.ux).max(), np.abs(uy - o.uy).max())
+    _say(f"max rel |dn| {rel:.2e}, max |du| {du:.2e}")
+    assert rel <= 1e-4 and du <= 1e-4
+
+
+def test_fused_launch_is_validated(torch_cuda):
+    from paper_1307_6703_amd import Lattice, LBError
+    g = Lattice(64, 16, fp32=False)
+    with pytest.raises(LBError):
+        g.set_launch(128, 0, steps_per_launch=2)  # FP64 storage
+    g.close()
+    g = _lattice(64, 16, False, seed=1)
+    for t in (64, 320, 512):
+        with pytest.raises(LBError):
+            g.set_launch(t, 0, steps_per_launch=2)
+    g.set_launch(0, 0, steps_per_launch=2)
+    assert g.steps_per_launch() == 2 and g.get_launch()[0] == 128
+    g.set_launch(0, 0)
+    assert g.steps_per_launch() == 1

@@ -262,7 +262,7 @@ def test_autotune_keeps_results(torch_cuda):
     a, _ = _pair(600, 96, U=0.03, V0=0.1, k=2, fp32=True)
     b, _ = _pair(600, 96, U=0.03, V0=0.1, k=2, fp32=True)
     t, r, ms = a.autotune(nsteps=2)
-    assert t in (64, 128, 256, 512) and r >= 8 and ms > 0
+    assert t in (64, 128, 192, 256, 512) and r >= 8 and ms > 0
     steps = a.step_count
     b.step(steps)
     assert np.array_equal(a.populations(), b.populations())

@@ -105,7 +105,7 @@ def batched_bench(steps: int, seed: int = 1307):
     draws = [w for w, st in zip(pool, status) if st == 0][:96]
     replaced = pool.index(draws[-1]) + 1 - len(draws)
     b = batch_of(draws)
-    th, rw, _ = b.autotune(nsteps=4)
+    th, rw, _ = b.autotune(nsteps=10)
     b.step(100)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -117,7 +117,8 @@ def batched_bench(steps: int, seed: int = 1307):
     status = b.status()
     out = {"instances": len(draws), "nodes": b.nodes, "steps": steps,
            "MLUPS": round(b.nodes * steps / (ms * 1e-3) / 1e6, 1),
-           "ms_per_step": round(ms / steps, 4), "launch": {"threads": th, "rows": rw},
+           "ms_per_step": round(ms / steps, 4),
+           "launch": {"threads": th, "rows": rw, "steps_per_launch": b.steps_per_launch()},
            "unstable_instances": sum(1 for v in status if v != 0),
            "draws_replaced_unstable": replaced,
            "workload": "96 draws: Lx in {128..1024}, Ly in {64,128,256}, T in [0.85,0.98], "

@@ -221,6 +221,10 @@ lb_status lb_batch_set_launch(lb_batch* b, int32_t threads, int32_t rows);
  * step. lb_get_steps_per_launch reports 1 or 2 for the current shape. */
 lb_status lb_set_launch_fused(lb_handle* h, int32_t threads, int32_t rows);
 lb_status lb_get_steps_per_launch(lb_handle* h, int32_t* steps);
+/* The same for a batch (all instances share the shape; rows 0: 65). Subset
+ * steps (lb_batch_step_subset) always run one step per launch. */
+lb_status lb_batch_set_launch_fused(lb_batch* b, int32_t threads, int32_t rows);
+lb_status lb_batch_get_steps_per_launch(lb_batch* b, int32_t* steps);
 
 /* Time nsteps steps of each candidate launch shape (one step per launch
  * and, with FP32 populations, two), pick the fastest and apply it; return
@@ -232,7 +236,8 @@ lb_status lb_get_steps_per_launch(lb_handle* h, int32_t* steps);
 lb_status lb_autotune(lb_handle* h, int32_t nsteps, int32_t* threads, int32_t* rows,
                       double* ms_per_step);
 
-/* lb_autotune for a batch: candidate shapes are shared by all instances. */
+/* lb_autotune for a batch: candidate shapes (one and, with FP32, two steps
+ * per launch) are shared by all instances. */
 lb_status lb_batch_autotune(lb_batch* b, int32_t nsteps, int32_t* threads, int32_t* rows,
                             double* ms_per_step);
 

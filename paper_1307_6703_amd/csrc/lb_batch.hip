@@ -25,7 +25,7 @@ struct Inst {
 
 // Shared part of the batch workspace.
 struct BatchLayout {
-  size_t descs, reds, tiles, sub_tiles, part, part_off, list_all, list_sub, inst0, total;
+  size_t descs, reds, tiles, tiles1, sub_tiles, part, part_off, list_all, list_sub, inst0, total;
   int max_tiles;
   std::vector<int64_t> off;  // partial-sum block offset of each instance
 };
@@ -46,6 +46,7 @@ BatchLayout batch_layout(int count, const lb_params* p, std::vector<Inst>* insts
   B.descs = o; o = align_up(o + sizeof(Desc) * count);
   B.reds = o; o = align_up(o + sizeof(ReduceOut) * count);
   B.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)max_tiles);
+  B.tiles1 = o; o = align_up(o + sizeof(Tile) * (size_t)max_tiles);
   B.sub_tiles = o; o = align_up(o + sizeof(Tile) * (size_t)max_tiles);
   B.part = o; o = align_up(o + sizeof(double) * 6 * (size_t)sum_red);
   B.part_off = o; o = align_up(o + sizeof(int64_t) * count);
@@ -80,10 +81,13 @@ struct lb_batch {
   std::vector<Desc> hdesc;
   Desc* ddesc = nullptr;
   ReduceOut* dred = nullptr;
-  Tile* dtiles = nullptr;
-  Tile* dsub = nullptr;  // tile table of the last subset step
+  Tile* dtiles = nullptr;   // tiles of the current launch shape
+  Tile* dtiles1 = nullptr;  // one-step tiles for single steps of a two-step shape
+  Tile* dsub = nullptr;     // tile table of the last subset step
   double* dpart = nullptr;
   int threads = 256, rows = 64, ntiles = 0;
+  int fuse = 1;  // steps per launch of the current shape
+  int threads1 = 128, rows1 = 16, ntiles1 = 0;
   int parity = 0;
   int64_t step = 0;
   bool pending_shift = false;
@@ -139,7 +143,8 @@ lb_status upload_list(lb_batch* b, const int32_t* mask, int32_t* dlist, int* n, 
 // Tiles of the instances with mask[i] != 0 (all when mask is NULL), largest
 // instances first: the dispatcher hands out tiles in order, so the
 // long-running ones start early.
-std::vector<Tile> tile_list(const lb_batch* b, int threads, int rows, const int32_t* mask) {
+std::vector<Tile> tile_list(const lb_batch* b, int threads, int rows, const int32_t* mask,
+                            int halo = 3) {
   std::vector<int> order;
   for (int i = 0; i < b->count; ++i)
     if ((!mask || mask[i]) && !b->dropped[i]) order.push_back(i);
@@ -148,7 +153,7 @@ std::vector<Tile> tile_list(const lb_batch* b, int threads, int rows, const int3
   std::vector<Tile> all;
   for (int i : order) {
     const int r = std::max(std::min(rows, b->inst[i].p.Ly), std::min(8, b->inst[i].p.Ly));
-    std::vector<Tile> t = make_tiles(i, b->inst[i].p.Lx, b->inst[i].p.Ly, threads, r);
+    std::vector<Tile> t = make_tiles(i, b->inst[i].p.Lx, b->inst[i].p.Ly, threads, r, halo);
     all.insert(all.end(), t.begin(), t.end());
   }
   return all;
@@ -174,18 +179,42 @@ void default_batch_launch(const lb_batch* b, int* threads, int* rows) {
   *rows = r;
 }
 
-lb_status batch_tiles(lb_batch* b, int threads, int rows) {
-  if (threads != 64 && threads != 128 && threads != 256 && threads != 320 &&
-      !(threads == 512 && b->fp32))
-    return fail(LB_EINVAL, "threads must be 64, 128, 256, 320 or 512 (FP32 only) (got %d)", threads);
-  if (rows < 1) return fail(LB_EINVAL, "rows must be >= 1");
-  std::vector<Tile> all = tile_list(b, threads, rows, nullptr);
+lb_status upload_tiles(lb_batch* b, Tile* dst, int threads, int rows, int fuse, int* ntiles) {
+  std::vector<Tile> all = tile_list(b, threads, rows, nullptr, fuse == 2 ? 7 : 3);
   if ((int)all.size() > b->B.max_tiles) return fail(LB_EINVAL, "too many tiles for the workspace");
-  HIPCHK(hipMemcpyAsync(b->dtiles, all.data(), all.size() * sizeof(Tile), hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipMemcpyAsync(dst, all.data(), all.size() * sizeof(Tile), hipMemcpyHostToDevice, b->st));
   HIPCHK(hipStreamSynchronize(b->st));
+  *ntiles = (int)all.size();
+  return LB_OK;
+}
+
+// Launch shape (fuse = steps per launch). A two-step shape keeps the default
+// one-step shape for single steps (before a check that splits a pair, the
+// last of an odd count, subset steps).
+lb_status batch_tiles(lb_batch* b, int threads, int rows, int fuse = 1) {
+  if (fuse == 2) {
+    if (!b->fp32) return fail(LB_EINVAL, "two steps per launch need FP32 storage");
+    if (!fused_threads_ok(threads))
+      return fail(LB_EINVAL, "two steps per launch: threads must be 128, 192 or 256 (got %d)", threads);
+  } else if (threads != 64 && threads != 128 && threads != 256 && threads != 320 &&
+             !(threads == 512 && b->fp32)) {
+    return fail(LB_EINVAL, "threads must be 64, 128, 256, 320 or 512 (FP32 only) (got %d)", threads);
+  }
+  if (rows < 1) return fail(LB_EINVAL, "rows must be >= 1");
+  int nt = 0;
+  lb_status r = upload_tiles(b, b->dtiles, threads, rows, fuse, &nt);
+  if (r != LB_OK) return r;
+  if (fuse == 2) {
+    int t1 = 0, r1 = 0;
+    default_batch_launch(b, &t1, &r1);
+    if ((r = upload_tiles(b, b->dtiles1, t1, r1, 1, &b->ntiles1)) != LB_OK) return r;
+    b->threads1 = t1;
+    b->rows1 = r1;
+  }
   b->threads = threads;
   b->rows = rows;
-  b->ntiles = (int)all.size();
+  b->ntiles = nt;
+  b->fuse = fuse;
   drop_graphs(b);
   return LB_OK;
 }
@@ -212,20 +241,37 @@ lb_status enqueue_checks(lb_batch* b, int mode, int only = -1, const int32_t* ma
   return LB_OK;
 }
 
-// Enqueue `n` steps eagerly (also used while recording a graph).
-lb_status enqueue_steps(lb_batch* b, int64_t n, bool moments_last) {
-  for (int64_t s = 0; s < n; ++s) {
+// Enqueue `n` steps eagerly (also used while recording a graph). With a
+// two-step shape, pairs of steps are one launch unless a check falls after
+// the first of them or one step is left. dry: advance the counters exactly
+// as the launches would, without launching (after a graph replay).
+lb_status enqueue_steps(lb_batch* b, int64_t n, bool moments_last, bool dry = false) {
+  const int ce = b->check_every;
+  for (int64_t s = 0; s < n;) {
+    const bool pair = b->fuse == 2 && n - s >= 2 && !(ce > 0 && (b->step + 1) % ce == 0);
+    const int k = pair ? 2 : 1;
     int flags = 0;
-    if (moments_last && s == n - 1) flags |= lbk::kWriteMoments;
+    if (moments_last && s + k == n) flags |= lbk::kWriteMoments;
     if (b->pending_shift) flags |= lbk::kApplyShift;
-    HIPCHK(lbk::launch_step(b->fp32, b->threads, b->ddesc, b->dtiles, b->ntiles, b->parity, flags,
-                            b->st));
+    if (!dry) {
+      if (pair)
+        HIPCHK(lbk::launch_step2(b->threads, b->ddesc, b->dtiles, b->ntiles, b->parity, flags, b->st));
+      else if (b->fuse == 2)
+        HIPCHK(lbk::launch_step(b->fp32, b->threads1, b->ddesc, b->dtiles1, b->ntiles1, b->parity,
+                                flags, b->st));
+      else
+        HIPCHK(lbk::launch_step(b->fp32, b->threads, b->ddesc, b->dtiles, b->ntiles, b->parity,
+                                flags, b->st));
+    }
     b->pending_shift = false;
     b->parity ^= 1;
-    b->step += 1;
-    if (b->check_every > 0 && b->step % b->check_every == 0) {
-      lb_status r = enqueue_checks(b, 0);
-      if (r != LB_OK) return r;
+    b->step += k;
+    s += k;
+    if (ce > 0 && b->step % ce == 0) {
+      if (!dry) {
+        lb_status r = enqueue_checks(b, 0);
+        if (r != LB_OK) return r;
+      }
       b->pending_shift = b->drift != 0;
     }
   }
@@ -266,13 +312,7 @@ lb_status replay(lb_batch* b) {
   }
   HIPCHK(hipGraphLaunch(b->exec[key], b->st));
   // advance the counters exactly as the recorded steps do
-  for (int s = 0; s < kGraphSteps; ++s) {
-    b->pending_shift = false;
-    b->parity ^= 1;
-    b->step += 1;
-    if (b->check_every > 0 && b->step % b->check_every == 0) b->pending_shift = b->drift != 0;
-  }
-  return LB_OK;
+  return enqueue_steps(b, kGraphSteps, false, true);
 }
 
 lb_status read_batch_status(lb_batch* b) {
@@ -331,6 +371,7 @@ lb_status lb_batch_create(int32_t count, const lb_params* p, void* dev_ws, size_
   b->ddesc = (Desc*)(b->ws + b->B.descs);
   b->dred = (ReduceOut*)(b->ws + b->B.reds);
   b->dtiles = (Tile*)(b->ws + b->B.tiles);
+  b->dtiles1 = (Tile*)(b->ws + b->B.tiles1);
   b->dsub = (Tile*)(b->ws + b->B.sub_tiles);
   b->dpart = (double*)(b->ws + b->B.part);
   b->dpoff = (int64_t*)(b->ws + b->B.part_off);
@@ -434,15 +475,21 @@ lb_status lb_batch_step_n(lb_batch* b, int64_t nsteps) {
   if (nsteps == 0) return LB_OK;
   int64_t left = nsteps;
   lb_status r;
-  // recorded runs where the step count is on the check grid; eager steps in
-  // between; the last step is always eager (it writes the moments)
+  // recorded runs where the step count is on the check grid; eager steps up
+  // to the next point where a recorded run can start; the last step is
+  // always eager (it writes the moments)
   while (left > 1) {
     if (left > kGraphSteps && graph_aligned(b)) {
       if ((r = replay(b)) != LB_OK) return r;
       left -= kGraphSteps;
     } else {
-      if ((r = enqueue_steps(b, 1, false)) != LB_OK) return r;
-      --left;
+      int64_t k = left - 1;
+      if (b->check_every > 0)
+        k = std::min<int64_t>(k, b->check_every - b->step % b->check_every);
+      else if (b->parity != 0)
+        k = 1;
+      if ((r = enqueue_steps(b, k, false)) != LB_OK) return r;
+      left -= k;
     }
   }
   if ((r = enqueue_steps(b, left, true)) != LB_OK) return r;
@@ -500,7 +547,20 @@ lb_status lb_batch_set_launch(lb_batch* b, int32_t threads, int32_t rows) {
   default_batch_launch(b, &dt, &dr);
   if (threads == 0) threads = dt;
   if (rows == 0) rows = dr;
-  return batch_tiles(b, threads, rows);
+  return batch_tiles(b, threads, rows, 1);
+}
+
+lb_status lb_batch_set_launch_fused(lb_batch* b, int32_t threads, int32_t rows) {
+  if (!b) return fail(LB_EINVAL, "batch is NULL");
+  if (threads == 0) threads = 128;
+  if (rows == 0) rows = 65;
+  return batch_tiles(b, threads, rows, 2);
+}
+
+lb_status lb_batch_get_steps_per_launch(lb_batch* b, int32_t* steps) {
+  if (!b || !steps) return fail(LB_EINVAL, "NULL argument");
+  *steps = b->fuse;
+  return LB_OK;
 }
 
 lb_status lb_batch_autotune(lb_batch* b, int32_t nsteps, int32_t* threads, int32_t* rows,
@@ -510,35 +570,43 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t nsteps, int32_t* threads, int32
   for (int i = 0; i < b->count; ++i)
     if (!b->inst[i].has_state) return fail(LB_ESTATE, "instance %d has no state", i);
   if (b->unstable_any) return fail(LB_ESTATE, "an instance was flagged unstable");
-  const int cand_t[] = {128, 256, 512};
-  const int cand_r[] = {16, 32, 64, 128, 256};
+  // (threads, rows, steps per launch); the two-step kernel's shapes with FP32
+  struct Cand {
+    int t, rw, fuse;
+  };
+  std::vector<Cand> cand;
+  for (int t : {128, 256, 512})
+    for (int rw : {16, 32, 64, 128, 256})
+      if (t != 512 || b->fp32) cand.push_back({t, rw, 1});
+  if (b->fp32)
+    for (int t : {128, 192, 256})
+      for (int rw : {17, 33, 65, 129, 257}) cand.push_back({t, rw, 2});
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   double best = 1e300;
-  int bt = b->threads, br = b->rows;
+  int bt = b->threads, br = b->rows, bf = b->fuse;
   lb_status r = LB_OK;
-  for (int t : cand_t)
-    for (int rw : cand_r) {
-      if (t == 512 && !b->fp32) continue;
-      if (r != LB_OK) break;
-      if ((r = batch_tiles(b, t, rw)) != LB_OK) break;
-      if ((r = enqueue_steps(b, 1, false)) != LB_OK) break;
-      if (hipEventRecord(e0, b->st) != hipSuccess) { r = fail(LB_EDEVICE, "event record failed"); break; }
-      if ((r = enqueue_steps(b, nsteps, false)) != LB_OK) break;
-      if (hipEventRecord(e1, b->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-        r = fail(LB_EDEVICE, "event sync failed");
-        break;
-      }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms / nsteps < best) { best = ms / nsteps; bt = t; br = rw; }
+  for (const Cand& c : cand) {
+    const int t = c.t, rw = c.rw;
+    if (r != LB_OK) break;
+    if ((r = batch_tiles(b, t, rw, c.fuse)) != LB_OK) break;
+    if ((r = enqueue_steps(b, c.fuse, false)) != LB_OK) break;
+    if (hipEventRecord(e0, b->st) != hipSuccess) { r = fail(LB_EDEVICE, "event record failed"); break; }
+    if ((r = enqueue_steps(b, nsteps, false)) != LB_OK) break;
+    if (hipEventRecord(e1, b->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      r = fail(LB_EDEVICE, "event sync failed");
+      break;
     }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms / nsteps < best) { best = ms / nsteps; bt = t; br = rw; bf = c.fuse; }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (r != LB_OK) return r;
   for (auto& I : b->inst) I.moments_valid = false;
-  if ((r = batch_tiles(b, bt, br)) != LB_OK) return r;
+  if ((r = batch_tiles(b, bt, br, bf)) != LB_OK) return r;
   if (threads) *threads = bt;
   if (rows) *rows = br;
   if (ms_per_step) *ms_per_step = best;
@@ -601,14 +669,17 @@ lb_status lb_batch_step_subset(lb_batch* b, int64_t nsteps, const int32_t* mask)
       any = true;
     }
   if (!any || nsteps == 0) return LB_OK;
-  std::vector<Tile> t = tile_list(b, b->threads, b->rows, mask);
+  // one step per launch (the buffer parity must flip once per step)
+  const int th = b->fuse == 2 ? b->threads1 : b->threads;
+  const int rw = b->fuse == 2 ? b->rows1 : b->rows;
+  std::vector<Tile> t = tile_list(b, th, rw, mask);
   HIPCHK(hipMemcpyAsync(b->dsub, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice, b->st));
   HIPCHK(hipStreamSynchronize(b->st));  // t is a host temporary
   lb_status lr = upload_list(b, mask, b->dlist_sub, &b->n_sub, &b->nb_sub);
   if (lr != LB_OK) return lr;
   for (int64_t s = 0; s < nsteps; ++s) {
     const int flags = (s == nsteps - 1) ? lbk::kWriteMoments : 0;
-    HIPCHK(lbk::launch_step(b->fp32, b->threads, b->ddesc, b->dsub, (int)t.size(), b->parity ^ (int)(s & 1),
+    HIPCHK(lbk::launch_step(b->fp32, th, b->ddesc, b->dsub, (int)t.size(), b->parity ^ (int)(s & 1),
                             flags, b->st));
   }
   lb_status r = enqueue_checks(b, 0, -1, mask);
@@ -631,7 +702,7 @@ lb_status lb_batch_drop_unstable(lb_batch* b, int32_t* dropped) {
   b->unstable_any = false;
   if ((r = upload_list(b, nullptr, b->dlist_all, &b->n_all, &b->nb_all)) != LB_OK) return r;
   // rebuild the tile table without the dropped instances (drops the graphs)
-  if ((r = batch_tiles(b, b->threads, b->rows)) != LB_OK) return r;
+  if ((r = batch_tiles(b, b->threads, b->rows, b->fuse)) != LB_OK) return r;
   if (dropped) *dropped = n;
   return LB_OK;
 }

@@ -70,6 +70,8 @@ SIGNATURES = {
     "lb_get_launch": (ctypes.c_int, [_VP, _I32P, _I32P, _I32P]),
     "lb_set_launch_fused": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "lb_get_steps_per_launch": (ctypes.c_int, [_VP, _I32P]),
+    "lb_batch_set_launch_fused": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
+    "lb_batch_get_steps_per_launch": (ctypes.c_int, [_VP, _I32P]),
     "lb_batch_set_launch": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "lb_autotune": (ctypes.c_int, [_VP, ctypes.c_int32, _I32P, _I32P, _DP]),
     "lb_batch_autotune": (ctypes.c_int, [_VP, ctypes.c_int32, _I32P, _I32P, _DP]),
@@ -355,8 +357,20 @@ class Batch:
         _check(_lib.lb_batch_status(self._h, out))
         return list(out)
 
-    def set_launch(self, threads: int = 0, rows: int = 0):
-        _check(_lib.lb_batch_set_launch(self._h, int(threads), int(rows)))
+    def set_launch(self, threads: int = 0, rows: int = 0, steps_per_launch: int = 1):
+        """Launch shape shared by all instances; steps_per_launch = 2 selects
+        the two-step kernel (FP32 only; threads 128, 192 or 256)."""
+        if steps_per_launch == 2:
+            _check(_lib.lb_batch_set_launch_fused(self._h, int(threads), int(rows)))
+        elif steps_per_launch == 1:
+            _check(_lib.lb_batch_set_launch(self._h, int(threads), int(rows)))
+        else:
+            raise ValueError("steps_per_launch must be 1 or 2")
+
+    def steps_per_launch(self) -> int:
+        v = ctypes.c_int32()
+        _check(_lib.lb_batch_get_steps_per_launch(self._h, ctypes.byref(v)))
+        return v.value
 
     def drop_unstable(self) -> int:
         """Take instances that failed a check out of the steps; returns how

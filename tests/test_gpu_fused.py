@@ -124,3 +124,46 @@ def test_fused_launch_is_validated(torch_cuda):
     assert g.steps_per_launch() == 2 and g.get_launch()[0] == 128
     g.set_launch(0, 0)
     assert g.steps_per_launch() == 1
+
+
+def _batch_instances():
+    out = []
+    for i, w in enumerate(ls.batch_draws(7, seed=23)):
+        Lx, Ly = w.Lx // 2 + 5 * i, w.Ly // 2 + 3 * i  # uneven and ragged
+        out.append(dict(Lx=Lx, Ly=Ly, T=w.T, U=w.U, N=w.N, Q=w.Q, tau=w.tau, kappa=w.kappa,
+                        fext=ls.potential_force(Lx, w.V0, w.k), y_periodic=(i % 3 == 2),
+                        seed=w.seed))
+    return out
+
+
+@pytest.mark.parametrize("check_every,launch", [(20, (128, 33)), (7, (256, 17)), (0, (192, 65))])
+def test_batch_fused_equals_one_step_batch(torch_cuda, check_every, launch):
+    # graph runs of 64 steps (32 launches), eager steps up to the check grid,
+    # single steps before checks that split a pair, subset steps
+    from paper_1307_6703_amd import Batch
+    _say("batch fused vs one-step", check_every, launch)
+    insts = _batch_instances()
+    specs = [{k: v for k, v in d.items() if k != "seed"} for d in insts]
+    drift = check_every > 0
+    a = Batch(specs, fp32=True, check_every=check_every, drift_correct=drift)
+    b = Batch(specs, fp32=True, check_every=check_every, drift_correct=drift)
+    for i, d in enumerate(insts):
+        a.init(i, ls.noisy_density(d["Lx"], d["Ly"], d["seed"]))
+        b.init(i, ls.noisy_density(d["Lx"], d["Ly"], d["seed"]))
+    b.set_launch(*launch, steps_per_launch=2)
+    assert b.steps_per_launch() == 2
+    for n in (151, 6, 77):
+        a.step(n)
+        b.step(n)
+        for i in range(len(insts)):
+            for x, y in zip(a.moments(i), b.moments(i)):
+                assert np.array_equal(x, y), (n, i)
+    mask = [1 if i % 2 else 0 for i in range(len(insts))]
+    a.step_subset(10, mask)
+    b.step_subset(10, mask)
+    a.step(3)
+    b.step(3)
+    for i in range(len(insts)):
+        for x, y in zip(a.moments(i), b.moments(i)):
+            assert np.array_equal(x, y), ("subset", i)
+    assert all(s == 0 for s in b.status())

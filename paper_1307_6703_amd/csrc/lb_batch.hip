@@ -553,7 +553,7 @@ lb_status lb_batch_set_launch(lb_batch* b, int32_t threads, int32_t rows) {
 lb_status lb_batch_set_launch_fused(lb_batch* b, int32_t threads, int32_t rows) {
   if (!b) return fail(LB_EINVAL, "batch is NULL");
   if (threads == 0) threads = 128;
-  if (rows == 0) rows = 65;
+  if (rows == 0) rows = 64;
   return batch_tiles(b, threads, rows, 2);
 }
 
@@ -580,7 +580,7 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t nsteps, int32_t* threads, int32
       if (t != 512 || b->fp32) cand.push_back({t, rw, 1});
   if (b->fp32)
     for (int t : {128, 192, 256})
-      for (int rw : {17, 33, 65, 129, 257}) cand.push_back({t, rw, 2});
+      for (int rw : {16, 32, 64, 128, 256}) cand.push_back({t, rw, 2});
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));

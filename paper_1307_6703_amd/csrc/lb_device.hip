@@ -328,15 +328,12 @@ __device__ __forceinline__ void stage_force(const Pair<R>* Bk, const Pair<R>* Md
 template <typename R>
 __device__ __forceinline__ void stage_mom(const R v[9], int wall, int ysgn, R n, R Fx, R Fy,
                                           const Sten<R>& c, R& jx, R& jy) {
-  if (wall) {
-    jx = n * (wall == 1 ? c.Ub : c.Ut);
-    jy = (R)0;
-  } else {
-    jx = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]) + (R)0.5 * Fx;
-    R py = (v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]);
-    if (ysgn < 0) py = -py;
-    jy = py + (R)0.5 * Fy;
-  }
+  const R px = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
+  R py = (v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]);
+  if (ysgn < 0) py = -py;
+  // selects, not branches: wall is uniform, both values are cheap
+  jx = wall ? n * (wall == 1 ? c.Ub : c.Ut) : px + (R)0.5 * Fx;
+  jy = wall ? (R)0 : py + (R)0.5 * Fy;
 }
 
 // Stage D gradients (Eq.(coeff)): grad n and D = d/dx j*_x + d/dy j*_y, from
@@ -565,7 +562,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
 // pipeline of step_kernel over the columns and rows the second step needs (4
 // more on each side) and keeps its post-collision populations in an LDS ring
 // of four rows instead of storing them; the second step pulls from that ring,
-// runs the same four stages 8 rows behind the first, and stores. Each
+// runs the same four stages 9 rows behind the first, and stores. Each
 // population in HBM is read and written once per two steps.
 //
 // The second step has no ghost rows: at a wall row its stages read the
@@ -575,12 +572,14 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
 // three rows on each side, cut at a wall; the first step's outputs run one
 // row further on each side that is not a wall.
 //
-// Per iteration k, four phases separated by barriers:
-//   1: A1 (row k of the first step's pipeline), A2 (second step row k-8);
-//   2: B1, B2;  3: C1, C2;  4: D1 (to the LDS ring), D2 (to HBM).
-// The second step's rings are indexed like the first's (8 rows behind, 8 is
-// 0 mod the ring sizes); A2 reads ring rows that D1 wrote in earlier
-// iterations.
+// Per iteration k, four phases with barriers after the first three:
+//   1: A1 (row k of the first step's pipeline), A2 (second step row k-9);
+//   2: B1, B2;  3: C1, C2;  4: D1 (into the ring), D2 (to HBM).
+// A2 reads ring rows k-10 .. k-8, which D1 wrote at least two iterations
+// earlier, so phase 4 needs no barrier before the next phase 1; D1 then
+// writes row k-6 over row k-10, which A2 read in phase 1 of the same
+// iteration. Ring slots are row mod ring size, so those of the second step
+// are the first step's shifted by 9.
 // ---------------------------------------------------------------------------
 template <int NT, bool MOM>
 __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ descs,
@@ -666,7 +665,7 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
   const int rbs = r2s + (ws ? 0 : 1), rbe = r2e - (we ? 0 : 1);
   const int rcs = r2s + (ws ? 0 : 2), rce = r2e - (we ? 0 : 2);
   const int rds = dir * (ofirst - S1), rde = dir * (olast - S1);
-  const int K = rde + 12;  // D2 runs on relative row k - 11
+  const int K = rde + 13;  // D2 runs on relative row k - 12
 
   // LDS: 288 (NT + 2) bytes, so four 128-thread or two 256-thread
   // workgroups fit on a CU. The force F goes from stage C to stage D of the
@@ -683,7 +682,7 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
   __shared__ R O[4][6][NT + 2];
   const int u = t + 1;
 
-  constexpr int P = kPrefetch;
+  constexpr int P = 1;
   R f[4][9], f2[4][9], pf[P][9];
   R Fr[2][2], Fr2[2][2];  // (F_x, F_y) of the row stage C last finished
   R Or[4][3];             // populations 0, 2, 4 of the ring rows
@@ -710,13 +709,46 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
     pull_row<R>(pf[j], j < K1 ? Sin : Snone, pbytes, (uint32_t)rowb, Ly, periodic,
                 map_row_any(a0 + dir * j, Ly, periodic), vc, vm, vp);
 
+  // Every stage runs on every lane and iteration, valid or not: a ring
+  // write lands in the slot of a row that no valid stage still needs, and
+  // valid stages read only rows and columns that valid stages wrote, so the
+  // idle work is harmless; without branches around the stages the compiler
+  // can interleave the two steps' instructions. Stores go through the
+  // buffers' range checks.
   for (int kb = 0; kb < K; kb += 8) {
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       const int k = kb + s;
       const int a = a0 + dir * k;
-      // ---- phase 1 -------------------------------------------------------------
-      if (k < K1) {  // A1 on row a
+      // ---- phase 1: A2 (relative row k-9) pulls from the ring (rows k-10,
+      // k-9, k-8); A1 (row a) takes the row loaded P iterations ago ---------
+      {
+        const int y = S1 + dir * (k - 9);
+        const bool lo = !periodic && y == 0, hi = !periodic && y == Ly - 1;
+        constexpr int ps = NT + 2;  // plane stride; planes 0..5 hold populations 1, 3, 5, 6, 7, 8
+        const R* Ob = &O[(s + 2) & 3][0][0];
+        const R* Oc = &O[(s + 3) & 3][0][0];
+        const R* Oa = &O[s & 3][0][0];
+        const R* Os = dir > 0 ? Ob : Oa;  // row y - 1 (sources with c_y = +1)
+        const R* On = dir > 0 ? Oa : Ob;  // row y + 1 (sources with c_y = -1)
+        const R* rb = Or[(s + 2) & 3];
+        const R* rc = Or[(s + 3) & 3];
+        const R* ra = Or[s & 3];
+        const R s2 = dir > 0 ? rb[1] : ra[1];  // population 2 of row y - 1
+        const R n4 = dir > 0 ? ra[2] : rb[2];  // population 4 of row y + 1
+        R* v = f2[(s + 3) & 3];
+        v[0] = rc[0];
+        v[1] = Oc[0 * ps + u - 1];
+        v[3] = Oc[1 * ps + u + 1];
+        v[2] = lo ? rc[2] : s2;
+        v[5] = lo ? Oc[4 * ps + u] : Os[2 * ps + u - 1];
+        v[6] = lo ? Oc[5 * ps + u] : Os[3 * ps + u + 1];
+        v[4] = hi ? rc[1] : n4;
+        v[7] = hi ? Oc[2 * ps + u] : On[4 * ps + u + 1];
+        v[8] = hi ? Oc[3 * ps + u] : On[5 * ps + u - 1];
+        nR2[(s + 7) & 7][u] = slot_sum<R>(v);
+      }
+      {
         R* v = f[s & 3];
 #pragma unroll
         for (int i = 0; i < 9; ++i) v[i] = pf[s % P][i];
@@ -731,157 +763,119 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
       }
       pull_row<R>(pf[s % P], (k + P < K1) ? Sin : Snone, pbytes, (uint32_t)rowb, Ly, periodic,
                   map_row_any(a + P * dir, Ly, periodic), vc, vm, vp);
-      {  // A2 on relative row k - 8: pull from the ring (rows k-9, k-8, k-7)
-        const int r = k - 8;
-        if (r >= r2s && r <= r2e && act2A) {
-          const int y = S1 + dir * r;
-          const bool lo = !periodic && y == 0, hi = !periodic && y == Ly - 1;
-          constexpr int ps = NT + 2;  // plane stride; planes 0..5 hold populations 1, 3, 5, 6, 7, 8
-          const R* Ob = &O[(s + 3) & 3][0][0];
-          const R* Oc = &O[s & 3][0][0];
-          const R* Oa = &O[(s + 1) & 3][0][0];
-          const R* Os = dir > 0 ? Ob : Oa;  // row y - 1 (sources with c_y = +1)
-          const R* On = dir > 0 ? Oa : Ob;  // row y + 1 (sources with c_y = -1)
-          const R* rb = Or[(s + 3) & 3];
-          const R* rc = Or[s & 3];
-          const R* ra = Or[(s + 1) & 3];
-          const R s2 = dir > 0 ? rb[1] : ra[1];  // population 2 of row y - 1
-          const R n4 = dir > 0 ? ra[2] : rb[2];  // population 4 of row y + 1
-          R* v = f2[s & 3];
-          v[0] = rc[0];
-          v[1] = Oc[0 * ps + u - 1];
-          v[3] = Oc[1 * ps + u + 1];
-          v[2] = lo ? rc[2] : s2;
-          v[5] = lo ? Oc[4 * ps + u] : Os[2 * ps + u - 1];
-          v[6] = lo ? Oc[5 * ps + u] : Os[3 * ps + u + 1];
-          v[4] = hi ? rc[1] : n4;
-          v[7] = hi ? Oc[2 * ps + u] : On[4 * ps + u + 1];
-          v[8] = hi ? Oc[3 * ps + u] : On[5 * ps + u - 1];
-          nR2[s][u] = slot_sum<R>(v);
-        }
-      }
       __syncthreads();
-      // ---- phase 2 -------------------------------------------------------------
-      if (k >= 2 && k < K1 && actB)
-        LP[(s + 3) & 3][u] = stage_lp<R>(nR[(s + 6) & 7], nR[(s + 7) & 7], nR[s], u, c);
-      {
-        const int r = k - 9;
-        if (r >= rbs && r <= rbe && act2B) {
-          const R* bh = nR2[(s + 6) & 7];
-          const R* ah = nR2[s];
-          if (ws && r == r2s) bh = ah;  // behind the first row: its mirror
-          if (we && r == r2e) ah = bh;
-          LP2[(s + 3) & 3][u] = stage_lp<R>(bh, nR2[(s + 7) & 7], ah, u, c);
-        }
-      }
-      __syncthreads();
-      // ---- phase 3 -------------------------------------------------------------
-      if (k >= 4 && k < K1 && actC) {
-        const R n = c.nbar + nR[(s + 6) & 7][u];
-        R Fx, Fy, jx, jy;
-        stage_force<R>(LP[(s + 1) & 3], LP[(s + 2) & 3], LP[(s + 3) & 3], u, n, fx3, c, Fx, Fy);
-        const RowMap m = map_row(a - 2 * dir, Ly, periodic);
-        stage_mom<R>(f[(s + 2) & 3], m.wall, m.ysgn, n, Fx, Fy, c, jx, jy);
-        JR[(s + 2) & 3][u] = Mom<R>{jx, jy};
-        Fr[s & 1][0] = Fx;
-        Fr[s & 1][1] = Fy;
-      }
+      // ---- phase 2: B1 (row a - dir), B2 (relative row k-10) -----------------
+      LP[(s + 3) & 3][u] = stage_lp<R>(nR[(s + 6) & 7], nR[(s + 7) & 7], nR[s], u, c);
       {
         const int r = k - 10;
-        if (r >= rcs && r <= rce && act2C) {
-          const Pair<R>* bh = LP2[(s + 1) & 3];
-          const Pair<R>* ah = LP2[(s + 3) & 3];
-          if (ws && r == r2s) bh = ah;
-          if (we && r == r2e) ah = bh;
-          const R n = c.nbar + nR2[(s + 6) & 7][u];
-          R Fx, Fy, jx, jy;
-          stage_force<R>(bh, LP2[(s + 2) & 3], ah, u, n, fx3, c, Fx, Fy);
-          const int y = S1 + dir * r;
-          const int wall = periodic ? 0 : (y == 0 ? 1 : (y == Ly - 1 ? 2 : 0));
-          stage_mom<R>(f2[(s + 2) & 3], wall, 1, n, Fx, Fy, c, jx, jy);
-          JR2[(s + 2) & 3][u] = Mom<R>{jx, jy};
-          Fr2[s & 1][0] = Fx;
-          Fr2[s & 1][1] = Fy;
-        }
+        const R* bh = nR2[(s + 5) & 7];
+        const R* ah = nR2[(s + 7) & 7];
+        if (ws && r == r2s) bh = ah;  // behind the first row: its mirror
+        if (we && r == r2e) ah = bh;
+        LP2[(s + 2) & 3][u] = stage_lp<R>(bh, nR2[(s + 6) & 7], ah, u, c);
       }
       __syncthreads();
-      // ---- phase 4 -------------------------------------------------------------
-      if (k >= 6 && k < K1 && actD) {  // D1 on row a - 3 dir, into the ring
-        const int dd = a - 3 * dir;
-        R g[9];
+      // ---- phase 3: C1 (row a - 2 dir), C2 (relative row k-11) ---------------
+      {
+        const int r = k - 11;
+        const Pair<R>* bh = LP2[s & 3];
+        const Pair<R>* ah = LP2[(s + 2) & 3];
+        if (ws && r == r2s) bh = ah;
+        if (we && r == r2e) ah = bh;
+        const R n1 = c.nbar + nR[(s + 6) & 7][u];
+        const R n2 = c.nbar + nR2[(s + 5) & 7][u];
+        R Fx1, Fy1, jx1, jy1, Fx2, Fy2, jx2, jy2;
+        stage_force<R>(LP[(s + 1) & 3], LP[(s + 2) & 3], LP[(s + 3) & 3], u, n1, fx3, c, Fx1, Fy1);
+        stage_force<R>(bh, LP2[(s + 1) & 3], ah, u, n2, fx3, c, Fx2, Fy2);
+        const RowMap m = map_row(a - 2 * dir, Ly, periodic);
+        const int y = S1 + dir * r;
+        const int wall2 = periodic ? 0 : (y == 0 ? 1 : (y == Ly - 1 ? 2 : 0));
+        stage_mom<R>(f[(s + 2) & 3], m.wall, m.ysgn, n1, Fx1, Fy1, c, jx1, jy1);
+        stage_mom<R>(f2[(s + 1) & 3], wall2, 1, n2, Fx2, Fy2, c, jx2, jy2);
+        JR[(s + 2) & 3][u] = Mom<R>{jx1, jy1};
+        JR2[(s + 1) & 3][u] = Mom<R>{jx2, jy2};
+        Fr[s & 1][0] = Fx1;
+        Fr[s & 1][1] = Fy1;
+        Fr2[(s + 1) & 1][0] = Fx2;
+        Fr2[(s + 1) & 1][1] = Fy2;
+      }
+      __syncthreads();
+      // ---- phase 4: D1 (row a - 3 dir) into the ring, D2 (relative row k-12)
+      // to HBM ---------------------------------------------------------------
+      if (k >= 6 && k < K1) {
+        const int dd1 = a - 3 * dir;
+        R g1[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = f[(s + 1) & 3][i];
-        R dnx, dny, D;
+        for (int i = 0; i < 9; ++i) g1[i] = f[(s + 1) & 3][i];
+        R dnx1, dny1, D1;
         stage_grad<R>(nR[(s + 4) & 7], nR[(s + 5) & 7], nR[(s + 6) & 7], JR[s & 3],
-                      JR[(s + 1) & 3], JR[(s + 2) & 3], u, (R)1, (R)1, c, dnx, dny, D);
-        const Mom<R> mC = JR[(s + 1) & 3][u];
-        const R Fx = Fr[(s + 1) & 1][0], Fy = Fr[(s + 1) & 1][1];
-        const R dn = nR[(s + 5) & 7][u];
-        const R n = c.nbar + dn;
-        const R rn = fast_rcp<R>(n);
-        const int wall = periodic ? 0 : (dd == 0 ? 1 : (dd == Ly - 1 ? 2 : 0));
-        stage_wall<R>(g, wall, dn, n, Fx, Fy, c);
-        collide<R>(g, cl, n, dn, mC.jx, mC.jy, rn, Fx, Fy, dnx, dny, D);
+                      JR[(s + 1) & 3], JR[(s + 2) & 3], u, (R)1, (R)1, c, dnx1, dny1, D1);
+        const Mom<R> m1 = JR[(s + 1) & 3][u];
+        const R Fx1 = Fr[(s + 1) & 1][0], Fy1 = Fr[(s + 1) & 1][1];
+        const R dn1 = nR[(s + 5) & 7][u];
+        const R n1 = c.nbar + dn1;
+        const R rn1 = fast_rcp<R>(n1);
+        const int wall1 = periodic ? 0 : (dd1 == 0 ? 1 : (dd1 == Ly - 1 ? 2 : 0));
+        stage_wall<R>(g1, wall1, dn1, n1, Fx1, Fy1, c);
+        collide<R>(g1, cl, n1, dn1, m1.jx, m1.jy, rn1, Fx1, Fy1, dnx1, dny1, D1);
         R* o = &O[(s + 2) & 3][0][0];
         constexpr int ps = NT + 2;
-        o[0 * ps + u] = g[1];
-        o[1 * ps + u] = g[3];
-        o[2 * ps + u] = g[5];
-        o[3 * ps + u] = g[6];
-        o[4 * ps + u] = g[7];
-        o[5 * ps + u] = g[8];
-        Or[(s + 2) & 3][0] = g[0];
-        Or[(s + 2) & 3][1] = g[2];
-        Or[(s + 2) & 3][2] = g[4];
+        o[0 * ps + u] = g1[1];
+        o[1 * ps + u] = g1[3];
+        o[2 * ps + u] = g1[5];
+        o[3 * ps + u] = g1[6];
+        o[4 * ps + u] = g1[7];
+        o[5 * ps + u] = g1[8];
+        Or[(s + 2) & 3][0] = g1[0];
+        Or[(s + 2) & 3][1] = g1[2];
+        Or[(s + 2) & 3][2] = g1[4];
       }
-      {  // D2 on relative row k - 11, to HBM
-        const int r = k - 11;
-        const bool validD = r >= rds && r <= rde;
-        const int dd = S1 + dir * r;
-        R g[9];
+      {
+        const int r = k - 12;
+        const int dd2 = S1 + dir * r;
+        const bool valid2 = r >= rds && r <= rde;
+        R g2[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = f2[(s + 1) & 3][i];
-        R n = (R)1, ux = (R)0, uy = (R)0;
-        if (validD && act2D) {
-          const R* bh = nR2[(s + 4) & 7];
-          const R* ah = nR2[(s + 6) & 7];
-          const Mom<R>* Jb = JR2[s & 3];
-          const Mom<R>* Ja = JR2[(s + 2) & 3];
-          R sb = (R)1, sa = (R)1;
-          if (ws && r == r2s) { bh = ah; Jb = Ja; sb = (R)-1; }
-          if (we && r == r2e) { ah = bh; Ja = Jb; sa = (R)-1; }
-          R dnx, dny, D;
-          stage_grad<R>(bh, nR2[(s + 5) & 7], ah, Jb, JR2[(s + 1) & 3], Ja, u, sb, sa, c, dnx,
-                        dny, D);
-          const Mom<R> mC = JR2[(s + 1) & 3][u];
-          const R Fx = Fr2[(s + 1) & 1][0], Fy = Fr2[(s + 1) & 1][1];
-          const R dn = nR2[(s + 5) & 7][u];
-          n = c.nbar + dn;
-          const R rn = fast_rcp<R>(n);
-          ux = mC.jx * rn;
-          uy = mC.jy * rn;
-          const int wall = periodic ? 0 : (dd == 0 ? 1 : (dd == Ly - 1 ? 2 : 0));
-          stage_wall<R>(g, wall, dn, n, Fx, Fy, c);
-          collide<R>(g, cl, n, dn, mC.jx, mC.jy, rn, Fx, Fy, dnx, dny, D);
+        for (int i = 0; i < 9; ++i) g2[i] = f2[s & 3][i];
+        R n2 = (R)1, ux2 = (R)0, uy2 = (R)0;
+        if (valid2) {
+        const R* bh = nR2[(s + 3) & 7];
+        const R* ah = nR2[(s + 5) & 7];
+        const Mom<R>* Jb = JR2[(s + 3) & 3];
+        const Mom<R>* Ja = JR2[(s + 1) & 3];
+        R sb = (R)1, sa = (R)1;
+        if (ws && r == r2s) { bh = ah; Jb = Ja; sb = (R)-1; }
+        if (we && r == r2e) { ah = bh; Ja = Jb; sa = (R)-1; }
+        R dnx2, dny2, D2;
+        stage_grad<R>(bh, nR2[(s + 4) & 7], ah, Jb, JR2[s & 3], Ja, u, sb, sa, c, dnx2, dny2, D2);
+        const Mom<R> m2 = JR2[s & 3][u];
+        const R Fx2 = Fr2[s & 1][0], Fy2 = Fr2[s & 1][1];
+        const R dn2 = nR2[(s + 4) & 7][u];
+        n2 = c.nbar + dn2;
+        const R rn2 = fast_rcp<R>(n2);
+        ux2 = m2.jx * rn2;
+        uy2 = m2.jy * rn2;
+        const int wall2 = periodic ? 0 : (dd2 == 0 ? 1 : (dd2 == Ly - 1 ? 2 : 0));
+        stage_wall<R>(g2, wall2, dn2, n2, Fx2, Fy2, c);
+        collide<R>(g2, cl, n2, dn2, m2.jx, m2.jy, rn2, Fx2, Fy2, dnx2, dny2, D2);
         }
-        const __amdgpu_buffer_rsrc_t so = validD ? Sout : Snone;
-        int yy = dd % Ly;
-        if (yy < 0) yy += Ly;
-        const uint32_t roff = validD ? (uint32_t)yy * (uint32_t)rowb : 0u;
+        // output rows lie in [0, Ly) (y0 .. y1-1 of the tile), periodic or not
+        const __amdgpu_buffer_rsrc_t so = valid2 ? Sout : Snone;
+        const int yy = valid2 ? dd2 : 0;
+        const uint32_t roff = (uint32_t)yy * (uint32_t)rowb;
         const int vst = act2D ? vc : arrb;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) buf_st(g[i], so, vst, (int)((uint32_t)i * pbytes + roff));
+        for (int i = 0; i < 9; ++i) buf_st(g2[i], so, vst, (int)((uint32_t)i * pbytes + roff));
         if (MOM) {
           const int momb = (int)(3 * nn * 8);
-          const __amdgpu_buffer_rsrc_t mo = make_rsrc(d.mom, validD ? momb : 0);
+          const __amdgpu_buffer_rsrc_t mo = make_rsrc(d.mom, valid2 ? momb : 0);
           const int vo = act2D ? xc * 8 : momb;
-          const int ro = validD ? yy * Lx * 8 : 0;
-          buf_st((double)n, mo, vo, ro);
-          buf_st((double)ux, mo, vo, (int)(nn * 8) + ro);
-          buf_st((double)uy, mo, vo, (int)(2 * nn * 8) + ro);
+          const int ro = yy * Lx * 8;
+          buf_st((double)n2, mo, vo, ro);
+          buf_st((double)ux2, mo, vo, (int)(nn * 8) + ro);
+          buf_st((double)uy2, mo, vo, (int)(2 * nn * 8) + ro);
         }
       }
-      __syncthreads();
     }
   }
 }

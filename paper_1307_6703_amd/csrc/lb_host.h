@@ -123,7 +123,7 @@ inline int resident_slots(const lb_params* p, int threads) {
 
 // Rows per chunk for a target number of chunks: a height of `mod` mod 8 so
 // the kernel's 8-row unrolled march has no idle tail (2 for the one-step
-// kernel, whose march is rows + 6 long; 1 for the two-step kernel, rows + 15).
+// kernel, whose march is rows + 6 long; 0 for the two-step kernel, rows + 16).
 inline int rows_for_chunks(int Ly, int chunks, int mod = 2) {
   int rows = (Ly + std::max(chunks, 1) - 1) / std::max(chunks, 1);
   rows = ((std::max(rows, 8 + mod) - mod + 7) / 8) * 8 + mod;
@@ -159,7 +159,7 @@ inline int fused_resident_slots(int threads) {
 
 inline int fused_default_rows(const lb_params* p, int threads, int rounds = 1) {
   const int strips = (p->Lx + threads - 15) / (threads - 14);
-  return rows_for_chunks(p->Ly, rounds * fused_resident_slots(threads) / strips, 1);
+  return rows_for_chunks(p->Ly, rounds * fused_resident_slots(threads) / strips, 0);
 }
 
 // Tiles of one lattice: strips of `threads - 2 halo` columns (halo 3 for the

@@ -96,10 +96,12 @@ def batched_bench(steps: int, seed: int = 1307):
         return b
 
     # a draw whose lattice fails a stability check within the run (a deep
-    # quench under strong shear can) is replaced by the next draw
+    # quench under strong shear can) is replaced by the next draw; the
+    # screening covers the autotuner's steps (about 350), the warm-up and the
+    # timed steps
     pool = ls.batch_draws(128, seed=seed)
     scr = batch_of(pool)
-    scr.step(steps + 200)
+    scr.step(steps + 600)
     status = scr.status()
     scr.close()
     draws = [w for w, st in zip(pool, status) if st == 0][:96]

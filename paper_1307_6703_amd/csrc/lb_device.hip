@@ -682,6 +682,8 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
   __shared__ R O[4][6][NT + 2];
   const int u = t + 1;
 
+  // one row in flight: an iteration of two steps outlasts the load latency,
+  // and the registers are scarce (two rows measured the same)
   constexpr int P = 1;
   R f[4][9], f2[4][9], pf[P][9];
   R Fr[2][2], Fr2[2][2];  // (F_x, F_y) of the row stage C last finished
@@ -839,25 +841,25 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
         for (int i = 0; i < 9; ++i) g2[i] = f2[s & 3][i];
         R n2 = (R)1, ux2 = (R)0, uy2 = (R)0;
         if (valid2) {
-        const R* bh = nR2[(s + 3) & 7];
-        const R* ah = nR2[(s + 5) & 7];
-        const Mom<R>* Jb = JR2[(s + 3) & 3];
-        const Mom<R>* Ja = JR2[(s + 1) & 3];
-        R sb = (R)1, sa = (R)1;
-        if (ws && r == r2s) { bh = ah; Jb = Ja; sb = (R)-1; }
-        if (we && r == r2e) { ah = bh; Ja = Jb; sa = (R)-1; }
-        R dnx2, dny2, D2;
-        stage_grad<R>(bh, nR2[(s + 4) & 7], ah, Jb, JR2[s & 3], Ja, u, sb, sa, c, dnx2, dny2, D2);
-        const Mom<R> m2 = JR2[s & 3][u];
-        const R Fx2 = Fr2[s & 1][0], Fy2 = Fr2[s & 1][1];
-        const R dn2 = nR2[(s + 4) & 7][u];
-        n2 = c.nbar + dn2;
-        const R rn2 = fast_rcp<R>(n2);
-        ux2 = m2.jx * rn2;
-        uy2 = m2.jy * rn2;
-        const int wall2 = periodic ? 0 : (dd2 == 0 ? 1 : (dd2 == Ly - 1 ? 2 : 0));
-        stage_wall<R>(g2, wall2, dn2, n2, Fx2, Fy2, c);
-        collide<R>(g2, cl, n2, dn2, m2.jx, m2.jy, rn2, Fx2, Fy2, dnx2, dny2, D2);
+          const R* bh = nR2[(s + 3) & 7];
+          const R* ah = nR2[(s + 5) & 7];
+          const Mom<R>* Jb = JR2[(s + 3) & 3];
+          const Mom<R>* Ja = JR2[(s + 1) & 3];
+          R sb = (R)1, sa = (R)1;
+          if (ws && r == r2s) { bh = ah; Jb = Ja; sb = (R)-1; }
+          if (we && r == r2e) { ah = bh; Ja = Jb; sa = (R)-1; }
+          R dnx2, dny2, D2;
+          stage_grad<R>(bh, nR2[(s + 4) & 7], ah, Jb, JR2[s & 3], Ja, u, sb, sa, c, dnx2, dny2, D2);
+          const Mom<R> m2 = JR2[s & 3][u];
+          const R Fx2 = Fr2[s & 1][0], Fy2 = Fr2[s & 1][1];
+          const R dn2 = nR2[(s + 4) & 7][u];
+          n2 = c.nbar + dn2;
+          const R rn2 = fast_rcp<R>(n2);
+          ux2 = m2.jx * rn2;
+          uy2 = m2.jy * rn2;
+          const int wall2 = periodic ? 0 : (dd2 == 0 ? 1 : (dd2 == Ly - 1 ? 2 : 0));
+          stage_wall<R>(g2, wall2, dn2, n2, Fx2, Fy2, c);
+          collide<R>(g2, cl, n2, dn2, m2.jx, m2.jy, rn2, Fx2, Fy2, dnx2, dny2, D2);
         }
         // output rows lie in [0, Ly) (y0 .. y1-1 of the tile), periodic or not
         const __amdgpu_buffer_rsrc_t so = valid2 ? Sout : Snone;

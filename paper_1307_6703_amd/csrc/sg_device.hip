@@ -31,9 +31,15 @@ constexpr int NTH = 256; // threads per workgroup
 __device__ __forceinline__ float bf2f(bf16 v) { return (float)v; }
 __device__ __forceinline__ bf16 f2bf(float v) { return (bf16)v; }  // round to nearest even
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with the hardware reciprocal (about 1 ulp in FP32,
+// far below the bf16 rounding the results go through) instead of an IEEE
+// division, which costs about ten instructions.
+__device__ __forceinline__ float sigmoid(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
+__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 __device__ __forceinline__ float silu_grad(float z) {
-  const float s = 1.0f / (1.0f + __expf(-z));
+  const float s = sigmoid(z);
   return s * (1.0f + z * (1.0f - s));
 }
 
@@ -61,25 +67,44 @@ struct ConvShape {
   static constexpr int SE = CO + 4;   // LDS stride (floats) of one output pixel
 };
 
+// The 16-byte chunks a thread loads for every tile: chunk j is input pixel
+// (row, col) of the tile (with its 1-pixel halo), channels 8 c .. 8 c + 7.
+// These depend only on the thread, so they are worked out once.
 template <int CI, int CO>
-__device__ __forceinline__ void conv_load_tile(uint4* pre, const bf16* x,
+struct TileChunks {
+  int row[ConvShape<CI, CO>::PER], col[ConvShape<CI, CO>::PER], c[ConvShape<CI, CO>::PER];
+  __device__ __forceinline__ TileChunks() {
+    using S = ConvShape<CI, CO>;
+#pragma unroll
+    for (int j = 0; j < S::PER; ++j) {
+      const int i = threadIdx.x + j * NTH;
+      const int pix = i / S::CH;
+      c[j] = i % S::CH;
+      col[j] = pix % S::TCOLS;
+      row[j] = i < S::NLD ? pix / S::TCOLS : -(1 << 20);  // past the last chunk: never loaded
+    }
+  }
+};
+
+template <int CI, int CO>
+__device__ __forceinline__ void conv_load_tile(uint4* pre, const bf16* x, const TileChunks<CI, CO>& tc,
                                                int tile, int tilesX, int tilesY, int H, int W) {
   using S = ConvShape<CI, CO>;
   const int tx = tile % tilesX, ty = (tile / tilesX) % tilesY, img = tile / (tilesX * tilesY);
   const int x0 = tx * TW, h0 = ty * TR;
+  const bf16* xi = x + (int64_t)img * H * W * CI;
 #pragma unroll
   for (int j = 0; j < S::PER; ++j) {
-    const int i = threadIdx.x + j * NTH;
     uint4 v = {0u, 0u, 0u, 0u};
-    if (i < S::NLD) {
-      const int c = i % S::CH, pix = i / S::CH;
-      const int col = pix % S::TCOLS, row = pix / S::TCOLS;
-      const int h = h0 - 1 + row;
-      int xx = (x0 - 1 + col) % W;
+    const int h = h0 - 1 + tc.row[j];
+    int xx = x0 - 1 + tc.col[j];  // in [-1, x0 + TW]: periodic in x
+    if (W >= S::TCOLS) {
+      xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
+    } else {
+      xx %= W;
       if (xx < 0) xx += W;
-      if (h >= 0 && h < H)
-        v = *(const uint4*)(x + (((int64_t)img * H + h) * W + xx) * CI + c * 8);
     }
+    if (h >= 0 && h < H) v = *(const uint4*)(xi + ((int64_t)h * W + xx) * CI + tc.c[j] * 8);
     pre[j] = v;
   }
 }
@@ -103,8 +128,9 @@ __global__ __launch_bounds__(NTH) void conv_kernel(ConvArgs a) {
   const int ntiles = tilesX * tilesY * a.B;
   const int wave = tid >> 6, lane = tid & 63, lm = lane & 15, lg = lane >> 4;
 
+  const TileChunks<CI, CO> tc;
   uint4 pre[S::PER];
-  if (blockIdx.x < ntiles) conv_load_tile<CI, CO>(pre, a.x, blockIdx.x, tilesX, tilesY, a.H, a.W);
+  if (blockIdx.x < ntiles) conv_load_tile<CI, CO>(pre, a.x, tc, blockIdx.x, tilesX, tilesY, a.H, a.W);
 
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int tx = tile % tilesX;
@@ -115,14 +141,11 @@ __global__ __launch_bounds__(NTH) void conv_kernel(ConvArgs a) {
 #pragma unroll
     for (int j = 0; j < S::PER; ++j) {
       const int i = tid + j * NTH;
-      if (i < S::NLD) {
-        const int c = i % S::CH, pix = i / S::CH;
-        *(uint4*)&sx[pix * PX + c * 8] = pre[j];
-      }
+      if (i < S::NLD) *(uint4*)&sx[(tc.row[j] * TCOLS + tc.col[j]) * PX + tc.c[j] * 8] = pre[j];
     }
     __syncthreads();
     if (tile + (int)gridDim.x < ntiles)  // in flight during the matrix work
-      conv_load_tile<CI, CO>(pre, a.x, tile + gridDim.x, tilesX, tilesY, a.H, a.W);
+      conv_load_tile<CI, CO>(pre, a.x, tc, tile + gridDim.x, tilesX, tilesY, a.H, a.W);
 
     f32x4 acc[4][NS];
 #pragma unroll
@@ -171,12 +194,41 @@ __global__ __launch_bounds__(NTH) void conv_kernel(ConvArgs a) {
         for (int c = 0; c < a.nout; ++c) a.yf[p * a.nout + c] = se[i * SE + c];
       }
     } else {
+      // NTH threads cover the TR x TW x CO/8 vectors of a tile in exactly
+      // CO/8 items each. The global inputs of all items (residual, previous
+      // pre-activation) are loaded before any store, so their latencies
+      // overlap instead of adding up item by item; a residual that is this
+      // layer's own input comes from the tile already in LDS.
       constexpr int C8 = CO / 8;
-      for (int i = tid; i < TR * TW * C8; i += NTH) {
+      static_assert(TR * TW == NTH, "one epilogue item per thread and 8 channels");
+      const bool res_in_tile = MODE == FWD_RES && a.res == a.x;
+      int64_t off[C8];
+      bool ok[C8];
+      bf16x8 rr[C8], zp[C8];
+#pragma unroll
+      for (int it = 0; it < C8; ++it) {
+        const int i = tid + it * NTH;
         const int c8 = i % C8, pi = i / C8;
         const int row = pi / TW, px = pi % TW, h = h0 + row, xx = x0 + px;
-        if (h >= a.H || xx >= a.W) continue;
-        const int64_t off = (((int64_t)img * a.H + h) * a.W + xx) * CO + c8 * 8;
+        ok[it] = h < a.H && xx < a.W;
+        off[it] = (((int64_t)img * a.H + (ok[it] ? h : 0)) * a.W + (ok[it] ? xx : 0)) * CO + c8 * 8;
+        rr[it] = bf16x8{};
+        zp[it] = bf16x8{};
+        if (MODE == FWD_RES) {
+          if (res_in_tile)
+            rr[it] = *(const bf16x8*)&sx[((row + 1) * TCOLS + (px + 1)) * PX + c8 * 8];
+          else if (ok[it])
+            rr[it] = *(const bf16x8*)(a.res + off[it]);
+        } else if (MODE == BWD && ok[it]) {
+          if (a.res) rr[it] = *(const bf16x8*)(a.res + off[it]);
+          zp[it] = *(const bf16x8*)(a.zprev + off[it]);
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < C8; ++it) {
+        if (!ok[it]) continue;
+        const int i = tid + it * NTH;
+        const int c8 = i % C8, pi = i / C8;
         const float4 v0 = *(const float4*)&se[pi * SE + c8 * 8];
         const float4 v1 = *(const float4*)&se[pi * SE + c8 * 8 + 4];
         const float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
@@ -188,25 +240,21 @@ __global__ __launch_bounds__(NTH) void conv_kernel(ConvArgs a) {
             zo[j] = f2bf(v[j]);
           }
         } else if (MODE == FWD_RES) {
-          const bf16x8 rr = *(const bf16x8*)(a.res + off);
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
-            yo[j] = f2bf(bf2f(rr[j]) + silu(v[j]));
+            yo[j] = f2bf(bf2f(rr[it][j]) + silu(v[j]));
             zo[j] = f2bf(v[j]);
           }
         } else {  // BWD: v = dL/dh of this layer's input (+ the residual path)
-          bf16x8 rr = bf16x8{};
-          if (a.res) rr = *(const bf16x8*)(a.res + off);
-          const bf16x8 zp = *(const bf16x8*)(a.zprev + off);
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
-            const float g = v[j] + bf2f(rr[j]);
+            const float g = v[j] + bf2f(rr[it][j]);
             zo[j] = f2bf(g);
-            yo[j] = f2bf(g * silu_grad(bf2f(zp[j])));
+            yo[j] = f2bf(g * silu_grad(bf2f(zp[it][j])));
           }
         }
-        *(bf16x8*)(a.y + off) = yo;
-        if (a.z) *(bf16x8*)(a.z + off) = zo;
+        *(bf16x8*)(a.y + off[it]) = yo;
+        if (a.z) *(bf16x8*)(a.z + off[it]) = zo;
       }
     }
   }

@@ -53,6 +53,9 @@ CASES = [
     (100, 5, True, (128, 8), 21),
     (57, 12, False, (256, 8), 30),       # one strip wider than the lattice
     (514, 40, True, (192, 8), 12),
+    (1, 9, False, (128, 8), 14),         # one column: every pull wraps onto itself
+    (2, 6, True, (128, 8), 9),
+    (115, 33, False, (128, 1), 10),      # chunks of 8 rows (the minimum), one column past a strip
 ]
 
 

@@ -232,8 +232,14 @@ lb_status lb_create(const lb_params* p, void* dev_ws, size_t ws_bytes, void* hip
   if (hipMemcpyAsync(h->dred, &z, sizeof z, hipMemcpyHostToDevice, h->st) != hipSuccess)
     return cleanup(fail(LB_EDEVICE, "clearing the check block failed"));
   if ((r = upload_desc(h)) != LB_OK) return cleanup(r);
-  const int th = default_threads(p);
-  if ((r = set_tiles(h, th, default_rows(p, th))) != LB_OK) return cleanup(r);
+  // default shape: two steps per launch for FP32 lattices of at least 2^20
+  // nodes whose strips are mostly interior columns, else one step per launch
+  if (p->fp32 && (int64_t)p->Lx * p->Ly >= ((int64_t)1 << 20) && p->Lx >= 256) {
+    if ((r = set_tiles(h, 128, fused_default_rows(p, 128), 2)) != LB_OK) return cleanup(r);
+  } else {
+    const int th = default_threads(p);
+    if ((r = set_tiles(h, th, default_rows(p, th))) != LB_OK) return cleanup(r);
+  }
   *out = h;
   return LB_OK;
 }

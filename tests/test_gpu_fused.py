@@ -170,3 +170,15 @@ def test_batch_fused_equals_one_step_batch(torch_cuda, check_every, launch):
         for x, y in zip(a.moments(i), b.moments(i)):
             assert np.array_equal(x, y), ("subset", i)
     assert all(s == 0 for s in b.status())
+
+
+def test_default_shape(torch_cuda):
+    from paper_1307_6703_amd import Lattice
+    big = Lattice(2048, 512, fp32=True)
+    assert big.steps_per_launch() == 2 and big.get_launch()[0] == 128
+    big.close()
+    for kw in (dict(Lx=2048, Ly=512, fp32=False), dict(Lx=300, Ly=70, fp32=True),
+               dict(Lx=128, Ly=8192, fp32=True)):
+        g = Lattice(kw.pop("Lx"), kw.pop("Ly"), **kw)
+        assert g.steps_per_launch() == 1, kw
+        g.close()

@@ -1,6 +1,8 @@
 // Device code: the fused lattice Boltzmann step for a van der Waals fluid
-// (Coclite, Gonnella, Lamura, arXiv:1307.6703, Sec. II) for gfx950, plus the
-// initial-state, reduction and population-conversion kernels.
+// (Coclite, Gonnella, Lamura, arXiv:1307.6703, Sec. II) for gfx950, one step
+// per launch (step_kernel) or two with the intermediate populations kept on
+// chip (step2_kernel), plus the initial-state, reduction and
+// population-conversion kernels.
 //
 // Lattice units throughout (dx = dt = 1, c_i in {0,+-1}^2); the host converts
 // the paper's tau and kappa. Populations are stored as g_i = f_i - w^_i nbar,
@@ -560,10 +562,11 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
 // Two time steps per launch (FP32). A workgroup of NT threads owns a strip of
 // NT-14 columns; thread t works on column x0-7+t. The first step runs the
 // pipeline of step_kernel over the columns and rows the second step needs (4
-// more on each side) and keeps its post-collision populations in an LDS ring
-// of four rows instead of storing them; the second step pulls from that ring,
-// runs the same four stages 9 rows behind the first, and stores. Each
-// population in HBM is read and written once per two steps.
+// more on each side) and keeps its post-collision populations in a ring of
+// four rows instead of storing them (populations 1, 3, 5-8, which move along
+// x, in LDS; 0, 2 and 4 in the thread's registers); the second step pulls
+// from that ring, runs the same four stages 9 rows behind the first, and
+// stores. Each population in HBM is read and written once per two steps.
 //
 // The second step has no ghost rows: at a wall row its stages read the
 // mirror image of the row inside the lattice where the first step reads a

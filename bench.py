@@ -38,7 +38,13 @@ TUNED = os.path.join(ROOT, "paper_1307_6703_amd", "tuned_launch.json")
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    """SHA-256 prefix of the kernel source with comments and blank space
+    removed, so that counters stay attached to the code they measured."""
+    import re
+    src = open(KERNEL_SOURCE).read()
+    src = re.sub(r"//[^\n]*", "", src)
+    src = " ".join(src.split())
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
 def tuned_launch(key: str):

@@ -25,8 +25,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int TW = 64;   // output columns per conv tile
-constexpr int TR = 4;    // output rows per conv tile (one per wave)
-constexpr int NTH = 256; // threads per workgroup
+constexpr int TR = 8;    // output rows per conv tile (one per wave)
+constexpr int CNT = 512; // threads per conv workgroup (TR waves)
+constexpr int EH = 4;    // rows per pass of the conv epilogue
+constexpr int NTH = 256; // threads per workgroup of the other kernels
 
 __device__ __forceinline__ float bf2f(bf16 v) { return (float)v; }
 __device__ __forceinline__ bf16 f2bf(float v) { return (bf16)v; }  // round to nearest even
@@ -49,11 +51,13 @@ __host__ __device__ constexpr int kpad() { return (9 * CI + 31) / 32 * 32; }
 // ---------------------------------------------------------------------------
 // 3x3 convolution (forward, or input-gradient with flipped weights).
 // Persistent workgroups: the packed weights are staged in LDS once, then each
-// workgroup walks tiles of TR rows x TW columns of one image. Each wave owns
-// one output row: 4 M-subtiles of 16 pixels by CO/16 N-subtiles. The next
-// tile's input is loaded into registers while the matrix cores work on the
-// current one; results go through LDS (FP32) so that the epilogue reads and
-// writes whole 16-byte vectors of 8 channels.
+// workgroup walks tiles of TR rows x TW columns of one image. Each of its TR
+// waves owns one output row: 4 M-subtiles of 16 pixels by CO/16 N-subtiles.
+// The next tile's input is loaded into registers while the matrix cores work
+// on the current one; results go through LDS (FP32, in the input tile's
+// buffer, half the rows at a time) so that the epilogue reads and writes
+// whole 16-byte vectors of 8 channels. Eight waves per workgroup and about
+// 115 KB of LDS: two waves per SIMD.
 // ---------------------------------------------------------------------------
 template <int CI, int CO>
 struct ConvShape {
@@ -63,7 +67,7 @@ struct ConvShape {
   static constexpr int TCOLS = TW + 2, TROWS = TR + 2;
   static constexpr int CH = CI / 8;   // 16-byte chunks per input pixel
   static constexpr int NLD = TROWS * TCOLS * CH;
-  static constexpr int PER = (NLD + NTH - 1) / NTH;  // input chunks per thread
+  static constexpr int PER = (NLD + CNT - 1) / CNT;  // input chunks per thread
   static constexpr int SE = CO + 4;   // LDS stride (floats) of one output pixel
 };
 
@@ -77,7 +81,7 @@ struct TileChunks {
     using S = ConvShape<CI, CO>;
 #pragma unroll
     for (int j = 0; j < S::PER; ++j) {
-      const int i = threadIdx.x + j * NTH;
+      const int i = threadIdx.x + j * CNT;
       const int pix = i / S::CH;
       c[j] = i % S::CH;
       col[j] = pix % S::TCOLS;
@@ -110,16 +114,21 @@ __device__ __forceinline__ void conv_load_tile(uint4* pre, const bf16* x, const 
 }
 
 template <int CI, int CO, int MODE>
-__global__ __launch_bounds__(NTH) void conv_kernel(ConvArgs a) {
+__global__ __launch_bounds__(CNT) void conv_kernel(ConvArgs a) {
   using S = ConvShape<CI, CO>;
   constexpr int KP = S::KP, NS = S::NS, PX = S::PX, WS = S::WS, TCOLS = S::TCOLS;
   constexpr int K = S::K, SE = S::SE;
-  __shared__ __attribute__((aligned(16))) bf16 sx[S::TROWS * TCOLS * PX];
+  constexpr int C8 = CO / 8;
+  // The input tile (bf16) and, once the matrix work is done, the FP32 output
+  // of half the tile's rows share one LDS buffer.
+  constexpr int SX_BYTES = S::TROWS * TCOLS * PX * 2, SE_BYTES = EH * TW * SE * 4;
+  __shared__ __attribute__((aligned(16))) unsigned char sbuf[SX_BYTES > SE_BYTES ? SX_BYTES : SE_BYTES];
   __shared__ __attribute__((aligned(16))) bf16 sw[CO * WS];
-  __shared__ __attribute__((aligned(16))) float se[TR * TW * SE];
+  bf16* sx = (bf16*)sbuf;
+  float* se = (float*)sbuf;
 
   const int tid = threadIdx.x;
-  for (int i = tid; i < CO * (KP / 8); i += NTH) {
+  for (int i = tid; i < CO * (KP / 8); i += CNT) {
     const int co = i / (KP / 8), c = i % (KP / 8);
     *(uint4*)&sw[co * WS + c * 8] = ((const uint4*)a.w)[i];
   }
@@ -137,10 +146,10 @@ __global__ __launch_bounds__(NTH) void conv_kernel(ConvArgs a) {
     const int ty = (tile / tilesX) % tilesY;
     const int img = tile / (tilesX * tilesY);
     const int x0 = tx * TW, h0 = ty * TR;
-    __syncthreads();  // the previous tile's readers of sx and se are done (and sw is staged)
+    __syncthreads();  // the previous tile's readers of sbuf are done (and sw is staged)
 #pragma unroll
     for (int j = 0; j < S::PER; ++j) {
-      const int i = tid + j * NTH;
+      const int i = tid + j * CNT;
       if (i < S::NLD) *(uint4*)&sx[(tc.row[j] * TCOLS + tc.col[j]) * PX + tc.c[j] * 8] = pre[j];
     }
     __syncthreads();
@@ -172,90 +181,108 @@ __global__ __launch_bounds__(NTH) void conv_kernel(ConvArgs a) {
       }
     }
 
-    // D[m][n] -> pixel (wave, 16 ms + 4 lg + r), channel 16 ns + lm, plus the bias
+    // Epilogue in two passes of EH rows: the waves of those rows put their
+    // results (plus the bias) into LDS, then all threads turn them into whole
+    // 16-byte vectors of 8 channels (coalesced). Work item i of a pass is
+    // pixel i / C8 of its rows, channels 8 (i % C8) .. +7. The global inputs
+    // of a thread's items (residual, previous pre-activation) are loaded
+    // before any store so their latencies overlap; a residual that is this
+    // layer's own input is read from the tile, before the output overwrites it.
+    constexpr int NIT = (EH * TW * C8 + CNT - 1) / CNT;  // items per thread and pass
+    const bool res_in_tile = MODE == FWD_RES && a.res == a.x;
+    bf16x8 rt[2][NIT];
+    if (MODE == FWD_RES && res_in_tile) {
 #pragma unroll
-    for (int ns = 0; ns < NS; ++ns) {
-      const int co = ns * 16 + lm;
-      const float bv = (a.bias && (MODE != FWD_OUT || co < a.nout)) ? a.bias[co] : 0.f;
+      for (int p = 0; p < 2; ++p)
 #pragma unroll
-      for (int ms = 0; ms < 4; ++ms)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          se[(wave * TW + ms * 16 + lg * 4 + r) * SE + co] = acc[ms][ns][r] + bv;
+        for (int it = 0; it < NIT; ++it) {
+          const int i = tid + it * CNT;
+          const int pi = i / C8, c8 = i % C8;
+          const int row = p * EH + pi / TW, px = pi % TW;
+          rt[p][it] = i < EH * TW * C8 ? *(const bf16x8*)&sx[((row + 1) * TCOLS + (px + 1)) * PX + c8 * 8]
+                                       : bf16x8{};
+        }
     }
-    __syncthreads();
-
-    // epilogue: one 8-channel vector per work item, coalesced
-    if (MODE == FWD_OUT) {
-      for (int i = tid; i < TR * TW; i += NTH) {
-        const int row = i / TW, px = i % TW, h = h0 + row, xx = x0 + px;
-        if (h >= a.H || xx >= a.W) continue;
-        const int64_t p = ((int64_t)img * a.H + h) * a.W + xx;
-        for (int c = 0; c < a.nout; ++c) a.yf[p * a.nout + c] = se[i * SE + c];
-      }
-    } else {
-      // NTH threads cover the TR x TW x CO/8 vectors of a tile in exactly
-      // CO/8 items each. The global inputs of all items (residual, previous
-      // pre-activation) are loaded before any store, so their latencies
-      // overlap instead of adding up item by item; a residual that is this
-      // layer's own input comes from the tile already in LDS.
-      constexpr int C8 = CO / 8;
-      static_assert(TR * TW == NTH, "one epilogue item per thread and 8 channels");
-      const bool res_in_tile = MODE == FWD_RES && a.res == a.x;
-      int64_t off[C8];
-      bool ok[C8];
-      bf16x8 rr[C8], zp[C8];
+    __syncthreads();  // every wave is done with the input tile
 #pragma unroll
-      for (int it = 0; it < C8; ++it) {
-        const int i = tid + it * NTH;
-        const int c8 = i % C8, pi = i / C8;
-        const int row = pi / TW, px = pi % TW, h = h0 + row, xx = x0 + px;
-        ok[it] = h < a.H && xx < a.W;
-        off[it] = (((int64_t)img * a.H + (ok[it] ? h : 0)) * a.W + (ok[it] ? xx : 0)) * CO + c8 * 8;
-        rr[it] = bf16x8{};
-        zp[it] = bf16x8{};
-        if (MODE == FWD_RES) {
-          if (res_in_tile)
-            rr[it] = *(const bf16x8*)&sx[((row + 1) * TCOLS + (px + 1)) * PX + c8 * 8];
-          else if (ok[it])
-            rr[it] = *(const bf16x8*)(a.res + off[it]);
-        } else if (MODE == BWD && ok[it]) {
-          if (a.res) rr[it] = *(const bf16x8*)(a.res + off[it]);
-          zp[it] = *(const bf16x8*)(a.zprev + off[it]);
+    for (int p = 0; p < 2; ++p) {
+      if ((wave >= EH) == (p == 1)) {  // D[m][n] -> pixel (16 ms + 4 lg + r), channel 16 ns + lm
+#pragma unroll
+        for (int ns = 0; ns < NS; ++ns) {
+          const int co = ns * 16 + lm;
+          const float bv = (a.bias && (MODE != FWD_OUT || co < a.nout)) ? a.bias[co] : 0.f;
+#pragma unroll
+          for (int ms = 0; ms < 4; ++ms)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              se[((wave - p * EH) * TW + ms * 16 + lg * 4 + r) * SE + co] = acc[ms][ns][r] + bv;
         }
       }
+      __syncthreads();
+      if (MODE == FWD_OUT) {
+        for (int i = tid; i < EH * TW; i += CNT) {
+          const int row = p * EH + i / TW, px = i % TW, h = h0 + row, xx = x0 + px;
+          if (h >= a.H || xx >= a.W) continue;
+          const int64_t q = ((int64_t)img * a.H + h) * a.W + xx;
+          for (int c = 0; c < a.nout; ++c) a.yf[q * a.nout + c] = se[i * SE + c];
+        }
+      } else {
+        int64_t off[NIT];
+        bool ok[NIT];
+        bf16x8 rr[NIT], zp[NIT];
 #pragma unroll
-      for (int it = 0; it < C8; ++it) {
-        if (!ok[it]) continue;
-        const int i = tid + it * NTH;
-        const int c8 = i % C8, pi = i / C8;
-        const float4 v0 = *(const float4*)&se[pi * SE + c8 * 8];
-        const float4 v1 = *(const float4*)&se[pi * SE + c8 * 8 + 4];
-        const float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-        bf16x8 yo, zo;
-        if (MODE == FWD_FIRST) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            yo[j] = f2bf(silu(v[j]));
-            zo[j] = f2bf(v[j]);
-          }
-        } else if (MODE == FWD_RES) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            yo[j] = f2bf(bf2f(rr[it][j]) + silu(v[j]));
-            zo[j] = f2bf(v[j]);
-          }
-        } else {  // BWD: v = dL/dh of this layer's input (+ the residual path)
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const float g = v[j] + bf2f(rr[it][j]);
-            zo[j] = f2bf(g);
-            yo[j] = f2bf(g * silu_grad(bf2f(zp[it][j])));
+        for (int it = 0; it < NIT; ++it) {
+          const int i = tid + it * CNT;
+          const int pi = i / C8, c8 = i % C8;
+          const int row = p * EH + pi / TW, px = pi % TW, h = h0 + row, xx = x0 + px;
+          ok[it] = i < EH * TW * C8 && h < a.H && xx < a.W;
+          off[it] = (((int64_t)img * a.H + (ok[it] ? h : 0)) * a.W + (ok[it] ? xx : 0)) * CO + c8 * 8;
+          rr[it] = bf16x8{};
+          zp[it] = bf16x8{};
+          if (MODE == FWD_RES) {
+            if (res_in_tile)
+              rr[it] = rt[p][it];
+            else if (ok[it])
+              rr[it] = *(const bf16x8*)(a.res + off[it]);
+          } else if (MODE == BWD && ok[it]) {
+            if (a.res) rr[it] = *(const bf16x8*)(a.res + off[it]);
+            zp[it] = *(const bf16x8*)(a.zprev + off[it]);
           }
         }
-        *(bf16x8*)(a.y + off[it]) = yo;
-        if (a.z) *(bf16x8*)(a.z + off[it]) = zo;
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+          if (!ok[it]) continue;
+          const int i = tid + it * CNT;
+          const int pi = i / C8, c8 = i % C8;
+          const float4 v0 = *(const float4*)&se[pi * SE + c8 * 8];
+          const float4 v1 = *(const float4*)&se[pi * SE + c8 * 8 + 4];
+          const float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+          bf16x8 yo, zo;
+          if (MODE == FWD_FIRST) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              yo[j] = f2bf(silu(v[j]));
+              zo[j] = f2bf(v[j]);
+            }
+          } else if (MODE == FWD_RES) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              yo[j] = f2bf(bf2f(rr[it][j]) + silu(v[j]));
+              zo[j] = f2bf(v[j]);
+            }
+          } else {  // BWD: v = dL/dh of this layer's input (+ the residual path)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const float g = v[j] + bf2f(rr[it][j]);
+              zo[j] = f2bf(g);
+              yo[j] = f2bf(g * silu_grad(bf2f(zp[it][j])));
+            }
+          }
+          *(bf16x8*)(a.y + off[it]) = yo;
+          if (a.z) *(bf16x8*)(a.z + off[it]) = zo;
+        }
       }
+      __syncthreads();  // the pass's output is read before the next one overwrites it
     }
   }
 }
@@ -268,12 +295,12 @@ static hipError_t launch_conv_t(const ConvArgs& a, int grid, hipStream_t st) {
     int dev = 0, cus = 256, per = 1;
     if (hipGetDevice(&dev) == hipSuccess)
       (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, conv_kernel<CI, CO, MODE>, NTH, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, conv_kernel<CI, CO, MODE>, CNT, 0) !=
             hipSuccess || per < 1)
       per = 1;
     resident = cus * per;
   }
-  hipLaunchKernelGGL((conv_kernel<CI, CO, MODE>), dim3(grid < resident ? grid : resident), dim3(NTH),
+  hipLaunchKernelGGL((conv_kernel<CI, CO, MODE>), dim3(grid < resident ? grid : resident), dim3(CNT),
                      0, st, a);
   return hipGetLastError();
 }

@@ -371,14 +371,14 @@ __global__ __launch_bounds__(NTH) void wgrad_kernel(WgradArgs a) {
         const int dy = tap / 3 - 1, dx = tap % 3 - 1;
         const int hh = h + dy;
         const bool rowok = hh >= 0 && hh < a.H;
+        const bf16* xr = a.x + ((int64_t)img * a.H + (rowok ? hh : 0)) * a.W * CI + c8 * 8;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const int p = g * 8 + q;
-          int xx = (x0 + p + dx) % a.W;
-          if (xx < 0) xx += a.W;
+          int xx = x0 + p + dx;  // in [-1, W] for the loaded pixels: periodic in x
+          xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
           in[q] = uint4{0u, 0u, 0u, 0u};
-          if (rowok && x0 + p < a.W)
-            in[q] = *(const uint4*)(a.x + (((int64_t)img * a.H + hh) * a.W + xx) * CI + c8 * 8);
+          if (rowok && x0 + p < a.W) in[q] = *(const uint4*)(xr + (int64_t)xx * CI);
         }
         row0 = tap * CI + c8 * 8;
         base = sa;

@@ -327,6 +327,7 @@ hipError_t launch_conv(int ci, int co, int mode, const ConvArgs& a, int grid, hi
 // segments of 64 pixels; it stages the nine shifted copies of the input (one
 // per tap) and the output gradient in LDS, transposed so that pixels are
 // contiguous, and accumulates its share of the 9CI x CO tiles in registers.
+// The next segment's blocks are loaded into registers during the matrix work.
 // Partial sums per workgroup go to `part`; wgrad_reduce adds them in a fixed
 // order.
 // ---------------------------------------------------------------------------
@@ -335,6 +336,13 @@ __global__ __launch_bounds__(NTH) void wgrad_kernel(WgradArgs a) {
   constexpr int M = 9 * CI, MS = (M + 15) / 16, NS = CO / 16;
   constexpr int SEG = 64, PS = SEG + 8;  // pixels per segment, LDS row stride
   constexpr int MPW = (MS + 3) / 4;      // M-subtiles per wave (strided by 4)
+  // A^T[tap*CI + ci][p] = x[h + dy][x0 + p + dx][ci] (0 outside rows, or past W) and
+  // gz^T[co][p] are built from blocks of 8 pixels x 8 channels: eight 16-byte
+  // loads, a register transpose, eight 16-byte LDS stores. Block `it` < NA is
+  // (c8, group, tap) of A, the rest (c8, group) of gz; a thread owns blocks
+  // tid + j NTH.
+  constexpr int CA = CI / 8, NA = 9 * (SEG / 8) * CA, NB = NA + (SEG / 8) * (CO / 8);
+  constexpr int IPT = (NB + NTH - 1) / NTH;
   __shared__ __attribute__((aligned(16))) bf16 sa[MS * 16 * PS];  // A^T[m][p]
   __shared__ __attribute__((aligned(16))) bf16 sg[CO * PS];       // gz^T[co][p]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lm = lane & 15, lg = lane >> 4;
@@ -351,59 +359,68 @@ __global__ __launch_bounds__(NTH) void wgrad_kernel(WgradArgs a) {
 
   const int segX = (a.W + SEG - 1) / SEG;
   const int nseg = segX * a.H * a.B;
-  for (int sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
+  // the blocks of segment sgi, loaded into registers one segment ahead of
+  // the matrix work
+  uint4 in[IPT][8];
+  auto load = [&](int sgi) {
     const int sx = sgi % segX, h = (sgi / segX) % a.H, img = sgi / (segX * a.H);
     const int x0 = sx * SEG;
-    __syncthreads();
-    // A^T[tap*CI + ci][p] = x[h + dy][x0 + p + dx][ci] (0 outside rows, or past W), built
-    // from blocks of 8 pixels x 8 channels: eight 16-byte loads, a register transpose,
-    // eight 16-byte LDS stores
-    constexpr int CA = CI / 8, NA = 9 * (SEG / 8) * CA;
-    for (int it = tid; it < NA + (SEG / 8) * (CO / 8); it += NTH) {
-      uint4 in[8];
-      int row0;                // LDS row of channel 0 of this block
-      bf16* base;
-      int g;                   // pixel group
-      if (it < NA) {
-        const int c8 = it % CA, t2 = it / CA;
-        g = t2 % (SEG / 8);
-        const int tap = t2 / (SEG / 8);
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        const int hh = h + dy;
-        const bool rowok = hh >= 0 && hh < a.H;
-        const bf16* xr = a.x + ((int64_t)img * a.H + (rowok ? hh : 0)) * a.W * CI + c8 * 8;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int p = g * 8 + q;
-          int xx = x0 + p + dx;  // in [-1, W] for the loaded pixels: periodic in x
-          xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
-          in[q] = uint4{0u, 0u, 0u, 0u};
-          if (rowok && x0 + p < a.W) in[q] = *(const uint4*)(xr + (int64_t)xx * CI);
+    for (int j = 0; j < IPT; ++j) {
+      const int it = tid + j * NTH;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) in[j][q] = uint4{0u, 0u, 0u, 0u};
+      if (it < NA) {
+        const int c8 = it % CA, t2 = it / CA, g = t2 % (SEG / 8), tap = t2 / (SEG / 8);
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1, hh = h + dy;
+        if (hh >= 0 && hh < a.H) {
+          const bf16* xr = a.x + ((int64_t)img * a.H + hh) * a.W * CI + c8 * 8;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int p = g * 8 + q;
+            int xx = x0 + p + dx;  // in [-1, W] for the loaded pixels: periodic in x
+            xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
+            if (x0 + p < a.W) in[j][q] = *(const uint4*)(xr + (int64_t)xx * CI);
+          }
         }
+      } else if (it < NB) {
+        const int j2 = it - NA, c8 = j2 % (CO / 8), g = j2 / (CO / 8);
+        const bf16* gr = a.gz + (((int64_t)img * a.H + h) * a.W + x0) * CO + c8 * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (x0 + g * 8 + q < a.W) in[j][q] = *(const uint4*)(gr + (int64_t)(g * 8 + q) * CO);
+      }
+    }
+  };
+  if (blockIdx.x < nseg) load(blockIdx.x);
+  for (int sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
+    __syncthreads();  // the previous segment's readers of sa and sg are done
+    // transpose: out row (channel) 2w holds the low halves of dword w of the 8
+    // pixels, row 2w + 1 the high halves; dword k of a row packs pixels 2k, 2k + 1
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const int it = tid + j * NTH;
+      if (it >= NB) continue;
+      int row0, g;
+      bf16* base;
+      if (it < NA) {
+        const int c8 = it % CA, t2 = it / CA, tap = t2 / (SEG / 8);
+        g = t2 % (SEG / 8);
         row0 = tap * CI + c8 * 8;
         base = sa;
       } else {
-        const int j2 = it - NA, c8 = j2 % (CO / 8);
+        const int j2 = it - NA;
         g = j2 / (CO / 8);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int p = g * 8 + q;
-          in[q] = uint4{0u, 0u, 0u, 0u};
-          if (x0 + p < a.W)
-            in[q] = *(const uint4*)(a.gz + (((int64_t)img * a.H + h) * a.W + x0 + p) * CO + c8 * 8);
-        }
-        row0 = c8 * 8;
+        row0 = (j2 % (CO / 8)) * 8;
         base = sg;
       }
-      // transpose: out row (channel) 2w holds the low halves of dword w of the 8
-      // pixels, row 2w + 1 the high halves; dword k of a row packs pixels 2k, 2k + 1
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         uint32_t lo[4], hi[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const uint32_t e = ((const uint32_t*)&in[2 * k])[w];
-          const uint32_t o = ((const uint32_t*)&in[2 * k + 1])[w];
+          const uint32_t e = ((const uint32_t*)&in[j][2 * k])[w];
+          const uint32_t o = ((const uint32_t*)&in[j][2 * k + 1])[w];
           lo[k] = __builtin_amdgcn_perm(o, e, 0x05040100u);
           hi[k] = __builtin_amdgcn_perm(o, e, 0x07060302u);
         }
@@ -412,10 +429,18 @@ __global__ __launch_bounds__(NTH) void wgrad_kernel(WgradArgs a) {
       }
     }
     __syncthreads();
-    if (tid < CO) {
+    if (sgi + (int)gridDim.x < nseg) load(sgi + gridDim.x);  // in flight during the matrix work
+    if (tid < CO) {  // the bias gradient: 16-byte reads issued together, then added
+      uint4 v[SEG / 8];
+#pragma unroll
+      for (int c = 0; c < SEG / 8; ++c) v[c] = *(const uint4*)&sg[tid * PS + c * 8];
       float t = 0.f;
-#pragma unroll 8
-      for (int p = 0; p < SEG; ++p) t += bf2f(sg[tid * PS + p]);
+#pragma unroll
+      for (int c = 0; c < SEG / 8; ++c) {
+        const bf16x8 e = __builtin_bit_cast(bf16x8, v[c]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t += bf2f(e[q]);
+      }
       bsum += t;
     }
 #pragma unroll

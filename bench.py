@@ -150,8 +150,12 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=2000,
                     help="steps of the 96-lattice batched sweep reported beside the headline (0: skip)")
     ap.add_argument("--surrogate-seconds", type=float, default=30.0,
-                    help="training time of the learned surrogate reported beside the headline "
-                         "(0: skip)")
+                    help="training time limit of the learned surrogate reported beside the "
+                         "headline (0: skip)")
+    ap.add_argument("--surrogate-iters", type=int, default=20000,
+                    help="Adam steps of the surrogate's training; the learning-rate schedule "
+                         "runs over them unless the time limit ends it first (then the result "
+                         "depends on the device's speed)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (for scaling HBM counters)")
     args = ap.parse_args()
@@ -294,7 +298,7 @@ def main():
     if args.surrogate_seconds > 0:
         from paper_1307_6703_amd import surrogate
         out["surrogate"] = surrogate.experiment(
-            train_seconds=args.surrogate_seconds,
+            train_seconds=args.surrogate_seconds, iters=args.surrogate_iters,
             log=lambda m: print(f"[bench] surrogate {m}", file=sys.stderr, flush=True))
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

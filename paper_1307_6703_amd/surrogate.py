@@ -364,25 +364,27 @@ def generate_data(draws, warmup: int, chunks: int, K: int = 50, scales=None):
 def train(net: Net, x, tgt, iters: int, batch: int = 16, lr: float = 1e-3, seed: int = 0,
           log_every: int = 100, time_limit: Optional[float] = None):
     """Minibatch Adam with a cosine learning-rate decay over the iterations
-    or, with a time limit, over the time. Minibatches are contiguous runs of
-    `batch` samples at random offsets. Returns [(iteration, loss)] sampled
-    every log_every iterations (the loss of that iteration's minibatch)."""
+    or, with a time limit that ends training first, over the time (the
+    schedule follows whichever is further along). Minibatches are contiguous
+    runs of `batch` samples at random offsets. Returns [(iteration, loss)]
+    sampled every log_every iterations (the loss of that iteration's
+    minibatch); the time is read there too."""
     import torch
     g = np.random.Generator(np.random.PCG64(seed))
     n = x.shape[0]
     hist = []
     t0 = time.perf_counter()
-    frac = 0.0
+    tfrac = 0.0  # fraction of the time limit used, as of the last log point
     for it in range(iters):
         s = int(g.integers(0, n - batch + 1))
-        cur = lr * 0.5 * (1.0 + np.cos(np.pi * frac))
+        frac = max(it / iters, tfrac)
+        cur = lr * 0.5 * (1.0 + np.cos(np.pi * min(frac, 1.0)))
         loss = net.train_step(x[s:s + batch], tgt[s:s + batch], max(cur, lr * 0.02))
-        frac = (it + 1) / iters
         if it % log_every == 0 or it == iters - 1:
             hist.append((it, float(loss.item())))
             if time_limit is not None:
                 el = time.perf_counter() - t0
-                frac = max(frac, el / time_limit)
+                tfrac = el / time_limit
                 if el > time_limit:
                     break
     torch.cuda.synchronize()

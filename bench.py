@@ -282,6 +282,11 @@ def main():
                      # is read and written once per launch, whatever its steps
                      "hbm_bytes_per_launch_min": BYTES_PER_UPDATE_FP32 * w.nodes,
                      "hbm_gbs_min": round(BYTES_PER_UPDATE_FP32 * w.nodes / (k_ms * 1e-3) / 1e9, 1),
+                     "note": ("two steps per launch: achieved counts 72 B per node update as the "
+                              "one-step roofline does (an effective rate); the populations cross "
+                              "HBM once per launch (hbm_gbs_min, traffic), and the kernel is bound "
+                              "by instruction issue at two waves per SIMD" if spl == 2 else
+                              "one step per launch: HBM-bound streaming of the populations"),
                      "copy_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
         "hbm_frac_of_peak": round(mlups * 1e6 * BYTES_PER_UPDATE_FP32 / 1e9 / HBM_PEAK_GBS, 4),

@@ -402,6 +402,18 @@ def dataset_loss(net: Net, x, tgt, batch: int) -> float:
     return tot / n
 
 
+def persistence_loss(tgt, batch: int) -> float:
+    """Mean loss over tgt of the prediction that nothing changes (zero
+    output), the baseline a trained network's dataset loss compares with."""
+    import torch
+    n, tot = tgt.shape[0], 0.0
+    for s in range(0, n, batch):
+        e = min(n, s + batch)
+        loss, _ = mse(torch.zeros_like(tgt[s:e]), tgt[s:e])
+        tot += float(loss.item()) * (e - s)
+    return tot / n
+
+
 @dataclass
 class RunStats:
     chunks: int = 0
@@ -431,15 +443,21 @@ class SurrogateRun:
     and goes back on probation when an audit fails. mass_tol bounds the
     relative change of the total density of a raw prediction (a sanity gate:
     accepted predictions are projected onto the exact FP64 mass afterwards,
-    so the run's own mass drift stays at rounding level)."""
+    so the run's own mass drift stays at rounding level).
 
-    def __init__(self, net: Net, batch: Batch, draws, K: int = 50, tol: float = 1e-2,
+    predictor "persist" replaces the network by the prediction that nothing
+    changes over the chunk (same audit, tolerance and re-entry): the
+    baseline that shows what the network itself adds."""
+
+    def __init__(self, net: Optional[Net], batch: Batch, draws, K: int = 50, tol: float = 1e-2,
                  mass_tol: float = 1e-2, audit_every: int = 8, need: int = 1, norm: str = "max",
-                 scales=None):
+                 scales=None, predictor: str = "net"):
         import torch
         if norm not in ("max", "rms"):
             raise ValueError("norm must be 'max' or 'rms'")
-        self.norm = norm
+        if predictor not in ("net", "persist") or (predictor == "net" and net is None):
+            raise ValueError("predictor must be 'net' (with a network) or 'persist'")
+        self.norm, self.predictor = norm, predictor
         self.net, self.b, self.K = net, batch, int(K)
         self.tol, self.mass_tol = tol, mass_tol
         self.audit_every, self.need = int(audit_every), int(need)
@@ -463,9 +481,12 @@ class SurrogateRun:
         B = self.B
         b = self.b
         b.moments_device(self.f0)
-        fields_to_input(self.f0, self.vx, self.cond, True, self.scales, out=self.x)
-        self.net.forward(self.x, self.out)
-        apply_output(self.f0, self.out, self.scales, self.f1)
+        if self.predictor == "net":
+            fields_to_input(self.f0, self.vx, self.cond, True, self.scales, out=self.x)
+            self.net.forward(self.x, self.out)
+            apply_output(self.f0, self.out, self.scales, self.f1)
+        else:
+            self.f1.copy_(self.f0)
         raw = compare(self.f1, self.f0, self.cmp).cpu().numpy()
         mass_drift = np.abs(raw[:, 0] - raw[:, 1]) / raw[:, 1]
         bad = (raw[:, 3] > 0) | ~(mass_drift <= self.mass_tol)
@@ -501,74 +522,30 @@ class SurrogateRun:
 FLOPS_PER_NODE = 2 * 9 * (IN_REAL * WIDTH + BLOCKS * WIDTH * WIDTH + WIDTH * OUT)
 
 
-def experiment(H: int = 128, W: int = 256, train_count: int = 256, train_seed: int = 2024,
-               test_count: int = 256, test_seed: int = 99, warmup: int = 300,
-               data_chunks: int = 12, K: int = 50, iters: int = 10**7, batch: int = 16,
-               lr: float = 2e-3, train_seconds: float = 60.0, eval_chunks: int = 20,
-               audit_every: int = 8, tol: float = 1e-2, log=None):
-    """Train on lattice data, then advance `test_count` fresh lattices
-    (other draws) by eval_chunks * K steps twice from the same state: with
-    the lattice alone and with the audited surrogate. Returns timings,
-    errors against the lattice-only run and the fallback statistics."""
+def _audited_eval(net, test, start, eval_chunks, K, tol, audit_every, log):
+    """One evaluation window: the lattice alone from step `start` for
+    eval_chunks * K steps, then the same span from the same state with the
+    audited network (max and RMS norms) and with the persistence baseline."""
     import torch
-    import lbsynth as ls
-
-    def say(*a):
-        if log:
-            log(" ".join(str(v) for v in a))
-
-    out = {"size": f"{W}x{H}", "K": K}
-    t0 = time.perf_counter()
-    raw = ls.surrogate_draws(train_count, seed=train_seed, Lx=W, Ly=H)
-    draws = screen(raw, warmup + data_chunks * K)
-    x, tgt, status = generate_data(draws, warmup, data_chunks, K)
-    assert all(s == 0 for s in status)
-    out["train_samples"] = int(x.shape[0])
-    out["train_draws_dropped_unstable"] = len(raw) - len(draws)
-    say(f"data: {x.shape[0]} samples in {time.perf_counter() - t0:.1f} s")
-    net_t = Net(batch, H, W, train=True)
-    net_t.set_params(init_params(0))
-    loss0 = dataset_loss(net_t, x, tgt, batch)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    hist = train(net_t, x, tgt, iters, batch, lr, log_every=200, time_limit=train_seconds)
-    t_train = time.perf_counter() - t1
-    its = hist[-1][0] + 1
-    loss1 = dataset_loss(net_t, x, tgt, batch)
-    out["train"] = {"iterations": its, "batch": batch, "seconds": round(t_train, 1),
-                    "dataset_loss_before": loss0, "dataset_loss_after": loss1,
-                    "minibatch_loss_curve": [(it, round(l, 7))
-                                             for it, l in hist[:: max(1, len(hist) // 20)]],
-                    "train_tflops": round(3 * FLOPS_PER_NODE * H * W * batch * its / t_train / 1e12, 1)}
-    say(f"train: {its} iterations in {t_train:.1f} s, loss over the {x.shape[0]} samples "
-        f"{loss0:.3e} -> {loss1:.3e}")
-    params = net_t.params().clone()
-    net_t.close()
-    del x, tgt, net_t
-    torch.cuda.empty_cache()
-
-    raw = ls.surrogate_draws(test_count + test_count // 4, seed=test_seed, Lx=W, Ly=H)
-    test = screen(raw, warmup + eval_chunks * K, keep=test_count)
-    out["test_draws_dropped_unstable"] = raw.index(test[-1]) + 1 - len(test)
-    test_count = len(test)
-    net = Net(test_count, H, W)
-    net.set_params(params)
+    n = len(test)
     steps = eval_chunks * K
     ref = _batch_for(test)
-    ref.step(warmup)
+    ref.step(start)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ref.step(steps)
     torch.cuda.synchronize()
     t_lb = time.perf_counter() - t2
     fr = ref.moments_device()
-    out["eval"] = {"instances": test_count, "steps": steps, "warmup_steps": warmup,
-                   "lattice_seconds": round(t_lb, 4), "tol": tol, "audit_every": audit_every}
-    for norm in ("max", "rms"):
+    ref.close()
+    win = {"start_step": start, "steps": steps, "lattice_seconds": round(t_lb, 4)}
+    for key, norm, pred in (("audit_max", "max", "net"), ("audit_rms", "rms", "net"),
+                            ("persist_max", "max", "persist")):
         sgb = _batch_for(test)
-        sgb.step(warmup)
-        m0 = np.array([sgb.reduce(i)["mass"] for i in range(test_count)])
-        run = SurrogateRun(net, sgb, test, K=K, tol=tol, audit_every=audit_every, norm=norm)
+        sgb.step(start)
+        m0 = np.array([sgb.reduce(i)["mass"] for i in range(n)])
+        run = SurrogateRun(net, sgb, test, K=K, tol=tol, audit_every=audit_every, norm=norm,
+                           predictor=pred)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         for _ in range(eval_chunks):
@@ -580,10 +557,10 @@ def experiment(H: int = 128, W: int = 256, train_count: int = 256, train_seed: i
         alive = np.array(sgb.status()) == 0
         max_err = np.where(alive, c[:, 2], np.inf)
         rms_err = np.where(alive, np.sqrt(c[:, 4] / c[:, 5]), np.inf)
-        m1 = np.array([sgb.reduce(i)["mass"] if alive[i] else np.nan for i in range(test_count)])
+        m1 = np.array([sgb.reduce(i)["mass"] if alive[i] else np.nan for i in range(n)])
         st = run.stats
         err_final = max_err if norm == "max" else rms_err
-        out["eval"][f"audit_{norm}"] = {
+        win[key] = {
             "surrogate_seconds": round(t_sg, 4), "speedup": round(t_lb / t_sg, 3),
             "fallback_rate": round(st.fallback_rate, 4), "audits": st.audits,
             "audit_failures": st.audit_failures, "mass_rejects": st.mass_rejects,
@@ -594,10 +571,87 @@ def experiment(H: int = 128, W: int = 256, train_count: int = 256, train_seed: i
             "mass_drift_max": float(np.nanmax(np.abs(m1 - m0) / m0)),
             "diverged": int((~alive).sum()),
         }
-        say(f"eval[{norm}]: lattice {t_lb * 1e3:.1f} ms, surrogate {t_sg * 1e3:.1f} ms, "
-            f"fallback {st.fallback_rate:.3f}, audit err median "
-            f"{out['eval'][f'audit_{norm}']['audit_error_median']}, diverged {(~alive).sum()}")
+        log(f"eval[start {start}, {key}]: lattice {t_lb * 1e3:.1f} ms, run {t_sg * 1e3:.1f} ms, "
+            f"fallback {st.fallback_rate:.3f}, audit err median {win[key]['audit_error_median']}, "
+            f"final within tol {win[key]['final_frac_within_tol']:.3f}, diverged {(~alive).sum()}")
         sgb.close()
+    return win, fr
+
+
+def experiment(H: int = 128, W: int = 256, train_count: int = 256, train_seed: int = 2024,
+               test_count: int = 256, test_seed: int = 99,
+               train_windows=((300, 12), (8000, 12)), eval_starts=(300, 10000),
+               K: int = 50, iters: int = 10**7, batch: int = 16,
+               lr: float = 2e-3, train_seconds: float = 60.0, eval_chunks: int = 20,
+               audit_every: int = 8, tol: float = 1e-2, log=None):
+    """Train on lattice data recorded in the windows (start step, chunks),
+    then advance `test_count` fresh lattices (other draws) by
+    eval_chunks * K steps from each step of eval_starts, several times from
+    the same state: with the lattice alone, with the audited network and
+    with the audited persistence baseline. Returns timings, errors against
+    the lattice-only run and the fallback statistics."""
+    import torch
+    import lbsynth as ls
+
+    def say(*a):
+        if log:
+            log(" ".join(str(v) for v in a))
+
+    out = {"size": f"{W}x{H}", "K": K}
+    t0 = time.perf_counter()
+    raw = ls.surrogate_draws(train_count, seed=train_seed, Lx=W, Ly=H)
+    draws = screen(raw, max(s + c * K for s, c in train_windows))
+    xs, ts, spans = [], [], []
+    for s, c in train_windows:
+        x, tgt, status = generate_data(draws, s, c, K)
+        assert all(v == 0 for v in status)
+        spans.append((sum(v.shape[0] for v in xs), x.shape[0]))
+        xs.append(x)
+        ts.append(tgt)
+    x, tgt = torch.cat(xs), torch.cat(ts)
+    del xs, ts
+    out["train_samples"] = int(x.shape[0])
+    out["train_windows"] = [{"start_step": s, "chunks": c} for s, c in train_windows]
+    out["train_draws_dropped_unstable"] = len(raw) - len(draws)
+    say(f"data: {x.shape[0]} samples in {time.perf_counter() - t0:.1f} s")
+    net_t = Net(batch, H, W, train=True)
+    net_t.set_params(init_params(0))
+    loss0 = dataset_loss(net_t, x, tgt, batch)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = train(net_t, x, tgt, iters, batch, lr, log_every=200, time_limit=train_seconds)
+    t_train = time.perf_counter() - t1
+    its = hist[-1][0] + 1
+    loss1 = dataset_loss(net_t, x, tgt, batch)
+    per_window = [dataset_loss(net_t, x[a:a + m], tgt[a:a + m], batch) for a, m in spans]
+    persist = [persistence_loss(tgt[a:a + m], batch) for a, m in spans]
+    out["train"] = {"iterations": its, "batch": batch, "seconds": round(t_train, 1),
+                    "dataset_loss_before": loss0, "dataset_loss_after": loss1,
+                    "dataset_loss_after_per_window": per_window,
+                    "persistence_loss_per_window": persist,
+                    "minibatch_loss_curve": [(it, round(l, 7))
+                                             for it, l in hist[:: max(1, len(hist) // 20)]],
+                    "train_tflops": round(3 * FLOPS_PER_NODE * H * W * batch * its / t_train / 1e12, 1)}
+    say(f"train: {its} iterations in {t_train:.1f} s, loss over the {x.shape[0]} samples "
+        f"{loss0:.3e} -> {loss1:.3e} (per window {', '.join(f'{v:.3e}' for v in per_window)}; "
+        f"persistence {', '.join(f'{v:.3e}' for v in persist)})")
+    params = net_t.params().clone()
+    net_t.close()
+    del x, tgt, net_t
+    torch.cuda.empty_cache()
+
+    raw = ls.surrogate_draws(test_count + test_count // 4, seed=test_seed, Lx=W, Ly=H)
+    test = screen(raw, max(eval_starts) + eval_chunks * K, keep=test_count)
+    out["test_draws_dropped_unstable"] = raw.index(test[-1]) + 1 - len(test)
+    test_count = len(test)
+    net = Net(test_count, H, W)
+    net.set_params(params)
+    out["eval"] = {"instances": test_count, "tol": tol, "audit_every": audit_every,
+                   "windows": []}
+    fr = None
+    for start in eval_starts:
+        win, fr = _audited_eval(net, test, start, eval_chunks, K, tol, audit_every, say)
+        out["eval"]["windows"].append(win)
     # forward throughput on the whole test batch
     vx, cond = conditions(test)
     xin = fields_to_input(fr, vx, cond, True)
@@ -615,6 +669,5 @@ def experiment(H: int = 128, W: int = 256, train_count: int = 256, train_seed: i
     out["forward"] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) / 1e12, 1),
                       "peak_bf16_tflops": 2500.0, "frac": round(flops / (ms * 1e-3) / 1e12 / 2500.0, 4),
                       "gflop_per_instance": round(FLOPS_PER_NODE * H * W / 1e9, 3)}
-    ref.close()
     net.close()
     return out

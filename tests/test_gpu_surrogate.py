@@ -388,3 +388,28 @@ def test_audited_run_rejects_beyond_tolerance(torch_cuda):
     assert (st.audits, st.audit_failures, st.surrogate_chunks, st.lattice_chunks) == (16, 16, 0, 16)
     a.close()
     net.close()
+
+
+def test_persistence_baseline_equals_zero_network(torch_cuda):
+    """The persistence baseline (no network) runs exactly as a network whose
+    output is zero: same accepted instances, statistics and final state."""
+    from paper_1307_6703_amd import surrogate as sg
+    _say("audited run, persistence baseline")
+    draws = _draws(4, 64, 32, 11)
+    net = sg.Net(4, 32, 64)
+    net.set_params(np.zeros(sg.param_count(), np.float32))
+    a = sg._batch_for(draws, check_every=0, drift=False)
+    b = sg._batch_for(draws, check_every=0, drift=False)
+    ra = sg.SurrogateRun(net, a, draws, K=10, tol=0.05, audit_every=2)
+    rb = sg.SurrogateRun(None, b, draws, K=10, tol=0.05, audit_every=2, predictor="persist")
+    for _ in range(5):
+        assert np.array_equal(ra.chunk(), rb.chunk())
+    assert ra.stats == rb.stats
+    for i in range(4):
+        for u, v in zip(a.moments(i), b.moments(i)):
+            assert np.array_equal(u, v)
+    with pytest.raises(ValueError):
+        sg.SurrogateRun(None, a, draws, K=10)
+    for bb in (a, b):
+        bb.close()
+    net.close()

@@ -192,6 +192,16 @@ lb_status lb_batch_get_moments_device(lb_batch* b, double* d_out);
 lb_status lb_batch_set_equilibrium_device(lb_batch* b, const double* d_fields,
                                           const int32_t* mask);
 
+/* Re-entry that keeps the non-equilibrium part: for each instance with
+ * mask[i] != 0, add f_eq(d_fields) - f_eq(d_from) of Eq.(eqfunc) to the
+ * stored populations (d_from, d_fields: device FP64 [count][3][Ly][Lx] as
+ * above; d_from is normally the instance's current moments, so that only
+ * the equilibrium part moves; with equal fields the populations stay the
+ * same bits) and make d_fields the instance's moments. The step counter and
+ * a pending drift shift do not change. Synchronises the stream. */
+lb_status lb_batch_shift_equilibrium_device(lb_batch* b, const double* d_from,
+                                            const double* d_fields, const int32_t* mask);
+
 /* Advance only the instances with mask[i] != 0 by nsteps (even, so that
  * their buffer parity stays that of the batch), with the batch's launch
  * shape, no graph and no drift shift; the last step writes their moments;

@@ -630,8 +630,8 @@ lb_status lb_batch_get_moments_device(lb_batch* b, double* dev_out) {
   return LB_OK;
 }
 
-lb_status lb_batch_set_equilibrium_device(lb_batch* b, const double* dev_fields,
-                                          const int32_t* mask) {
+static lb_status reenter(lb_batch* b, const double* dev_fields, const double* dev_from,
+                         const int32_t* mask) {
   if (!b || !dev_fields || !mask) return fail(LB_EINVAL, "NULL argument");
   lb_status r = same_size(b);
   if (r != LB_OK) return r;
@@ -650,11 +650,22 @@ lb_status lb_batch_set_equilibrium_device(lb_batch* b, const double* dev_fields,
     return fail(LB_EINVAL, "batch too large for the mask buffer");
   HIPCHK(hipMemcpyAsync(dmask, m.data(), sizeof(int32_t) * b->count, hipMemcpyHostToDevice, b->st));
   HIPCHK(lbk::launch_scatter_eq(b->fp32, b->ddesc, b->dred, b->count, b->parity, inst_nodes(b, 0),
-                                dev_fields, dmask, b->st));
+                                dev_fields, dev_from, dmask, b->st));
   HIPCHK(hipStreamSynchronize(b->st));  // m is a host temporary
   for (int i = 0; i < b->count; ++i)
     if (m[i]) b->inst[i].moments_valid = true;
   return LB_OK;
+}
+
+lb_status lb_batch_set_equilibrium_device(lb_batch* b, const double* dev_fields,
+                                          const int32_t* mask) {
+  return reenter(b, dev_fields, nullptr, mask);
+}
+
+lb_status lb_batch_shift_equilibrium_device(lb_batch* b, const double* dev_from,
+                                            const double* dev_fields, const int32_t* mask) {
+  if (!dev_from) return fail(LB_EINVAL, "NULL argument");
+  return reenter(b, dev_fields, dev_from, mask);
 }
 
 lb_status lb_batch_step_subset(lb_batch* b, int64_t nsteps, const int32_t* mask) {

@@ -618,13 +618,10 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
   if (xc < 0) xc += Lx;
   const int xm = xc == 0 ? Lx - 1 : xc - 1;
   const int xp = xc == Lx - 1 ? 0 : xc + 1;
+  // lanes of the first step's pulls, of its force stage (the column force
+  // table), and of the second step's stores
   const bool actA = t < W + 14;
-  const bool actB = t >= 1 && t < W + 13;
   const bool actC = t >= 2 && t < W + 12;
-  const bool actD = t >= 3 && t < W + 11;
-  const bool act2A = t >= 4 && t < W + 10;
-  const bool act2B = t >= 5 && t < W + 9;
-  const bool act2C = t >= 6 && t < W + 8;
   const bool act2D = t >= 7 && t < W + 7;
   const int vc = actA ? xc * (int)sizeof(R) : arrb;
   const int vm = actA ? xm * (int)sizeof(R) : arrb;
@@ -663,10 +660,9 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
   const int E1 = we ? E2 : E2 + dir;
   const int K1 = dir * (E1 - S1) + 1 + 6;  // first step: pipeline rows S1-3 .. E1+3
   const int a0 = S1 - 3 * dir;
-  // second step, relative rows of each stage (first, last)
+  // second step, relative rows: first and last of its pipeline, and of its
+  // outputs
   const int r2s = dir * (S2 - S1), r2e = dir * (E2 - S1);
-  const int rbs = r2s + (ws ? 0 : 1), rbe = r2e - (we ? 0 : 1);
-  const int rcs = r2s + (ws ? 0 : 2), rce = r2e - (we ? 0 : 2);
   const int rds = dir * (ofirst - S1), rde = dir * (olast - S1);
   const int K = rde + 13;  // D2 runs on relative row k - 12
 
@@ -1240,27 +1236,40 @@ __global__ void gather_moments_kernel(const Desc* __restrict__ descs, int64_t nn
     o[k] = mom[k];
 }
 
+// Re-entry of instance i (mask[i] != 0) at the fields [i][3][nn] (n, u*_x,
+// u*_y): with from == null its populations become the equilibrium of
+// Eq.(eqfunc) at those fields; otherwise they gain f_eq(fields) - f_eq(from)
+// and keep their non-equilibrium part (with fields == from, bit for bit
+// unchanged). The fields become the instance's moments.
 template <typename R>
 __global__ void scatter_eq_kernel(const Desc* __restrict__ descs, ReduceOut* __restrict__ red,
                                   int parity, int64_t nn, const double* __restrict__ fields,
-                                  const int32_t* __restrict__ mask) {
+                                  const double* __restrict__ from, const int32_t* __restrict__ mask) {
   const int i = blockIdx.y;
   if (!mask[i]) return;  // uniform per block
   const Desc& d = descs[i];
-  // a drift shift measured on the replaced state does not apply to the new one
-  if (blockIdx.x == 0 && threadIdx.x == 0) red[i].shift = 0.0;
+  // a drift shift measured on a replaced state does not apply to the new
+  // one; an added equilibrium difference keeps the state's mass error
+  if (!from && blockIdx.x == 0 && threadIdx.x == 0) red[i].shift = 0.0;
   R* S = (R*)d.S[parity];
   const double* f = fields + (int64_t)i * 3 * nn;
+  const double* f0 = from ? from + (int64_t)i * 3 * nn : nullptr;
   const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  auto feq = [&](int q, double n, double ux, double uy) {
+    const double cu = cx(q) * ux + cy(q) * uy;
+    return rest_weight_hd(q, d.T) * (n - d.nbar) +
+           w[q] * n * (3.0 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy));
+  };
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nn;
        k += (int64_t)gridDim.x * blockDim.x) {
     const double n = f[k], ux = f[nn + k], uy = f[2 * nn + k];
-    const double usq = 1.5 * (ux * ux + uy * uy);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      const double cu = cx(q) * ux + cy(q) * uy;
-      S[pidx(q, k, k / d.Lx, d.Lx)] =
-          (R)(rest_weight_hd(q, d.T) * (n - d.nbar) + w[q] * n * (3.0 * cu + 4.5 * cu * cu - usq));
+      R& s = S[pidx(q, k, k / d.Lx, d.Lx)];
+      if (f0)
+        s = (R)((double)s + (feq(q, n, ux, uy) - feq(q, f0[k], f0[nn + k], f0[2 * nn + k])));
+      else
+        s = (R)feq(q, n, ux, uy);
     }
     d.mom[k] = n;
     d.mom[nn + k] = ux;
@@ -1276,14 +1285,14 @@ hipError_t launch_gather_moments(const Desc* d_descs, int count, int64_t nn, dou
 }
 
 hipError_t launch_scatter_eq(bool fp32, const Desc* d_descs, ReduceOut* d_red, int count,
-                             int parity, int64_t nn, const double* fields, const int32_t* d_mask,
-                             hipStream_t st) {
+                             int parity, int64_t nn, const double* fields, const double* from,
+                             const int32_t* d_mask, hipStream_t st) {
   if (fp32)
     hipLaunchKernelGGL(scatter_eq_kernel<float>, dim3(grid_for(nn, 256), count), dim3(256), 0, st,
-                       d_descs, d_red, parity, nn, fields, d_mask);
+                       d_descs, d_red, parity, nn, fields, from, d_mask);
   else
     hipLaunchKernelGGL(scatter_eq_kernel<double>, dim3(grid_for(nn, 256), count), dim3(256), 0, st,
-                       d_descs, d_red, parity, nn, fields, d_mask);
+                       d_descs, d_red, parity, nn, fields, from, d_mask);
   return hipGetLastError();
 }
 

@@ -71,12 +71,13 @@ hipError_t launch_set_pops(bool fp32, const Desc* d_desc, int parity, int p0, in
                            int64_t nn, const double* d_f, hipStream_t stream);
 // Batch helpers (all instances of the same size nn): gather the moment blocks
 // into out[count][3][nn]; write equilibrium populations from fields
-// [count][3][nn] for instances with d_mask[i] != 0 (device array).
+// [count][3][nn] for instances with d_mask[i] != 0 (device array), or, with
+// from != null, add f_eq(fields) - f_eq(from) to their populations.
 hipError_t launch_gather_moments(const Desc* d_descs, int count, int64_t nn, double* out,
                                  hipStream_t st);
 hipError_t launch_scatter_eq(bool fp32, const Desc* d_descs, ReduceOut* d_red, int count,
-                             int parity, int64_t nn, const double* fields, const int32_t* d_mask,
-                             hipStream_t st);
+                             int parity, int64_t nn, const double* fields, const double* from,
+                             const int32_t* d_mask, hipStream_t st);
 // Rest-state weight w^_i at temperature T.
 double rest_weight(int i, double T);
 

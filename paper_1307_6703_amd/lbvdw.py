@@ -77,6 +77,7 @@ SIGNATURES = {
     "lb_batch_autotune": (ctypes.c_int, [_VP, ctypes.c_int32, _I32P, _I32P, _DP]),
     "lb_batch_get_moments_device": (ctypes.c_int, [_VP, _VP]),
     "lb_batch_set_equilibrium_device": (ctypes.c_int, [_VP, _VP, _I32P]),
+    "lb_batch_shift_equilibrium_device": (ctypes.c_int, [_VP, _VP, _VP, _I32P]),
     "lb_batch_step_subset": (ctypes.c_int, [_VP, ctypes.c_int64, _I32P]),
     # include/lbsurrogate.h
     "lbs_param_count": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64)]),
@@ -404,6 +405,18 @@ class Batch:
         _require(fields, torch.float64, self.count * 3 * Ly * Lx)
         m, mp = self._mask(mask)
         _check(_lib.lb_batch_set_equilibrium_device(self._h, ctypes.c_void_p(fields.data_ptr()), mp))
+
+    def shift_equilibrium(self, frm, fields, mask):
+        """Re-enter the instances with mask != 0 at the device FP64 fields
+        [count, 3, Ly, Lx] keeping their non-equilibrium part: add
+        f_eq(fields) - f_eq(frm) to their populations."""
+        import torch
+        Ly, Lx = self.shapes[0]
+        _require(frm, torch.float64, self.count * 3 * Ly * Lx)
+        _require(fields, torch.float64, self.count * 3 * Ly * Lx)
+        m, mp = self._mask(mask)
+        _check(_lib.lb_batch_shift_equilibrium_device(self._h, ctypes.c_void_p(frm.data_ptr()),
+                                                      ctypes.c_void_p(fields.data_ptr()), mp))
 
     def step_subset(self, nsteps: int, mask):
         """Advance only the instances with mask != 0 by an even number of steps."""

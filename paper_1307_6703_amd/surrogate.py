@@ -447,17 +447,24 @@ class SurrogateRun:
 
     predictor "persist" replaces the network by the prediction that nothing
     changes over the chunk (same audit, tolerance and re-entry): the
-    baseline that shows what the network itself adds."""
+    baseline that shows what the network itself adds.
+
+    reentry "shift" adds f_eq(prediction) - f_eq(chunk start) to the
+    populations, so they keep their non-equilibrium part (an accepted
+    persistence prediction then leaves the lattice exactly as it was);
+    "eq" replaces them by f_eq(prediction)."""
 
     def __init__(self, net: Optional[Net], batch: Batch, draws, K: int = 50, tol: float = 1e-2,
                  mass_tol: float = 1e-2, audit_every: int = 8, need: int = 1, norm: str = "max",
-                 scales=None, predictor: str = "net"):
+                 scales=None, predictor: str = "net", reentry: str = "shift"):
         import torch
         if norm not in ("max", "rms"):
             raise ValueError("norm must be 'max' or 'rms'")
         if predictor not in ("net", "persist") or (predictor == "net" and net is None):
             raise ValueError("predictor must be 'net' (with a network) or 'persist'")
-        self.norm, self.predictor = norm, predictor
+        if reentry not in ("shift", "eq"):
+            raise ValueError("reentry must be 'shift' or 'eq'")
+        self.norm, self.predictor, self.reentry = norm, predictor, reentry
         self.net, self.b, self.K = net, batch, int(K)
         self.tol, self.mass_tol = tol, mass_tol
         self.audit_every, self.need = int(audit_every), int(need)
@@ -512,7 +519,10 @@ class SurrogateRun:
                 else:
                     self.stats.audit_failures += 1
                     self.passes[i] = 0
-        b.set_equilibrium(self.f1, accept.astype(np.int32))
+        if self.reentry == "shift":
+            b.shift_equilibrium(self.f0, self.f1, accept.astype(np.int32))
+        else:
+            b.set_equilibrium(self.f1, accept.astype(np.int32))
         self.stats.lattice_chunks += int(lattice.sum())
         self.stats.surrogate_chunks += int(accept.sum())
         self.stats.chunks += 1

@@ -413,3 +413,58 @@ def test_persistence_baseline_equals_zero_network(torch_cuda):
     for bb in (a, b):
         bb.close()
     net.close()
+
+
+def test_shift_reentry_keeps_the_non_equilibrium_part(torch_cuda):
+    """lb_batch_shift_equilibrium_device: at equal fields the populations stay
+    the same bits; from an equilibrium state it agrees with replacing the
+    populations by f_eq (up to FP32 rounding); the mass moves by the change
+    of the density field; a shift there and back returns the state."""
+    from paper_1307_6703_amd.surrogate import _batch_for
+    torch = torch_cuda
+    _say("shift re-entry")
+    draws = _draws(3, 70, 20, 12)
+    a, b, c = (_batch_for(draws, check_every=0, drift=False) for _ in range(3))
+    for bb in (a, b, c):
+        bb.step(40)  # a state with a non-equilibrium part
+    f0 = a.moments_device()
+    yy, xx = torch.meshgrid(torch.arange(20, device="cuda"), torch.arange(70, device="cuda"),
+                            indexing="ij")
+    f1 = f0.clone()
+    f1[:, 0] *= 1.0 + 0.01 * torch.sin(2 * np.pi * xx / 70).double()
+    f1[:, 1] += 0.002 * torch.cos(2 * np.pi * yy / 20).double()
+    m0 = [a.reduce(i)["mass"] for i in range(3)]
+    # equal fields: bit for bit the run without re-entry
+    a.shift_equilibrium(f0, f0, [1, 1, 1])
+    a.step(10)
+    c.step(10)
+    for i in range(3):
+        for u, v in zip(a.moments(i), c.moments(i)):
+            assert np.array_equal(u, v)
+    # there and back: the state returns up to FP32 rounding
+    b.shift_equilibrium(f0, f1, [1, 0, 1])
+    for i in (0, 2):
+        n, ux, _ = b.moments(i)
+        assert np.array_equal(n, _f64(f1[i, 0])) and np.array_equal(ux, _f64(f1[i, 1]))
+        dm = float((f1[i, 0] - f0[i, 0]).sum())
+        assert abs(b.reduce(i)["mass"] - (m0[i] + dm)) <= 1e-6 * m0[i]
+    assert np.array_equal(b.moments(1)[0], _f64(f0[1, 0]))
+    b.shift_equilibrium(f1, f0, [1, 0, 1])
+    b.step(10)
+    for i in range(3):
+        for u, v in zip(b.moments(i), c.moments(i)):
+            assert np.allclose(u, v, rtol=0, atol=1e-5)
+    # from an equilibrium state (just initialised) shift == replace
+    e, g = (_batch_for(draws, check_every=0, drift=False) for _ in range(2))
+    fi = e.moments_device()
+    fj = fi.clone()
+    fj[:, 0] *= 1.0 + 0.01 * torch.sin(2 * np.pi * xx / 70).double()
+    e.set_equilibrium(fj, [1, 1, 1])
+    g.shift_equilibrium(fi, fj, [1, 1, 1])
+    e.step(10)
+    g.step(10)
+    for i in range(3):
+        for u, v in zip(e.moments(i), g.moments(i)):
+            assert np.allclose(u, v, rtol=0, atol=1e-5)
+    for bb in (a, b, c, e, g):
+        bb.close()

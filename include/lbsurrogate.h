@@ -5,8 +5,10 @@
  * method. A small convolutional network predicts the change of the fields
  * (n, u*_x, u*_y) over a chunk of lattice steps; the lattice itself audits
  * the predictions (lb_batch_step_subset on a rotating subset of instances)
- * and replaces rejected ones; accepted ones re-enter the lattice as
- * equilibrium populations of Eq.(eqfunc) (lb_batch_set_equilibrium_device).
+ * and replaces rejected ones; accepted ones re-enter the lattice through
+ * the change of the equilibrium populations of Eq.(eqfunc)
+ * (lb_batch_shift_equilibrium_device) or as those equilibria
+ * (lb_batch_set_equilibrium_device).
  *
  * Network (fixed shape): 3x3 convolutions, x periodic, zero padding beyond
  * the first and last rows;

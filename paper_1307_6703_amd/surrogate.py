@@ -14,7 +14,8 @@ library's HIP kernels) plus the host logic that drives it:
   and the audited predictions are compared with the lattice's own result;
   an audit above the density tolerance makes the instance untrusted for a
   while. Accepted predictions are projected onto the exact mass and
-  re-enter the lattice as equilibrium populations of Eq.(eqfunc).
+  re-enter the lattice by adding the change of the equilibrium populations
+  of Eq.(eqfunc) (the populations keep their non-equilibrium part).
 
 The paper has no surrogate; the lattice's equations stay the reference
 throughout.
@@ -535,7 +536,9 @@ FLOPS_PER_NODE = 2 * 9 * (IN_REAL * WIDTH + BLOCKS * WIDTH * WIDTH + WIDTH * OUT
 def _audited_eval(net, test, start, eval_chunks, K, tol, audit_every, log):
     """One evaluation window: the lattice alone from step `start` for
     eval_chunks * K steps, then the same span from the same state with the
-    audited network (max and RMS norms) and with the persistence baseline."""
+    audited network (max and RMS norms) and with the persistence baseline,
+    re-entering accepted chunks by shift (the default) and, for the
+    baseline, also as pure equilibria."""
     import torch
     n = len(test)
     steps = eval_chunks * K
@@ -549,13 +552,15 @@ def _audited_eval(net, test, start, eval_chunks, K, tol, audit_every, log):
     fr = ref.moments_device()
     ref.close()
     win = {"start_step": start, "steps": steps, "lattice_seconds": round(t_lb, 4)}
-    for key, norm, pred in (("audit_max", "max", "net"), ("audit_rms", "rms", "net"),
-                            ("persist_max", "max", "persist")):
+    for key, norm, pred, reentry in (
+            ("audit_max", "max", "net", "shift"), ("audit_rms", "rms", "net", "shift"),
+            ("persist_max", "max", "persist", "shift"),
+            ("persist_max_eq_reentry", "max", "persist", "eq")):
         sgb = _batch_for(test)
         sgb.step(start)
         m0 = np.array([sgb.reduce(i)["mass"] for i in range(n)])
         run = SurrogateRun(net, sgb, test, K=K, tol=tol, audit_every=audit_every, norm=norm,
-                           predictor=pred)
+                           predictor=pred, reentry=reentry)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         for _ in range(eval_chunks):

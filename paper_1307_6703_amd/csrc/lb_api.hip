@@ -64,7 +64,7 @@ lb_status set_tiles(lb_handle* h, int threads, int rows, int fuse = 1) {
   if (fuse == 2) {
     if (!h->p.fp32) return fail(LB_EINVAL, "two steps per launch need FP32 storage");
     if (!fused_threads_ok(threads))
-      return fail(LB_EINVAL, "two steps per launch: threads must be 128, 192 or 256 (got %d)", threads);
+      return fail(LB_EINVAL, "two steps per launch: threads must be 64, 128, 192 or 256 (got %d)", threads);
   } else if (threads != 64 && threads != 128 && threads != 256 && threads != 320 &&
              !(threads == 512 && h->p.fp32)) {
     return fail(LB_EINVAL, "threads must be 64, 128, 256, 320 or 512 (FP32 only) (got %d)", threads);

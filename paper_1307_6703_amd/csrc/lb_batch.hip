@@ -36,7 +36,7 @@ BatchLayout batch_layout(int count, const lb_params* p, std::vector<Inst>* insts
   int64_t sum_red = 0;
   B.off.resize(count);
   for (int i = 0; i < count; ++i) {
-    const int strips = (p[i].Lx + 57) / 58;
+    const int strips = (p[i].Lx + 49) / 50;  // narrowest strip: 64 threads, two steps
     const int chunks = (p[i].Ly + 7) / 8;
     max_tiles += strips * chunks;
     B.off[i] = sum_red;
@@ -195,7 +195,7 @@ lb_status batch_tiles(lb_batch* b, int threads, int rows, int fuse = 1) {
   if (fuse == 2) {
     if (!b->fp32) return fail(LB_EINVAL, "two steps per launch need FP32 storage");
     if (!fused_threads_ok(threads))
-      return fail(LB_EINVAL, "two steps per launch: threads must be 128, 192 or 256 (got %d)", threads);
+      return fail(LB_EINVAL, "two steps per launch: threads must be 64, 128, 192 or 256 (got %d)", threads);
   } else if (threads != 64 && threads != 128 && threads != 256 && threads != 320 &&
              !(threads == 512 && b->fp32)) {
     return fail(LB_EINVAL, "threads must be 64, 128, 256, 320 or 512 (FP32 only) (got %d)", threads);

@@ -896,6 +896,7 @@ static hipError_t launch_step2_t(const Desc* dd, const Tile* dt, int ntiles, int
 hipError_t launch_step2(int threads, const Desc* d_descs, const Tile* d_tiles, int ntiles,
                         int parity, int flags, hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
+  if (threads == 64) return launch_step2_t<64>(d_descs, d_tiles, ntiles, parity, flags, stream);
   if (threads == 128) return launch_step2_t<128>(d_descs, d_tiles, ntiles, parity, flags, stream);
   if (threads == 192) return launch_step2_t<192>(d_descs, d_tiles, ntiles, parity, flags, stream);
   if (threads == 256) return launch_step2_t<256>(d_descs, d_tiles, ntiles, parity, flags, stream);

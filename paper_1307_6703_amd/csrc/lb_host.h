@@ -77,7 +77,7 @@ inline Layout layout_for(const lb_params* p, size_t base = 0) {
   const size_t nn = (size_t)p->Lx * p->Ly;
   const size_t rs = p->fp32 ? sizeof(float) : sizeof(double);
   Layout L;
-  const int strips = (p->Lx + 57) / 58;  // narrowest strip: 64 threads
+  const int strips = (p->Lx + 49) / 50;  // narrowest strip: 64 threads, two steps
   const int chunks = (p->Ly + kMinRows - 1) / kMinRows;
   L.max_tiles = strips * chunks;
   size_t o = base;
@@ -138,11 +138,11 @@ inline int default_rows(const lb_params* p, int threads, int rounds = 1) {
 }
 
 // Two-step kernel (FP32): strips of threads-14 columns. One workgroup's LDS
-// rings take 288 (threads + 2) bytes, so 4, 2 or 2 workgroups of 128, 192 or
-// 256 threads fit on a CU (160 KB of LDS); at most 256 VGPRs allow 2 waves
-// per SIMD.
+// rings take 288 (threads + 2) bytes, so 8, 4, 2 or 2 workgroups of 64, 128,
+// 192 or 256 threads fit on a CU (160 KB of LDS); at most 256 VGPRs allow 2
+// waves per SIMD.
 inline bool fused_threads_ok(int threads) {
-  return threads == 128 || threads == 192 || threads == 256;
+  return threads == 64 || threads == 128 || threads == 192 || threads == 256;
 }
 
 inline int fused_resident_slots(int threads) {

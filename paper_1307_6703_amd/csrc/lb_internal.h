@@ -42,7 +42,7 @@ struct ReduceOut {
 // Launchers (all asynchronous on `stream`). fp32 selects the storage type.
 hipError_t launch_step(bool fp32, int threads, const Desc* d_descs, const Tile* d_tiles,
                        int ntiles, int parity, int flags, hipStream_t stream);
-// Two steps per launch (FP32 only; threads 128, 192 or 256): tiles of
+// Two steps per launch (FP32 only; threads 64, 128, 192 or 256): tiles of
 // threads-14 columns, reads S[parity], writes S[parity ^ 1].
 hipError_t launch_step2(int threads, const Desc* d_descs, const Tile* d_tiles, int ntiles,
                         int parity, int flags, hipStream_t stream);

@@ -261,7 +261,7 @@ class Lattice:
 
     def set_launch(self, threads: int = 0, rows: int = 0, steps_per_launch: int = 1):
         """Launch shape; steps_per_launch = 2 selects the two-step kernel
-        (FP32 only; threads 128, 192 or 256)."""
+        (FP32 only; threads 64, 128, 192 or 256)."""
         if steps_per_launch == 2:
             _check(_lib.lb_set_launch_fused(self._h, int(threads), int(rows)))
         elif steps_per_launch == 1:
@@ -360,7 +360,7 @@ class Batch:
 
     def set_launch(self, threads: int = 0, rows: int = 0, steps_per_launch: int = 1):
         """Launch shape shared by all instances; steps_per_launch = 2 selects
-        the two-step kernel (FP32 only; threads 128, 192 or 256)."""
+        the two-step kernel (FP32 only; threads 64, 128, 192 or 256)."""
         if steps_per_launch == 2:
             _check(_lib.lb_batch_set_launch_fused(self._h, int(threads), int(rows)))
         elif steps_per_launch == 1:

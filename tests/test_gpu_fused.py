@@ -56,6 +56,9 @@ CASES = [
     (1, 9, False, (128, 8), 14),         # one column: every pull wraps onto itself
     (2, 6, True, (128, 8), 9),
     (115, 33, False, (128, 1), 10),      # chunks of 8 rows (the minimum), one column past a strip
+    (300, 70, False, (64, 8), 41),       # one-wave workgroups: strips of 50 columns
+    (101, 37, True, (64, 17), 20),       # one column past two strips
+    (3, 9, False, (64, 8), 14),
 ]
 
 
@@ -120,7 +123,7 @@ def test_fused_launch_is_validated(torch_cuda):
         g.set_launch(128, 0, steps_per_launch=2)  # FP64 storage
     g.close()
     g = _lattice(64, 16, False, seed=1)
-    for t in (64, 320, 512):
+    for t in (96, 320, 512):
         with pytest.raises(LBError):
             g.set_launch(t, 0, steps_per_launch=2)
     g.set_launch(0, 0, steps_per_launch=2)
@@ -139,7 +142,8 @@ def _batch_instances():
     return out
 
 
-@pytest.mark.parametrize("check_every,launch", [(20, (128, 33)), (7, (256, 17)), (0, (192, 65))])
+@pytest.mark.parametrize("check_every,launch", [(20, (128, 33)), (7, (256, 17)), (0, (192, 65)),
+                                                (20, (64, 40))])
 def test_batch_fused_equals_one_step_batch(torch_cuda, check_every, launch):
     # graph runs of 64 steps (32 launches), eager steps up to the check grid,
     # single steps before checks that split a pair, subset steps

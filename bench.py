@@ -112,17 +112,17 @@ def batched_bench(steps: int, seed: int = 1307):
 
     # a draw whose lattice fails a stability check within the run (a deep
     # quench under strong shear can) is replaced by the next draw; the
-    # screening covers the autotuner's steps (about 350), the warm-up and the
+    # screening covers the autotuner's steps (about 1600), the warm-up and the
     # timed steps
     pool = ls.batch_draws(128, seed=seed)
     scr = batch_of(pool)
-    scr.step(steps + 600)
+    scr.step(steps + 1800)
     status = scr.status()
     scr.close()
     draws = [w for w, st in zip(pool, status) if st == 0][:96]
     replaced = pool.index(draws[-1]) + 1 - len(draws)
     b = batch_of(draws)
-    th, rw, _ = b.autotune(nsteps=10)
+    th, rw, _ = b.autotune(nsteps=40)
     b.step(100)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -461,7 +461,7 @@ lb_status lb_autotune(lb_handle* h, int32_t nsteps, int32_t* threads, int32_t* r
       if (rw <= h->p.Ly) cand.push_back({t, rw, 1});
   }
   if (h->p.fp32)
-    for (int t : {128, 192, 256}) {
+    for (int t : {64, 128, 192, 256}) {
       if (t > 128 && h->p.Lx + 14 <= t / 2) continue;
       std::vector<int> rs = {fused_default_rows(&h->p, t, 1), fused_default_rows(&h->p, t, 2), 32};
       std::sort(rs.begin(), rs.end());

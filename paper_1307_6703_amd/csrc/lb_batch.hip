@@ -579,8 +579,8 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t nsteps, int32_t* threads, int32
     for (int rw : {16, 32, 64, 128, 256})
       if (t != 512 || b->fp32) cand.push_back({t, rw, 1});
   if (b->fp32)
-    for (int t : {128, 192, 256})
-      for (int rw : {16, 32, 64, 128, 256}) cand.push_back({t, rw, 2});
+    for (int t : {64, 128, 192, 256})
+      for (int rw : {16, 32, 48, 64, 128, 256}) cand.push_back({t, rw, 2});
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));

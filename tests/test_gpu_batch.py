@@ -125,9 +125,9 @@ def test_batch_autotune_keeps_results(torch_cuda):
         c.init(i, ls.noisy_density(d["Lx"], d["Ly"], d["seed"]))
     t, r, ms = a.autotune(nsteps=2)
     assert t in (64, 128, 192, 256, 512) and ms > 0
-    # autotune took 15 one-step shapes x (1 + 2) steps and 15 two-step shapes
+    # autotune took 15 one-step shapes x (1 + 2) steps and 24 two-step shapes
     # x (2 + 2) steps
-    c.step(15 * 3 + 15 * 4)
+    c.step(15 * 3 + 24 * 4)
     a.step(1)
     c.step(1)
     for i in range(len(insts)):

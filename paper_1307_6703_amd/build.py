@@ -1,6 +1,7 @@
 """Build the HIP library liblbvdw.so (gfx950) in-tree.
 
-Compiles csrc/lb_device.hip and csrc/lb_api.hip with hipcc for gfx950 only.
+Compiles the HIP sources of csrc/ (lattice step, C ABI, batch, surrogate)
+with hipcc for gfx950 only.
 Packed FP32 instructions are disabled for device code. Multiply-adds fuse only
 within one source expression (-ffp-contract=on), so the arithmetic of a node
 does not depend on how the compiler lays out a kernel instance: every launch

@@ -22,12 +22,12 @@
 namespace sg {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int TW = 64;   // output columns per conv tile
 constexpr int TR = 8;    // output rows per conv tile (one per wave)
 constexpr int CNT = 512; // threads per conv workgroup (TR waves)
-constexpr int EH = 4;    // rows per pass of the conv epilogue
 constexpr int NTH = 256; // threads per workgroup of the other kernels
 
 __device__ __forceinline__ float bf2f(bf16 v) { return (float)v; }
@@ -52,12 +52,12 @@ __host__ __device__ constexpr int kpad() { return (9 * CI + 31) / 32 * 32; }
 // 3x3 convolution (forward, or input-gradient with flipped weights).
 // Persistent workgroups: the packed weights are staged in LDS once, then each
 // workgroup walks tiles of TR rows x TW columns of one image. Each of its TR
-// waves owns one output row: 4 M-subtiles of 16 pixels by CO/16 N-subtiles.
-// The next tile's input is loaded into registers while the matrix cores work
-// on the current one; results go through LDS (FP32, in the input tile's
-// buffer, half the rows at a time) so that the epilogue reads and writes
-// whole 16-byte vectors of 8 channels. Eight waves per workgroup and about
-// 115 KB of LDS: two waves per SIMD.
+// waves owns one output row: 4 subtiles of 16 pixels by CO/16 subtiles of 16
+// output channels, computed as W X^T so that every lane ends with 4
+// consecutive channels of one pixel and the epilogue (bias, SiLU, residual,
+// bf16 stores) runs straight from the accumulators. The next tile's input is
+// loaded into registers while the matrix cores work on the current one.
+// Eight waves per workgroup and about 115 KB of LDS: two waves per SIMD.
 // ---------------------------------------------------------------------------
 template <int CI, int CO>
 struct ConvShape {
@@ -68,7 +68,6 @@ struct ConvShape {
   static constexpr int CH = CI / 8;   // 16-byte chunks per input pixel
   static constexpr int NLD = TROWS * TCOLS * CH;
   static constexpr int PER = (NLD + CNT - 1) / CNT;  // input chunks per thread
-  static constexpr int SE = CO + 4;   // LDS stride (floats) of one output pixel
 };
 
 // The 16-byte chunks a thread loads for every tile: chunk j is input pixel
@@ -117,15 +116,9 @@ template <int CI, int CO, int MODE>
 __global__ __launch_bounds__(CNT) void conv_kernel(ConvArgs a) {
   using S = ConvShape<CI, CO>;
   constexpr int KP = S::KP, NS = S::NS, PX = S::PX, WS = S::WS, TCOLS = S::TCOLS;
-  constexpr int K = S::K, SE = S::SE;
-  constexpr int C8 = CO / 8;
-  // The input tile (bf16) and, once the matrix work is done, the FP32 output
-  // of half the tile's rows share one LDS buffer.
-  constexpr int SX_BYTES = S::TROWS * TCOLS * PX * 2, SE_BYTES = EH * TW * SE * 4;
-  __shared__ __attribute__((aligned(16))) unsigned char sbuf[SX_BYTES > SE_BYTES ? SX_BYTES : SE_BYTES];
+  constexpr int K = S::K;
+  __shared__ __attribute__((aligned(16))) bf16 sx[S::TROWS * TCOLS * PX];
   __shared__ __attribute__((aligned(16))) bf16 sw[CO * WS];
-  bf16* sx = (bf16*)sbuf;
-  float* se = (float*)sbuf;
 
   const int tid = threadIdx.x;
   for (int i = tid; i < CO * (KP / 8); i += CNT) {
@@ -137,6 +130,16 @@ __global__ __launch_bounds__(CNT) void conv_kernel(ConvArgs a) {
   const int ntiles = tilesX * tilesY * a.B;
   const int wave = tid >> 6, lane = tid & 63, lm = lane & 15, lg = lane >> 4;
 
+  // bias of the four output channels 16 ns + 4 lg .. +3 this lane holds
+  float bv[NS][4];
+#pragma unroll
+  for (int ns = 0; ns < NS; ++ns)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int co = ns * 16 + lg * 4 + r;
+      bv[ns][r] = (a.bias && (MODE != FWD_OUT || co < a.nout)) ? a.bias[co] : 0.f;
+    }
+
   const TileChunks<CI, CO> tc;
   uint4 pre[S::PER];
   if (blockIdx.x < ntiles) conv_load_tile<CI, CO>(pre, a.x, tc, blockIdx.x, tilesX, tilesY, a.H, a.W);
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(CNT) void conv_kernel(ConvArgs a) {
     const int ty = (tile / tilesX) % tilesY;
     const int img = tile / (tilesX * tilesY);
     const int x0 = tx * TW, h0 = ty * TR;
-    __syncthreads();  // the previous tile's readers of sbuf are done (and sw is staged)
+    __syncthreads();  // the previous tile's readers of sx are done (and sw is staged)
 #pragma unroll
     for (int j = 0; j < S::PER; ++j) {
       const int i = tid + j * CNT;
@@ -156,6 +159,9 @@ __global__ __launch_bounds__(CNT) void conv_kernel(ConvArgs a) {
     if (tile + (int)gridDim.x < ntiles)  // in flight during the matrix work
       conv_load_tile<CI, CO>(pre, a.x, tc, tile + gridDim.x, tilesX, tilesY, a.H, a.W);
 
+    // D = W X^T: the weights are the A operand (rows: output channels), the
+    // input pixels the B operand, so lane (lm, lg) ends with channels
+    // 16 ns + 4 lg .. +3 of pixel 16 ms + lm of the wave's row
     f32x4 acc[4][NS];
 #pragma unroll
     for (int ms = 0; ms < 4; ++ms)
@@ -168,121 +174,91 @@ __global__ __launch_bounds__(CNT) void conv_kernel(ConvArgs a) {
       const bool kv = k < K;
       const int tap = kv ? k / CI : 0, ci0 = kv ? k % CI : 0;
       const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-      bf16x8 bfr[NS];
+      bf16x8 wfr[NS];
 #pragma unroll
-      for (int ns = 0; ns < NS; ++ns) bfr[ns] = *(const bf16x8*)&sw[(ns * 16 + lm) * WS + k];
+      for (int ns = 0; ns < NS; ++ns) wfr[ns] = *(const bf16x8*)&sw[(ns * 16 + lm) * WS + k];
 #pragma unroll
       for (int ms = 0; ms < 4; ++ms) {
-        bf16x8 afr = *(const bf16x8*)&sx[((wave + 1 + dy) * TCOLS + (ms * 16 + lm + 1 + dx)) * PX + ci0];
-        if (!kv) afr = bf16x8{};
+        bf16x8 xfr = *(const bf16x8*)&sx[((wave + 1 + dy) * TCOLS + (ms * 16 + lm + 1 + dx)) * PX + ci0];
+        if (!kv) xfr = bf16x8{};
 #pragma unroll
         for (int ns = 0; ns < NS; ++ns)
-          acc[ms][ns] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[ns], acc[ms][ns], 0, 0, 0);
+          acc[ms][ns] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wfr[ns], xfr, acc[ms][ns], 0, 0, 0);
       }
     }
 
-    // Epilogue in two passes of EH rows: the waves of those rows put their
-    // results (plus the bias) into LDS, then all threads turn them into whole
-    // 16-byte vectors of 8 channels (coalesced). Work item i of a pass is
-    // pixel i / C8 of its rows, channels 8 (i % C8) .. +7. The global inputs
-    // of a thread's items (residual, previous pre-activation) are loaded
-    // before any store so their latencies overlap; a residual that is this
-    // layer's own input is read from the tile, before the output overwrites it.
-    constexpr int NIT = (EH * TW * C8 + CNT - 1) / CNT;  // items per thread and pass
-    const bool res_in_tile = MODE == FWD_RES && a.res == a.x;
-    bf16x8 rt[2][NIT];
-    if (MODE == FWD_RES && res_in_tile) {
+    // Epilogue straight from the accumulators, 8 bytes (4 channels) per lane
+    // and store; the four lanes lg of a pixel write 32 contiguous bytes. The
+    // inputs of every store (residual, previous pre-activation) are loaded
+    // first so their latencies overlap; a residual that is this layer's own
+    // input comes from the tile.
+    const int h = h0 + wave;
+    if (MODE == FWD_OUT) {
+      if (h < a.H) {
 #pragma unroll
-      for (int p = 0; p < 2; ++p)
+        for (int ms = 0; ms < 4; ++ms) {
+          const int xx = x0 + ms * 16 + lm;
+          if (xx >= a.W) continue;
+          const int64_t q = ((int64_t)img * a.H + h) * a.W + xx;
 #pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-          const int i = tid + it * CNT;
-          const int pi = i / C8, c8 = i % C8;
-          const int row = p * EH + pi / TW, px = pi % TW;
-          rt[p][it] = i < EH * TW * C8 ? *(const bf16x8*)&sx[((row + 1) * TCOLS + (px + 1)) * PX + c8 * 8]
-                                       : bf16x8{};
+          for (int ns = 0; ns < NS; ++ns)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int co = ns * 16 + lg * 4 + r;
+              if (co < a.nout) a.yf[q * a.nout + co] = acc[ms][ns][r] + bv[ns][r];
+            }
         }
-    }
-    __syncthreads();  // every wave is done with the input tile
+      }
+    } else {
+      const bool res_in_tile = MODE == FWD_RES && a.res == a.x;
+      int64_t off[4];
+      bool ok[4];
+      bf16x4 rr[4][NS], zp[4][NS];
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      if ((wave >= EH) == (p == 1)) {  // D[m][n] -> pixel (16 ms + 4 lg + r), channel 16 ns + lm
+      for (int ms = 0; ms < 4; ++ms) {
+        const int xx = x0 + ms * 16 + lm;
+        ok[ms] = h < a.H && xx < a.W;
+        off[ms] = (((int64_t)img * a.H + (ok[ms] ? h : 0)) * a.W + (ok[ms] ? xx : 0)) * CO + lg * 4;
 #pragma unroll
         for (int ns = 0; ns < NS; ++ns) {
-          const int co = ns * 16 + lm;
-          const float bv = (a.bias && (MODE != FWD_OUT || co < a.nout)) ? a.bias[co] : 0.f;
-#pragma unroll
-          for (int ms = 0; ms < 4; ++ms)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              se[((wave - p * EH) * TW + ms * 16 + lg * 4 + r) * SE + co] = acc[ms][ns][r] + bv;
-        }
-      }
-      __syncthreads();
-      if (MODE == FWD_OUT) {
-        for (int i = tid; i < EH * TW; i += CNT) {
-          const int row = p * EH + i / TW, px = i % TW, h = h0 + row, xx = x0 + px;
-          if (h >= a.H || xx >= a.W) continue;
-          const int64_t q = ((int64_t)img * a.H + h) * a.W + xx;
-          for (int c = 0; c < a.nout; ++c) a.yf[q * a.nout + c] = se[i * SE + c];
-        }
-      } else {
-        int64_t off[NIT];
-        bool ok[NIT];
-        bf16x8 rr[NIT], zp[NIT];
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-          const int i = tid + it * CNT;
-          const int pi = i / C8, c8 = i % C8;
-          const int row = p * EH + pi / TW, px = pi % TW, h = h0 + row, xx = x0 + px;
-          ok[it] = i < EH * TW * C8 && h < a.H && xx < a.W;
-          off[it] = (((int64_t)img * a.H + (ok[it] ? h : 0)) * a.W + (ok[it] ? xx : 0)) * CO + c8 * 8;
-          rr[it] = bf16x8{};
-          zp[it] = bf16x8{};
+          rr[ms][ns] = bf16x4{};
+          zp[ms][ns] = bf16x4{};
           if (MODE == FWD_RES) {
             if (res_in_tile)
-              rr[it] = rt[p][it];
-            else if (ok[it])
-              rr[it] = *(const bf16x8*)(a.res + off[it]);
-          } else if (MODE == BWD && ok[it]) {
-            if (a.res) rr[it] = *(const bf16x8*)(a.res + off[it]);
-            zp[it] = *(const bf16x8*)(a.zprev + off[it]);
+              rr[ms][ns] = *(const bf16x4*)&sx[((wave + 1) * TCOLS + (ms * 16 + lm + 1)) * PX + ns * 16 + lg * 4];
+            else if (ok[ms])
+              rr[ms][ns] = *(const bf16x4*)(a.res + off[ms] + ns * 16);
+          } else if (MODE == BWD && ok[ms]) {
+            if (a.res) rr[ms][ns] = *(const bf16x4*)(a.res + off[ms] + ns * 16);
+            zp[ms][ns] = *(const bf16x4*)(a.zprev + off[ms] + ns * 16);
           }
-        }
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-          if (!ok[it]) continue;
-          const int i = tid + it * CNT;
-          const int pi = i / C8, c8 = i % C8;
-          const float4 v0 = *(const float4*)&se[pi * SE + c8 * 8];
-          const float4 v1 = *(const float4*)&se[pi * SE + c8 * 8 + 4];
-          const float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-          bf16x8 yo, zo;
-          if (MODE == FWD_FIRST) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              yo[j] = f2bf(silu(v[j]));
-              zo[j] = f2bf(v[j]);
-            }
-          } else if (MODE == FWD_RES) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              yo[j] = f2bf(bf2f(rr[it][j]) + silu(v[j]));
-              zo[j] = f2bf(v[j]);
-            }
-          } else {  // BWD: v = dL/dh of this layer's input (+ the residual path)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              const float g = v[j] + bf2f(rr[it][j]);
-              zo[j] = f2bf(g);
-              yo[j] = f2bf(g * silu_grad(bf2f(zp[it][j])));
-            }
-          }
-          *(bf16x8*)(a.y + off[it]) = yo;
-          if (a.z) *(bf16x8*)(a.z + off[it]) = zo;
         }
       }
-      __syncthreads();  // the pass's output is read before the next one overwrites it
+#pragma unroll
+      for (int ms = 0; ms < 4; ++ms) {
+        if (!ok[ms]) continue;
+#pragma unroll
+        for (int ns = 0; ns < NS; ++ns) {
+          bf16x4 yo, zo;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float v = acc[ms][ns][r] + bv[ns][r];
+            if (MODE == FWD_FIRST) {
+              yo[r] = f2bf(silu(v));
+              zo[r] = f2bf(v);
+            } else if (MODE == FWD_RES) {
+              yo[r] = f2bf(bf2f(rr[ms][ns][r]) + silu(v));
+              zo[r] = f2bf(v);
+            } else {  // BWD: v = dL/dh of this layer's input (+ the residual path)
+              const float g = v + bf2f(rr[ms][ns][r]);
+              zo[r] = f2bf(g);
+              yo[r] = f2bf(g * silu_grad(bf2f(zp[ms][ns][r])));
+            }
+          }
+          *(bf16x4*)(a.y + off[ms] + ns * 16) = yo;
+          if (a.z) *(bf16x4*)(a.z + off[ms] + ns * 16) = zo;
+        }
+      }
     }
   }
 }

@@ -204,10 +204,12 @@ lb_status lb_batch_shift_equilibrium_device(lb_batch* b, const double* d_from,
 
 /* Advance only the instances with mask[i] != 0 by nsteps (even, so that
  * their buffer parity stays that of the batch), with the batch's launch
- * shape, no graph and no drift shift; the last step writes their moments;
- * one FP64 check per instance at the end (flags instabilities as the
- * periodic checks do). The batch step counter does not change. Launches
- * are asynchronous; the tile upload synchronises the stream first. */
+ * shape (two steps per launch: pairs, with two single steps in place of one
+ * pair when the number of pairs is odd; same bits either way), no graph and
+ * no drift shift; the last step writes their moments; one FP64 check per
+ * instance at the end (flags instabilities as the periodic checks do). The
+ * batch step counter does not change. Launches are asynchronous; each tile
+ * upload synchronises the stream first. */
 lb_status lb_batch_step_subset(lb_batch* b, int64_t nsteps, const int32_t* mask);
 
 /* ---- launch shape ----------------------------------------------------------

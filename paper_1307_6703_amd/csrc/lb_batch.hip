@@ -680,18 +680,41 @@ lb_status lb_batch_step_subset(lb_batch* b, int64_t nsteps, const int32_t* mask)
       any = true;
     }
   if (!any || nsteps == 0) return LB_OK;
-  // one step per launch (the buffer parity must flip once per step)
-  const int th = b->fuse == 2 ? b->threads1 : b->threads;
-  const int rw = b->fuse == 2 ? b->rows1 : b->rows;
-  std::vector<Tile> t = tile_list(b, th, rw, mask);
-  HIPCHK(hipMemcpyAsync(b->dsub, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice, b->st));
-  HIPCHK(hipStreamSynchronize(b->st));  // t is a host temporary
+  // Every launch flips the buffer parity once, and the subset must end on
+  // the batch's parity, so it takes an even number of launches: with the
+  // two-step shape, pairs of steps, and when their count is odd, two single
+  // steps (one-step shape) in place of one pair.
+  int64_t pairs = 0, singles = nsteps;
+  if (b->fuse == 2) {
+    pairs = nsteps / 2;
+    singles = 0;
+    if (pairs % 2) {
+      pairs -= 1;
+      singles = 2;
+    }
+  }
   lb_status lr = upload_list(b, mask, b->dlist_sub, &b->n_sub, &b->nb_sub);
   if (lr != LB_OK) return lr;
-  for (int64_t s = 0; s < nsteps; ++s) {
-    const int flags = (s == nsteps - 1) ? lbk::kWriteMoments : 0;
-    HIPCHK(lbk::launch_step(b->fp32, th, b->ddesc, b->dsub, (int)t.size(), b->parity ^ (int)(s & 1),
-                            flags, b->st));
+  int64_t launch = 0;
+  const int64_t launches = singles + pairs;
+  for (int kind = 1; kind <= 2; ++kind) {
+    const int64_t n = kind == 1 ? singles : pairs;
+    if (n == 0) continue;
+    const int th = kind == 2 ? b->threads : (b->fuse == 2 ? b->threads1 : b->threads);
+    const int rw = kind == 2 ? b->rows : (b->fuse == 2 ? b->rows1 : b->rows);
+    std::vector<Tile> t = tile_list(b, th, rw, mask, kind == 2 ? 7 : 3);
+    if ((int)t.size() > b->B.max_tiles) return fail(LB_EINVAL, "too many tiles for the workspace");
+    // stream order: the copy waits for earlier launches that read the table
+    HIPCHK(hipMemcpyAsync(b->dsub, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice, b->st));
+    HIPCHK(hipStreamSynchronize(b->st));  // t is a host temporary
+    for (int64_t s = 0; s < n; ++s, ++launch) {
+      const int flags = (launch == launches - 1) ? lbk::kWriteMoments : 0;
+      const int par = b->parity ^ (int)(launch & 1);
+      if (kind == 2)
+        HIPCHK(lbk::launch_step2(th, b->ddesc, b->dsub, (int)t.size(), par, flags, b->st));
+      else
+        HIPCHK(lbk::launch_step(b->fp32, th, b->ddesc, b->dsub, (int)t.size(), par, flags, b->st));
+    }
   }
   lb_status r = enqueue_checks(b, 0, -1, mask);
   if (r != LB_OK) return r;

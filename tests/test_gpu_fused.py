@@ -166,8 +166,9 @@ def test_batch_fused_equals_one_step_batch(torch_cuda, check_every, launch):
             for x, y in zip(a.moments(i), b.moments(i)):
                 assert np.array_equal(x, y), (n, i)
     mask = [1 if i % 2 else 0 for i in range(len(insts))]
-    a.step_subset(10, mask)
-    b.step_subset(10, mask)
+    for n in (10, 8, 2):  # 4 pairs + 2 single steps, 4 pairs, 2 single steps
+        a.step_subset(n, mask)
+        b.step_subset(n, mask)
     a.step(3)
     b.step(3)
     for i in range(len(insts)):

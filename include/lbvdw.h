@@ -236,7 +236,7 @@ lb_status lb_batch_set_launch(lb_batch* b, int32_t threads, int32_t rows);
 lb_status lb_set_launch_fused(lb_handle* h, int32_t threads, int32_t rows);
 lb_status lb_get_steps_per_launch(lb_handle* h, int32_t* steps);
 /* The same for a batch (all instances share the shape; rows 0: 64). Subset
- * steps (lb_batch_step_subset) always run one step per launch. */
+ * steps (lb_batch_step_subset) run in pairs too (see there). */
 lb_status lb_batch_set_launch_fused(lb_batch* b, int32_t threads, int32_t rows);
 lb_status lb_batch_get_steps_per_launch(lb_batch* b, int32_t* steps);
 

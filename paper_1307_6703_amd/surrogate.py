@@ -465,14 +465,25 @@ class SurrogateRun:
     reentry "shift" adds f_eq(prediction) - f_eq(chunk start) to the
     populations, so they keep their non-equilibrium part (an accepted
     persistence prediction then leaves the lattice exactly as it was);
-    "eq" replaces them by f_eq(prediction)."""
+    "eq" replaces them by f_eq(prediction).
+
+    budget (a run-level tolerance, or None) replaces the rotation: the
+    error of an instance's last passed audit stands for the error of each
+    chunk taken from the predictor after it, these add up until the next
+    audit, and a trusted instance is audited when the next chunk would take
+    the sum beyond the budget, or after audit_every chunks at most. An
+    audited chunk runs on the lattice, so the sum starts again from zero."""
 
     def __init__(self, net: Optional[Net], batch: Batch, draws, K: int = 50, tol: float = 1e-2,
                  mass_tol: float = 1e-2, audit_every: int = 8, need: int = 1, norm: str = "max",
-                 scales=None, predictor: str = "net", reentry: str = "shift"):
+                 scales=None, predictor: str = "net", reentry: str = "shift",
+                 budget: Optional[float] = None):
         import torch
         if norm not in ("max", "rms"):
             raise ValueError("norm must be 'max' or 'rms'")
+        if budget is not None and not budget >= 0:
+            raise ValueError("budget must be None or >= 0")
+        self.budget = budget
         if predictor not in ("net", "persist") or (predictor == "net" and net is None):
             raise ValueError("predictor must be 'net' (with a network) or 'persist'")
         if reentry not in ("shift", "eq"):
@@ -493,6 +504,9 @@ class SurrogateRun:
         self.out = torch.empty((self.B, H, W, OUT), dtype=torch.float32, device=dev)
         self.cmp = torch.empty((self.B, 6), dtype=torch.float64, device=dev)
         self.passes = np.zeros(self.B, dtype=np.int64)
+        self.est = np.zeros(self.B)            # error of the last passed audit
+        self.spent = np.zeros(self.B)          # estimated error taken since then
+        self.since = np.zeros(self.B, dtype=np.int64)  # chunks since the last audit
         self.stats = RunStats()
 
     def chunk(self):
@@ -511,7 +525,11 @@ class SurrogateRun:
         mass_drift = np.abs(raw[:, 0] - raw[:, 1]) / raw[:, 1]
         bad = (raw[:, 3] > 0) | ~(mass_drift <= self.mass_tol)
         trusted = self.passes >= self.need
-        audit = ~bad & (~trusted | ((np.arange(B) % self.audit_every) == (c % self.audit_every)))
+        if self.budget is None:
+            due = (np.arange(B) % self.audit_every) == (c % self.audit_every)
+        else:
+            due = (self.spent + self.est > self.budget) | (self.since + 1 >= self.audit_every)
+        audit = ~bad & (~trusted | due)
         lattice = bad | audit | ~trusted
         accept = ~lattice
         self.stats.mass_rejects += int(bad.sum())
@@ -529,6 +547,7 @@ class SurrogateRun:
                 self.stats.audit_errors.append(float(err[i]))
                 if err[i] <= self.tol:
                     self.passes[i] += 1
+                    self.est[i] = float(err[i])
                 else:
                     self.stats.audit_failures += 1
                     self.passes[i] = 0
@@ -536,6 +555,9 @@ class SurrogateRun:
             b.shift_equilibrium(self.f0, self.f1, accept.astype(np.int32))
         else:
             b.set_equilibrium(self.f1, accept.astype(np.int32))
+        # chunks on the lattice are exact; accepted ones add their estimate
+        self.spent = np.where(lattice, 0.0, self.spent + self.est)
+        self.since = np.where(lattice, 0, self.since + 1)
         self.stats.lattice_chunks += int(lattice.sum())
         self.stats.surrogate_chunks += int(accept.sum())
         self.stats.chunks += 1
@@ -550,7 +572,8 @@ def _audited_eval(net, test, start, eval_chunks, K, tol, audit_every, log, shape
     eval_chunks * K steps, then the same span from the same state with the
     audited network (max and RMS norms) and with the persistence baseline,
     re-entering accepted chunks by shift (the default) and, for the
-    baseline, also as pure equilibria."""
+    baseline, also as pure equilibria; both predictors also with audits
+    spaced by a run-level error budget equal to the tolerance."""
     import torch
     n = len(test)
     steps = eval_chunks * K
@@ -564,15 +587,25 @@ def _audited_eval(net, test, start, eval_chunks, K, tol, audit_every, log, shape
     fr = ref.moments_device()
     ref.close()
     win = {"start_step": start, "steps": steps, "lattice_seconds": round(t_lb, 4)}
-    for key, norm, pred, reentry in (
-            ("audit_max", "max", "net", "shift"), ("audit_rms", "rms", "net", "shift"),
-            ("persist_max", "max", "persist", "shift"),
-            ("persist_max_eq_reentry", "max", "persist", "eq")):
+    # (key, norm, predictor, re-entry, run-level budget, longest audit gap);
+    # the control fails every audit, so every chunk runs on the lattice
+    # (subset steps, which skip the drift shift the reference applies): it
+    # measures how far the lattice alone drifts from the reference through
+    # the same machinery
+    for key, norm, pred, reentry, budget, gap in (
+            ("lattice_control", "max", "persist", "shift", None, audit_every),
+            ("audit_max", "max", "net", "shift", None, audit_every),
+            ("audit_rms", "rms", "net", "shift", None, audit_every),
+            ("persist_max", "max", "persist", "shift", None, audit_every),
+            ("persist_max_eq_reentry", "max", "persist", "eq", None, audit_every),
+            ("audit_max_budget", "max", "net", "shift", tol, 2 * audit_every),
+            ("persist_max_budget", "max", "persist", "shift", tol, 2 * audit_every)):
         sgb = _batch_for(test, shape=shape)
         sgb.step(start)
         m0 = np.array([sgb.reduce(i)["mass"] for i in range(n)])
-        run = SurrogateRun(net, sgb, test, K=K, tol=tol, audit_every=audit_every, norm=norm,
-                           predictor=pred, reentry=reentry)
+        run = SurrogateRun(net, sgb, test, K=K, tol=-1.0 if key == "lattice_control" else tol,
+                           audit_every=gap, norm=norm, predictor=pred, reentry=reentry,
+                           budget=budget)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         for _ in range(eval_chunks):

@@ -468,3 +468,33 @@ def test_shift_reentry_keeps_the_non_equilibrium_part(torch_cuda):
             assert np.allclose(u, v, rtol=0, atol=1e-5)
     for bb in (a, b, c, e, g):
         bb.close()
+
+
+def test_budget_policy_spaces_the_audits(torch_cuda):
+    """Audits spaced by a run-level error budget: with budget 0 every chunk
+    after the probation audit is audited again (once the first audit has
+    measured a nonzero error); with a budget no chunk can exhaust, a trusted
+    instance is audited only after the longest gap; the results agree with
+    the rotation policy's bookkeeping."""
+    from paper_1307_6703_amd import surrogate as sg
+    _say("audited run, budget policy")
+    draws = _draws(4, 64, 32, 13)
+    net = sg.Net(4, 32, 64)
+    net.set_params(np.zeros(sg.param_count(), np.float32))
+    a = sg._batch_for(draws, check_every=0, drift=False)
+    run = sg.SurrogateRun(net, a, draws, K=10, tol=1.0, audit_every=100, budget=0.0)
+    acc = [run.chunk() for _ in range(4)]
+    assert all(not x.any() for x in acc)  # every chunk on the lattice
+    assert run.stats.audits == 16 and run.stats.audit_failures == 0
+    assert (run.est > 0).all()
+    b = sg._batch_for(draws, check_every=0, drift=False)
+    run = sg.SurrogateRun(net, b, draws, K=10, tol=1.0, audit_every=3, budget=1e9)
+    acc = [list(np.nonzero(run.chunk())[0]) for _ in range(7)]
+    # probation audit, two trusted chunks, audit at the gap, two more, audit
+    assert acc == [[], [0, 1, 2, 3], [0, 1, 2, 3], [], [0, 1, 2, 3], [0, 1, 2, 3], []]
+    assert run.stats.audits == 12 and run.stats.surrogate_chunks == 16
+    with pytest.raises(ValueError):
+        sg.SurrogateRun(net, b, draws, K=10, budget=-1.0)
+    for bb in (a, b):
+        bb.close()
+    net.close()

@@ -466,7 +466,19 @@ def test_shift_reentry_keeps_the_non_equilibrium_part(torch_cuda):
     for i in range(3):
         for u, v in zip(e.moments(i), g.moments(i)):
             assert np.allclose(u, v, rtol=0, atol=1e-5)
-    for bb in (a, b, c, e, g):
+    # errors: no "from" fields, a batch of uneven sizes
+    import ctypes
+    from paper_1307_6703_amd import Batch, LBError, lbvdw
+    m = np.ones(3, np.int32)
+    st = lbvdw.load_library().lb_batch_shift_equilibrium_device(
+        a._h, None, ctypes.c_void_p(f1.data_ptr()), m.ctypes.data_as(lbvdw._I32P))
+    assert st == lbvdw.LB_EINVAL
+    un = Batch([dict(Lx=70, Ly=20), dict(Lx=64, Ly=20)], fp32=True)
+    un.init(0, np.ones((20, 70)))
+    un.init(1, np.ones((20, 64)))
+    with pytest.raises(LBError):
+        un.shift_equilibrium(f1[:2], f1[:2], [1, 1])
+    for bb in (a, b, c, e, g, un):
         bb.close()
 
 

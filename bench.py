@@ -185,7 +185,6 @@ def main():
               "has no multi-GPU path; run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import lbsynth as ls

@@ -147,7 +147,8 @@ def batched_bench(steps: int, seed: int = 1307):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=10000,
+                    help="timed steps of the headline lattice (10k, about 1.7 s)")
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--launch", default=None,
                     help="threads,rows[,steps per launch] of the step kernel (steps 2: the "
@@ -156,8 +157,9 @@ def main():
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--batched-steps", type=int, default=2000,
-                    help="steps of the 96-lattice batched sweep reported beside the headline (0: skip)")
+    ap.add_argument("--batched-steps", type=int, default=20000,
+                    help="timed steps of the 96-lattice batched sweep reported beside the "
+                         "headline (20k, about 2.3 s; 0: skip)")
     ap.add_argument("--surrogate-seconds", type=float, default=30.0,
                     help="training time limit of the learned surrogate reported beside the "
                          "headline (0: skip)")

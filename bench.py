@@ -95,9 +95,10 @@ def cpu_baseline(w, n0, fext, seconds: float):
             "sample": f"{total} FP64 steps of the full {w.Lx}x{w.Ly} lattice ({dt:.1f} s)"}
 
 
-def batched_bench(steps: int, seed: int = 1307):
+def batched_bench(steps: int, seed: int = 1307, launch=None):
     """The batched sweep: 96 uneven lattices advanced together (one launch per
-    step over all their tiles, HIP-graph replay), autotuned launch shape.
+    step over all their tiles, HIP-graph replay), autotuned launch shape
+    unless `launch` = (threads, rows, steps per launch) fixes it.
     Returns aggregate MLUPS = sum of nodes x steps / time."""
     import torch
     import lbsynth as ls
@@ -122,7 +123,11 @@ def batched_bench(steps: int, seed: int = 1307):
     draws = [w for w, st in zip(pool, status) if st == 0][:96]
     replaced = pool.index(draws[-1]) + 1 - len(draws)
     b = batch_of(draws)
-    th, rw, _ = b.autotune(nsteps=40)
+    if launch is None:
+        th, rw, _ = b.autotune(nsteps=40)
+    else:
+        th, rw = launch[0], launch[1]
+        b.set_launch(th, rw, steps_per_launch=launch[2] if len(launch) > 2 else 1)
     b.step(100)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -160,6 +165,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=20000,
                     help="timed steps of the 96-lattice batched sweep reported beside the "
                          "headline (20k, about 2.3 s; 0: skip)")
+    ap.add_argument("--batched-launch", default=None,
+                    help="threads,rows[,steps per launch] of the batched sweep (default: autotuned)")
     ap.add_argument("--surrogate-seconds", type=float, default=30.0,
                     help="training time limit of the learned surrogate reported beside the "
                          "headline (0: skip)")
@@ -308,7 +315,8 @@ def main():
     del lat
     torch.cuda.empty_cache()
     if args.batched_steps > 0:
-        out["batched"] = batched_bench(args.batched_steps)
+        bl = tuple(int(v) for v in args.batched_launch.split(",")) if args.batched_launch else None
+        out["batched"] = batched_bench(args.batched_steps, launch=bl)
         print(f"[bench] batched: {out['batched']['MLUPS']} MLUPS", file=sys.stderr, flush=True)
     if args.surrogate_seconds > 0:
         from paper_1307_6703_amd import surrogate

@@ -108,7 +108,7 @@ bool wgrad_supported(int ci, int co) {
 }
 
 int conv_grid(int B, int H, int W) {
-  const int64_t tiles = (int64_t)((W + 63) / 64) * ((H + 3) / 4) * B;
+  const int64_t tiles = (int64_t)((W + sg::TW - 1) / sg::TW) * ((H + sg::TR - 1) / sg::TR) * B;
   return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kConvGridMax));
 }
 
@@ -156,8 +156,9 @@ lb_status wgrad(int ci, int co, int cir, int cor, const void* x, const void* gz,
   a.B = B;
   a.H = H;
   a.W = W;
-  const int64_t nseg = (int64_t)((W + 63) / 64) * H * B;
-  const int grid = (int)std::min<int64_t>(blocks, nseg);
+  const int64_t units = (int64_t)((W + sg::WG_SEG - 1) / sg::WG_SEG) *
+                        ((H + sg::WG_RC - 1) / sg::WG_RC) * B;
+  const int grid = (int)std::min<int64_t>(blocks, units);
   HIPCHK(sg::launch_wgrad(ci, co, a, grid, st));
   uintptr_t t = (uintptr_t)(part + (int64_t)blocks * (9 * ci * co + co));
   t = (t + 7) & ~(uintptr_t)7;

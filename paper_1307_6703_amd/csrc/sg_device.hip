@@ -25,9 +25,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int TW = 64;   // output columns per conv tile
-constexpr int TR = 8;    // output rows per conv tile (one per wave)
-constexpr int CNT = 512; // threads per conv workgroup (TR waves)
+constexpr int CNT = 64 * TR;  // threads per conv workgroup (TR waves)
 constexpr int NTH = 256; // threads per workgroup of the other kernels
 
 __device__ __forceinline__ float bf2f(bf16 v) { return (float)v; }
@@ -299,28 +297,31 @@ hipError_t launch_conv(int ci, int co, int mode, const ConvArgs& a, int grid, hi
 
 // ---------------------------------------------------------------------------
 // Weight gradient: dW[tap*CI + ci][co] = sum_p x[p + tap][ci] gz[p][co], a GEMM
-// with the pixels as the contraction. A persistent workgroup walks row
-// segments of 64 pixels; it stages the nine shifted copies of the input (one
-// per tap) and the output gradient in LDS, transposed so that pixels are
-// contiguous, and accumulates its share of the 9CI x CO tiles in registers.
-// The next segment's blocks are loaded into registers during the matrix work.
-// Partial sums per workgroup go to `part`; wgrad_reduce adds them in a fixed
-// order.
+// with the pixels as the contraction. A persistent workgroup takes work units
+// of WG_RC rows of one 64-pixel column segment of one image and marches down
+// them. Each input row is loaded once, transposed (pixels contiguous) and
+// stored in LDS three times, shifted by dx = -1, 0, 1; three rows stay in a
+// ring (row mod 3), so the A operand of tap (dy, dx) for output row h is the
+// copy dx of ring row h + dy. The output gradient row is staged transposed
+// beside it; the next row's blocks are loaded into registers during the
+// matrix work. The workgroup accumulates its share of the 9CI x CO tiles in
+// registers; partial sums per workgroup go to `part`, and wgrad_reduce adds
+// them in a fixed order.
 // ---------------------------------------------------------------------------
 template <int CI, int CO>
 __global__ __launch_bounds__(NTH) void wgrad_kernel(WgradArgs a) {
   constexpr int M = 9 * CI, MS = (M + 15) / 16, NS = CO / 16;
-  constexpr int SEG = 64, PS = SEG + 8;  // pixels per segment, LDS row stride
-  constexpr int MPW = (MS + 3) / 4;      // M-subtiles per wave (strided by 4)
-  // A^T[tap*CI + ci][p] = x[h + dy][x0 + p + dx][ci] (0 outside rows, or past W) and
-  // gz^T[co][p] are built from blocks of 8 pixels x 8 channels: eight 16-byte
-  // loads, a register transpose, eight 16-byte LDS stores. Block `it` < NA is
-  // (c8, group, tap) of A, the rest (c8, group) of gz; a thread owns blocks
-  // tid + j NTH.
-  constexpr int CA = CI / 8, NA = 9 * (SEG / 8) * CA, NB = NA + (SEG / 8) * (CO / 8);
+  constexpr int SEG = WG_SEG, PS = SEG + 8;  // pixels per segment, LDS row stride
+  constexpr int MPW = (MS + 3) / 4;          // M-subtiles per wave (strided by 4)
+  constexpr int RING = 3 * CI * PS;      // one ring row: three shifted copies
+  // Blocks of 8 pixels x 8 channels: eight 16-byte loads, a register
+  // transpose, eight 16-byte LDS stores. Block it < NA is (c8, group, dx)
+  // of the input row, the rest (c8, group) of the output-gradient row; a
+  // thread owns blocks tid + j NTH.
+  constexpr int CA = CI / 8, NA = 3 * (SEG / 8) * CA, NB = NA + (SEG / 8) * (CO / 8);
   constexpr int IPT = (NB + NTH - 1) / NTH;
-  __shared__ __attribute__((aligned(16))) bf16 sa[MS * 16 * PS];  // A^T[m][p]
-  __shared__ __attribute__((aligned(16))) bf16 sg[CO * PS];       // gz^T[co][p]
+  __shared__ __attribute__((aligned(16))) bf16 sa[3 * RING];  // [row mod 3][dx + 1][ci][p]
+  __shared__ __attribute__((aligned(16))) bf16 sg[CO * PS];   // gz^T[co][p]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lm = lane & 15, lg = lane >> 4;
 
   f32x4 acc[MPW][NS];
@@ -330,27 +331,35 @@ __global__ __launch_bounds__(NTH) void wgrad_kernel(WgradArgs a) {
     for (int ns = 0; ns < NS; ++ns) acc[i][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.f;  // bias gradient partial of channel tid (tid < CO)
 
-  // rows of A^T past M stay zero
-  for (int i = tid; i < (MS * 16 - M) * PS; i += NTH) sa[M * PS + i] = (bf16)0.f;
+  // this lane's A rows: m = 16 ms + lm of each of its M-subtiles, as
+  // (dy, offset of copy dx and channel ci within a ring row); m >= M is zero
+  int a_dy[MPW], a_off[MPW];
+  bool a_ok[MPW];
+#pragma unroll
+  for (int i = 0; i < MPW; ++i) {
+    const int m = (wave + 4 * i) * 16 + lm;
+    const int tap = m / CI, ci = m % CI;
+    a_ok[i] = m < M;
+    a_dy[i] = a_ok[i] ? tap / 3 - 1 : 0;
+    a_off[i] = a_ok[i] ? ((tap % 3) * CI + ci) * PS : 0;
+  }
 
   const int segX = (a.W + SEG - 1) / SEG;
-  const int nseg = segX * a.H * a.B;
-  // the blocks of segment sgi, loaded into registers one segment ahead of
-  // the matrix work
+  const int chunks = (a.H + WG_RC - 1) / WG_RC;
+  const int nunits = segX * chunks * a.B;
   uint4 in[IPT][8];
-  auto load = [&](int sgi) {
-    const int sx = sgi % segX, h = (sgi / segX) % a.H, img = sgi / (segX * a.H);
-    const int x0 = sx * SEG;
+  // blocks of input row hin (zero outside the image) and, if hg >= 0, of
+  // output-gradient row hg, of column segment x0 of image img
+  auto load = [&](int img, int x0, int hin, int hg) {
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
       const int it = tid + j * NTH;
 #pragma unroll
       for (int q = 0; q < 8; ++q) in[j][q] = uint4{0u, 0u, 0u, 0u};
       if (it < NA) {
-        const int c8 = it % CA, t2 = it / CA, g = t2 % (SEG / 8), tap = t2 / (SEG / 8);
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1, hh = h + dy;
-        if (hh >= 0 && hh < a.H) {
-          const bf16* xr = a.x + ((int64_t)img * a.H + hh) * a.W * CI + c8 * 8;
+        const int c8 = it % CA, t2 = it / CA, g = t2 % (SEG / 8), dx = t2 / (SEG / 8) - 1;
+        if (hin >= 0 && hin < a.H) {
+          const bf16* xr = a.x + ((int64_t)img * a.H + hin) * a.W * CI + c8 * 8;
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
             const int p = g * 8 + q;
@@ -359,31 +368,30 @@ __global__ __launch_bounds__(NTH) void wgrad_kernel(WgradArgs a) {
             if (x0 + p < a.W) in[j][q] = *(const uint4*)(xr + (int64_t)xx * CI);
           }
         }
-      } else if (it < NB) {
+      } else if (it < NB && hg >= 0) {
         const int j2 = it - NA, c8 = j2 % (CO / 8), g = j2 / (CO / 8);
-        const bf16* gr = a.gz + (((int64_t)img * a.H + h) * a.W + x0) * CO + c8 * 8;
+        const bf16* gr = a.gz + (((int64_t)img * a.H + hg) * a.W + x0) * CO + c8 * 8;
 #pragma unroll
         for (int q = 0; q < 8; ++q)
           if (x0 + g * 8 + q < a.W) in[j][q] = *(const uint4*)(gr + (int64_t)(g * 8 + q) * CO);
       }
     }
   };
-  if (blockIdx.x < nseg) load(blockIdx.x);
-  for (int sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
-    __syncthreads();  // the previous segment's readers of sa and sg are done
-    // transpose: out row (channel) 2w holds the low halves of dword w of the 8
-    // pixels, row 2w + 1 the high halves; dword k of a row packs pixels 2k, 2k + 1
+  // transpose the loaded blocks into ring row `slot` (and sg when with_gz):
+  // out row (channel) 2w holds the low halves of dword w of the 8 pixels,
+  // row 2w + 1 the high halves; dword k of a row packs pixels 2k, 2k + 1
+  auto store = [&](int slot, bool with_gz) {
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
       const int it = tid + j * NTH;
-      if (it >= NB) continue;
+      if (it >= (with_gz ? NB : NA)) continue;
       int row0, g;
       bf16* base;
       if (it < NA) {
-        const int c8 = it % CA, t2 = it / CA, tap = t2 / (SEG / 8);
+        const int c8 = it % CA, t2 = it / CA, dx1 = t2 / (SEG / 8);
         g = t2 % (SEG / 8);
-        row0 = tap * CI + c8 * 8;
-        base = sa;
+        row0 = dx1 * CI + c8 * 8;
+        base = sa + slot * RING;
       } else {
         const int j2 = it - NA;
         g = j2 / (CO / 8);
@@ -404,38 +412,62 @@ __global__ __launch_bounds__(NTH) void wgrad_kernel(WgradArgs a) {
         *(uint4*)&base[(row0 + 2 * w + 1) * PS + g * 8] = uint4{hi[0], hi[1], hi[2], hi[3]};
       }
     }
-    __syncthreads();
-    if (sgi + (int)gridDim.x < nseg) load(sgi + gridDim.x);  // in flight during the matrix work
-    if (tid < CO) {  // the bias gradient: 16-byte reads issued together, then added
-      uint4 v[SEG / 8];
-#pragma unroll
-      for (int c = 0; c < SEG / 8; ++c) v[c] = *(const uint4*)&sg[tid * PS + c * 8];
-      float t = 0.f;
-#pragma unroll
-      for (int c = 0; c < SEG / 8; ++c) {
-        const bf16x8 e = __builtin_bit_cast(bf16x8, v[c]);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) t += bf2f(e[q]);
-      }
-      bsum += t;
+  };
+  auto slot_of = [](int row) { return ((row % 3) + 3) % 3; };
+
+  for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+    const int sx = u % segX, ch = (u / segX) % chunks, img = u / (segX * chunks);
+    const int x0 = sx * SEG, h0 = ch * WG_RC, h1 = min(a.H, h0 + WG_RC);
+    // the ring's first two rows (h0 - 1, h0)
+#pragma unroll 1
+    for (int r = h0 - 1; r <= h0; ++r) {
+      load(img, x0, r, -1);
+      __syncthreads();  // earlier readers of this ring row are done
+      store(slot_of(r), false);
     }
+    load(img, x0, h0 + 1, h0);
+#pragma unroll 1
+    for (int h = h0; h < h1; ++h) {
+      __syncthreads();  // the previous row's readers of the ring row and sg are done
+      store(slot_of(h + 1), true);
+      __syncthreads();
+      if (h + 1 < h1) load(img, x0, h + 2, h + 1);  // in flight during the matrix work
+      if (tid < CO) {  // the bias gradient: 16-byte reads issued together, then added
+        uint4 v[SEG / 8];
 #pragma unroll
-    for (int kc = 0; kc < SEG / 32; ++kc) {
-      const int k = kc * 32 + lg * 8;
-      bf16x8 bfr[NS];
+        for (int c = 0; c < SEG / 8; ++c) v[c] = *(const uint4*)&sg[tid * PS + c * 8];
+        float t = 0.f;
 #pragma unroll
-      for (int ns = 0; ns < NS; ++ns) bfr[ns] = *(const bf16x8*)&sg[(ns * 16 + lm) * PS + k];
+        for (int c = 0; c < SEG / 8; ++c) {
+          const bf16x8 e = __builtin_bit_cast(bf16x8, v[c]);
 #pragma unroll
-      for (int i = 0; i < MPW; ++i) {
-        const int ms = wave + 4 * i;
-        if (ms < MS) {  // uniform per wave
-          const bf16x8 afr = *(const bf16x8*)&sa[(ms * 16 + lm) * PS + k];
+          for (int q = 0; q < 8; ++q) t += bf2f(e[q]);
+        }
+        bsum += t;
+      }
+      int abase[MPW];
 #pragma unroll
-          for (int ns = 0; ns < NS; ++ns)
-            acc[i][ns] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[ns], acc[i][ns], 0, 0, 0);
+      for (int i = 0; i < MPW; ++i) abase[i] = slot_of(h + a_dy[i]) * RING + a_off[i];
+#pragma unroll
+      for (int kc = 0; kc < SEG / 32; ++kc) {
+        const int k = kc * 32 + lg * 8;
+        bf16x8 bfr[NS];
+#pragma unroll
+        for (int ns = 0; ns < NS; ++ns) bfr[ns] = *(const bf16x8*)&sg[(ns * 16 + lm) * PS + k];
+#pragma unroll
+        for (int i = 0; i < MPW; ++i) {
+          const int ms = wave + 4 * i;
+          if (ms < MS) {  // uniform per wave
+            bf16x8 afr = *(const bf16x8*)&sa[abase[i] + k];
+            if (!a_ok[i]) afr = bf16x8{};
+#pragma unroll
+            for (int ns = 0; ns < NS; ++ns)
+              acc[i][ns] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[ns], acc[i][ns], 0, 0, 0);
+          }
         }
       }
     }
+    __syncthreads();  // the last row's readers are done before the next unit's ring rows
   }
   // partial sums of this workgroup: part[block][m][co], then the bias
   // partials part[block][M CO + co]

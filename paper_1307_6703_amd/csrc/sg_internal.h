@@ -12,6 +12,14 @@ typedef __bf16 bf16;
 
 enum Mode { FWD_FIRST = 0, FWD_RES = 1, FWD_OUT = 2, BWD = 3 };
 
+// Output tile of the convolution kernel: TR rows (one per wave) x TW columns.
+constexpr int TW = 64;
+constexpr int TR = 8;
+// Work unit of the weight-gradient kernel: WG_RC rows of a WG_SEG-pixel
+// column segment of one image.
+constexpr int WG_SEG = 64;
+constexpr int WG_RC = 16;
+
 struct ConvArgs {
   const bf16* x;       // [B,H,W,CI]: layer input (forward) or dL/dz of the layer above (BWD)
   const bf16* w;       // packed weights [CO][kpad(CI)]

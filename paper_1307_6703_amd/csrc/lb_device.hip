@@ -666,8 +666,8 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
   const int rds = dir * (ofirst - S1), rde = dir * (olast - S1);
   const int K = rde + 13;  // D2 runs on relative row k - 12
 
-  // LDS: 288 (NT + 2) bytes, so four 128-thread or two 256-thread
-  // workgroups fit on a CU. The force F goes from stage C to stage D of the
+  // LDS: 288 (NT + 2) bytes, so eight 64-thread, four 128-thread or two
+  // 256-thread workgroups fit on a CU. The force F goes from stage C to stage D of the
   // next iteration in registers (Fr); of the first step's post-collision
   // populations only those that move along x (1, 3, 5, 6, 7, 8) go through
   // LDS (O, planes in that order), populations 0, 2 and 4 stay in the

@@ -567,7 +567,8 @@ class SurrogateRun:
 FLOPS_PER_NODE = 2 * 9 * (IN_REAL * WIDTH + BLOCKS * WIDTH * WIDTH + WIDTH * OUT)
 
 
-def _audited_eval(net, test, start, eval_chunks, K, tol, audit_every, log, shape=None):
+def _audited_eval(net, test, start, eval_chunks, K, tol, audit_every, log, shape=None,
+                  scales=None):
     """One evaluation window: the lattice alone from step `start` for
     eval_chunks * K steps, then the same span from the same state with the
     audited network (max and RMS norms) and with the persistence baseline,
@@ -605,7 +606,7 @@ def _audited_eval(net, test, start, eval_chunks, K, tol, audit_every, log, shape
         m0 = np.array([sgb.reduce(i)["mass"] for i in range(n)])
         run = SurrogateRun(net, sgb, test, K=K, tol=-1.0 if key == "lattice_control" else tol,
                            audit_every=gap, norm=norm, predictor=pred, reentry=reentry,
-                           budget=budget)
+                           budget=budget, scales=scales)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         for _ in range(eval_chunks):
@@ -643,7 +644,7 @@ def experiment(H: int = 128, W: int = 256, train_count: int = 256, train_seed: i
                train_windows=((300, 12), (8000, 12)), eval_starts=(300, 10000),
                K: int = 50, iters: int = 10**7, batch: int = 16,
                lr: float = 2e-3, train_seconds: float = 60.0, eval_chunks: int = 20,
-               audit_every: int = 8, tol: float = 1e-2, log=None):
+               audit_every: int = 8, tol: float = 1e-2, scales=None, log=None):
     """Train on lattice data recorded in the windows (start step, chunks),
     then advance `test_count` fresh lattices (other draws) by
     eval_chunks * K steps from each step of eval_starts, several times from
@@ -657,14 +658,15 @@ def experiment(H: int = 128, W: int = 256, train_count: int = 256, train_seed: i
         if log:
             log(" ".join(str(v) for v in a))
 
-    out = {"size": f"{W}x{H}", "K": K}
+    out = {"size": f"{W}x{H}", "K": K,
+           "scales": list(scales if scales is not None else DEFAULT_SCALES)}
     t0 = time.perf_counter()
     raw = ls.surrogate_draws(train_count, seed=train_seed, Lx=W, Ly=H)
     draws = screen(raw, max(s + c * K for s, c in train_windows))
     shape = LATTICE_SHAPE
     xs, ts, spans = [], [], []
     for s, c in train_windows:
-        x, tgt, status = generate_data(draws, s, c, K, shape=shape)
+        x, tgt, status = generate_data(draws, s, c, K, scales=scales, shape=shape)
         assert all(v == 0 for v in status)
         spans.append((sum(v.shape[0] for v in xs), x.shape[0]))
         xs.append(x)
@@ -714,11 +716,12 @@ def experiment(H: int = 128, W: int = 256, train_count: int = 256, train_seed: i
     say(f"lattice launch shape: {shape}")
     fr = None
     for start in eval_starts:
-        win, fr = _audited_eval(net, test, start, eval_chunks, K, tol, audit_every, say, shape)
+        win, fr = _audited_eval(net, test, start, eval_chunks, K, tol, audit_every, say, shape,
+                                scales)
         out["eval"]["windows"].append(win)
     # forward throughput on the whole test batch
     vx, cond = conditions(test)
-    xin = fields_to_input(fr, vx, cond, True)
+    xin = fields_to_input(fr, vx, cond, True, scales)
     yo = torch.empty((test_count, H, W, OUT), dtype=torch.float32, device="cuda")
     for _ in range(3):  # warm-up: the first calls after the lattice runs are slower
         net.forward(xin, yo)

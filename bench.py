@@ -113,18 +113,20 @@ def batched_bench(steps: int, seed: int = 1307, launch=None):
 
     # a draw whose lattice fails a stability check within the run (a deep
     # quench under strong shear can) is replaced by the next draw; the
-    # screening covers the autotuner's steps (about 1600), the warm-up and the
+    # screening covers the autotuner's steps (about 4000), the warm-up and the
     # timed steps
     pool = ls.batch_draws(128, seed=seed)
     scr = batch_of(pool)
-    scr.step(steps + 1800)
+    scr.step(steps + 5000)
     status = scr.status()
     scr.close()
     draws = [w for w, st in zip(pool, status) if st == 0][:96]
     replaced = pool.index(draws[-1]) + 1 - len(draws)
     b = batch_of(draws)
     if launch is None:
-        th, rw, _ = b.autotune(nsteps=40)
+        # 100 timed steps per candidate: every candidate's window holds
+        # exactly one of the checks (every 100 steps), so none is favoured
+        th, rw, _ = b.autotune(nsteps=100)
     else:
         th, rw = launch[0], launch[1]
         b.set_launch(th, rw, steps_per_launch=launch[2] if len(launch) > 2 else 1)

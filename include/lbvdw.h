@@ -244,7 +244,10 @@ lb_status lb_batch_get_steps_per_launch(lb_batch* b, int32_t* steps);
  * and, with FP32 populations, two), pick the fastest and apply it; return
  * it (ms_per_step may be NULL; lb_get_steps_per_launch tells which kernel
  * won). The timed steps are real steps: the lattice advances by nsteps plus
- * one or two warm-up steps per candidate. The launch shape never changes
+ * one or two warm-up steps per candidate. The timed steps include the
+ * periodic checks that fall in them (and the single steps before a check
+ * that splits a pair), so nsteps a multiple of check_every gives every
+ * candidate the same share of them. The launch shape never changes
  * results (every node runs the same arithmetic on the same inputs whatever
  * the tiling). Synchronises. */
 lb_status lb_autotune(lb_handle* h, int32_t nsteps, int32_t* threads, int32_t* rows,

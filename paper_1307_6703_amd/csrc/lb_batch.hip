@@ -142,7 +142,8 @@ lb_status upload_list(lb_batch* b, const int32_t* mask, int32_t* dlist, int* n, 
 
 // Tiles of the instances with mask[i] != 0 (all when mask is NULL), largest
 // instances first: the dispatcher hands out tiles in order, so the
-// long-running ones start early.
+// long-running ones start early. Chunk heights are balanced within each
+// instance, so no short ragged chunk finishes early beside full ones.
 std::vector<Tile> tile_list(const lb_batch* b, int threads, int rows, const int32_t* mask,
                             int halo = 3) {
   std::vector<int> order;
@@ -153,7 +154,7 @@ std::vector<Tile> tile_list(const lb_batch* b, int threads, int rows, const int3
   std::vector<Tile> all;
   for (int i : order) {
     const int r = std::max(std::min(rows, b->inst[i].p.Ly), std::min(8, b->inst[i].p.Ly));
-    std::vector<Tile> t = make_tiles(i, b->inst[i].p.Lx, b->inst[i].p.Ly, threads, r, halo);
+    std::vector<Tile> t = make_tiles(i, b->inst[i].p.Lx, b->inst[i].p.Ly, threads, r, halo, true);
     all.insert(all.end(), t.begin(), t.end());
   }
   return all;

@@ -163,21 +163,32 @@ inline int fused_default_rows(const lb_params* p, int threads, int rounds = 1) {
 }
 
 // Tiles of one lattice: strips of `threads - 2 halo` columns (halo 3 for the
-// one-step kernel, 7 for the two-step kernel), chunks of `rows` rows,
+// one-step kernel, 7 for the two-step kernel), chunks of `rows` rows (the
+// last one ragged) or, with `balanced` and Ly a multiple of 8, as many
+// chunks with heights that are multiples of 8 and differ by at most 8;
 // strip-major so consecutive tiles are vertical neighbours. Odd chunks march
 // downwards (sign bit of inst), so two neighbouring chunks reach their
 // shared boundary rows at the same time and share those loads in L2.
 inline std::vector<Tile> make_tiles(int inst, int Lx, int Ly, int threads, int rows,
-                                    int halo = 3) {
+                                    int halo = 3, bool balanced = false) {
+  std::vector<int> y0s;
+  if (balanced && Ly % 8 == 0 && rows >= 8) {
+    const int n = (Ly + rows - 1) / rows, units = Ly / 8;
+    for (int j = 0, y = 0; j < n; ++j) {
+      y0s.push_back(y);
+      y += 8 * (units / n + (j < units % n ? 1 : 0));
+    }
+  } else {
+    for (int y0 = 0; y0 < Ly; y0 += rows) y0s.push_back(y0);
+  }
+  y0s.push_back(Ly);
   std::vector<Tile> t;
   const int w = threads - 2 * halo;
-  for (int x0 = 0; x0 < Lx; x0 += w) {
-    int j = 0;
-    for (int y0 = 0; y0 < Ly; y0 += rows, ++j) {
+  for (int x0 = 0; x0 < Lx; x0 += w)
+    for (size_t j = 0; j + 1 < y0s.size(); ++j) {
       const int code = (j & 1) ? (int)((unsigned)inst | 0x80000000u) : inst;
-      t.push_back({code, x0, y0, std::min(Ly, y0 + rows)});
+      t.push_back({code, x0, y0s[j], std::min(Ly, y0s[j + 1])});
     }
-  }
   return t;
 }
 

@@ -510,3 +510,25 @@ def test_budget_policy_spaces_the_audits(torch_cuda):
     for bb in (a, b):
         bb.close()
     net.close()
+
+
+def test_experiment_runs_end_to_end(torch_cuda):
+    """The benchmark's surrogate experiment at a toy size: data, training,
+    every evaluation variant, and the lattice-only control matching the
+    reference run."""
+    from paper_1307_6703_amd import surrogate as sg
+    _say("surrogate experiment, toy size")
+    out = sg.experiment(H=32, W=64, train_count=8, test_count=8, train_windows=((20, 2), (60, 2)),
+                        eval_starts=(20,), K=10, iters=40, batch=4, train_seconds=10.0,
+                        eval_chunks=3, audit_every=2)
+    assert out["train"]["iterations"] == 40 and out["train_samples"] > 0
+    win = out["eval"]["windows"][0]
+    for key in ("lattice_control", "audit_max", "audit_rms", "persist_max",
+                "persist_max_eq_reentry", "audit_max_budget", "persist_max_budget"):
+        v = win[key]
+        # FP32 storage; subset steps skip the drift shift: the bar is the
+        # run's mass tolerance (1e-4), with margin
+        assert v["speedup"] > 0 and v["diverged"] == 0 and v["mass_drift_max"] < 1e-6, key
+    assert win["lattice_control"]["fallback_rate"] == 1.0
+    assert win["lattice_control"]["final_frac_within_tol"] == 1.0
+    assert out["forward"]["ms"] > 0

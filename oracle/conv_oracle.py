@@ -60,6 +60,62 @@ def conv3x3_wgrad(x, gy):
     return gw, gy.sum(axis=(0, 1, 2))
 
 
+def _patches(x, idx, r):
+    """Patches of x of radius r around the pixels idx (rows (n, h, w)):
+    [P, 2r + 1, 2r + 1, C], columns wrapped, rows outside the image zero;
+    also the mask [P, 2r + 1] of patch rows inside the image."""
+    B, H, W, C = x.shape
+    n, h, w = idx[:, 0], idx[:, 1], idx[:, 2]
+    off = np.arange(-r, r + 1)
+    rows = h[:, None] + off[None, :]
+    cols = (w[:, None] + off[None, :]) % W
+    inside = (rows >= 0) & (rows < H)
+    rc = np.clip(rows, 0, H - 1)
+    p = x[n[:, None, None], rc[:, :, None], cols[:, None, :]]
+    return p * inside[:, :, None, None], inside
+
+
+def conv3x3_at(x, w, b, idx):
+    """conv3x3(x, w, b) at the pixels idx only ([P, 3] rows (n, h, w)):
+    [P, C_out], from the 3x3 neighbourhood of each pixel."""
+    p, _ = _patches(x, idx, 1)
+    y = np.einsum("pijc,ijcd->pd", p, w)
+    return y + b if b is not None else y
+
+
+def conv3x3_dgrad_at(gy, w, idx):
+    """conv3x3_dgrad(gy, w) at the pixels idx only: [P, C_in]."""
+    p, _ = _patches(gy, idx, 1)
+    # gx[h, x] = sum gy[h - dy, x - dx] w[dy + 1, dx + 1]: the flipped patch
+    return np.einsum("pijd,ijcd->pc", p[:, ::-1, ::-1], w)
+
+
+def forward_at(params, x, idx):
+    """forward(params, x)[0] at the pixels idx only: [P, C_out]. Each pixel's
+    output depends on the input within len(params) pixels; the network runs
+    on that patch, with the rows outside the image held at zero before every
+    layer (the zero padding of each convolution) and the columns wrapped."""
+    L = len(params)
+    h, inside = _patches(x, idx, L)
+    mask = inside[:, :, None, None].astype(h.dtype)  # rows only; broadcast over columns
+    for li, (w, b) in enumerate(params):
+        # a valid 3x3 convolution over the patch: it shrinks by one pixel per side
+        P, S = h.shape[0], h.shape[1]
+        z = np.zeros((P, S - 2, S - 2, w.shape[3]))
+        for dy in range(3):
+            for dx in range(3):
+                z += np.tensordot(h[:, dy:S - 2 + dy, dx:S - 2 + dx], w[dy, dx], axes=([3], [0]))
+        z += b
+        mask = mask[:, 1:-1]
+        if li == 0:
+            h = silu(z) * mask
+        elif li < L - 1:
+            h = (h[:, 1:-1, 1:-1] + silu(z)) * mask
+        else:
+            return z[:, 0, 0]
+    raise ValueError("network needs at least one layer")
+
+
 def silu(z):
     return z / (1.0 + np.exp(-z))
 

@@ -39,7 +39,7 @@ static const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
 typedef struct {
   int32_t Lx, Ly;
   int32_t y_periodic; /* 1: periodic in y; 0: moving walls at rows 0, Ly-1 */
-  int32_t pad;
+  int32_t collision;  /* 0: BGK, Eq.(evoleq); 1: regularised (lbo_regularize) */
   double T;     /* reduced temperature */
   double tau;   /* relaxation time, paper units */
   double kappa; /* surface-tension parameter, paper units */
@@ -81,6 +81,36 @@ void lbo_forcing(double ux, double uy, double Fx, double Fy, double dnx,
     double XQ = Xxx * (3.0 * cx * cx - 1.0) + Xyy * (3.0 * cy * cy - 1.0) +
                 Xxy * (3.0 * cx * cy) + Xyx * (3.0 * cy * cx);
     out[i] = W[i] * s * (3.0 * cF + 0.5 * XQ);
+  }
+}
+
+/* Regularisation (Sec. II: the step that re-projects the post-collision
+ * populations onto the Hermite space, which the paper names and leaves out
+ * at its Knudsen numbers). The equilibrium of Eq.(eqfunc) and the forcing of
+ * Eq.(forceterm) are expansions in the Hermite polynomials of order <= 2,
+ * H0 = 1, H1 = c, H2 = c c - I/3 (lattice units, c_s^2 = 1/3); the
+ * projection keeps the part of a population vector in that space:
+ *   a0 = sum_i h_i,  a1 = sum_i h_i c_i,  a2 = sum_i h_i (c_i c_i - I/3),
+ *   P[h]_i = w_i [a0 + 3 a1.c_i + (9/2) a2 : (c_i c_i - I/3)].
+ * The D2Q9 weights integrate products of these polynomials exactly, so P
+ * keeps the moments of order 0, 1, 2 and removes the rest (the terms of
+ * order 3 and 4 that D2Q9 can also carry). */
+void lbo_regularize(const double h[9], double out[9]) {
+  double a0 = 0.0, a1x = 0.0, a1y = 0.0, pxx = 0.0, pyy = 0.0, pxy = 0.0;
+  for (int i = 0; i < 9; i++) {
+    a0 += h[i];
+    a1x += h[i] * CX[i];
+    a1y += h[i] * CY[i];
+    pxx += h[i] * CX[i] * CX[i];
+    pyy += h[i] * CY[i] * CY[i];
+    pxy += h[i] * CX[i] * CY[i];
+  }
+  double a2xx = pxx - a0 / 3.0, a2yy = pyy - a0 / 3.0, a2xy = pxy;
+  for (int i = 0; i < 9; i++) {
+    double hxx = CX[i] * CX[i] - 1.0 / 3.0, hyy = CY[i] * CY[i] - 1.0 / 3.0;
+    double hxy = (double)(CX[i] * CY[i]);
+    out[i] = W[i] * (a0 + 3.0 * (a1x * CX[i] + a1y * CY[i]) +
+                     4.5 * (a2xx * hxx + a2yy * hyy + 2.0 * a2xy * hxy));
   }
 }
 
@@ -188,7 +218,7 @@ void lbo_init(const lbo_params *p, const double *n0, const double *ux0,
 int lbo_step(const lbo_params *p, const double *fext, const double *S_in,
              double *S_out, double *n_out, double *ux_out, double *uy_out) {
   const int Lx = p->Lx, Ly = p->Ly;
-  if (Lx < 1 || Ly < 4) return -1;
+  if (Lx < 1 || Ly < 4 || p->collision < 0 || p->collision > 1) return -1;
   const size_t nn = (size_t)Lx * Ly;
   const double tau_l = sqrt(3.0) * p->tau;
   const double omega = 1.0 / tau_l;
@@ -314,7 +344,10 @@ int lbo_step(const lbo_params *p, const double *fext, const double *S_in,
 
   /* 9-12. Per node: grad n and D = div(n u*) with the same stencil (ghosts:
    *       n and jx even, jy odd), equilibrium, forcing, BGK collision
-   *       (Eq.(evoleq)) on all nodes including the walls. */
+   *       (Eq.(evoleq)) on all nodes including the walls; with collision = 1
+   *       the non-equilibrium part f - f_eq is replaced by its projection
+   *       (lbo_regularize) before it relaxes:
+   *       S = f_eq + (1 - omega) P[f - f_eq] + dt F. */
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < Ly; y++)
     for (int x = 0; x < Lx; x++) {
@@ -326,8 +359,16 @@ int lbo_step(const lbo_params *p, const double *fext, const double *S_in,
       double fe[9], fo[9];
       lbo_feq(nk, ux, uy, T, fe);
       lbo_forcing(ux, uy, Fx[k], Fy[k], dnx, dny, D, T, tau_l, fo);
-      for (int i = 0; i < 9; i++)
-        S_out[i * nn + k] = Fv(i) - omega * (Fv(i) - fe[i]) + fo[i];
+      if (p->collision == 1) {
+        double neq[9], pr[9];
+        for (int i = 0; i < 9; i++) neq[i] = Fv(i) - fe[i];
+        lbo_regularize(neq, pr);
+        for (int i = 0; i < 9; i++)
+          S_out[i * nn + k] = fe[i] + (1.0 - omega) * pr[i] + fo[i];
+      } else {
+        for (int i = 0; i < 9; i++)
+          S_out[i * nn + k] = Fv(i) - omega * (Fv(i) - fe[i]) + fo[i];
+      }
       if (n_out) n_out[k] = nk;
       if (ux_out) ux_out[k] = ux;
       if (uy_out) uy_out[k] = uy;

@@ -31,7 +31,7 @@ W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
 
 class _Params(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32),
-                ("y_periodic", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("y_periodic", ctypes.c_int32), ("collision", ctypes.c_int32),
                 ("T", ctypes.c_double), ("tau", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("N", ctypes.c_double),
                 ("Q", ctypes.c_double), ("U", ctypes.c_double)]
@@ -48,6 +48,7 @@ def _lib():
         pp = ctypes.POINTER(_Params)
         lib.lbo_feq.argtypes = [ctypes.c_double] * 4 + [dp]
         lib.lbo_forcing.argtypes = [ctypes.c_double] * 9 + [dp]
+        lib.lbo_regularize.argtypes = [dp, dp]
         lib.lbo_pressure_term.argtypes = [ctypes.c_double, ctypes.c_double]
         lib.lbo_pressure_term.restype = ctypes.c_double
         lib.lbo_apply_stencils.argtypes = [pp, dp, ctypes.c_double, dp, dp, dp]
@@ -80,10 +81,11 @@ class Params:
     Q: float = 2.0
     U: float = 0.0
     y_periodic: bool = False
+    regularized: bool = False  # collision of the non-equilibrium part's projection
 
     def c(self) -> _Params:
-        return _Params(self.Lx, self.Ly, int(self.y_periodic), 0, self.T, self.tau,
-                       self.kappa, self.N, self.Q, self.U)
+        return _Params(self.Lx, self.Ly, int(self.y_periodic), int(bool(self.regularized)),
+                       self.T, self.tau, self.kappa, self.N, self.Q, self.U)
 
     @property
     def tau_l(self) -> float:
@@ -93,6 +95,15 @@ class Params:
 def feq(n, ux, uy, T):
     out = np.zeros(9)
     _lib().lbo_feq(n, ux, uy, T, _ptr(out))
+    return out
+
+
+def regularize(h):
+    """Projection of a population vector onto the Hermite polynomials of
+    order <= 2 (lbo_regularize)."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    out = np.zeros(9)
+    _lib().lbo_regularize(_ptr(h), _ptr(out))
     return out
 
 

@@ -110,3 +110,40 @@ def test_first_adam_step_moves_by_lr_times_sign():
     g = np.array([0.3, -2.0, 1e-3])
     p, m, v = co.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01)
     assert np.allclose(p, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def _idx(g, B, H, W, P):
+    return np.stack([g.integers(0, B, P), g.integers(0, H, P), g.integers(0, W, P)], axis=1)
+
+
+def test_pointwise_conv_matches_brute_force():
+    # the pointwise forms used for full-size checks, against the loops above
+    g = _rng(31)
+    x = g.normal(size=(2, 5, 6, 3))
+    w = g.normal(size=(3, 3, 3, 4))
+    b = g.normal(size=4)
+    full = _brute_conv(x, w, b)
+    idx = np.array([[n, h, c] for n in range(2) for h in range(5) for c in range(6)])
+    assert np.allclose(co.conv3x3_at(x, w, b, idx), full[idx[:, 0], idx[:, 1], idx[:, 2]],
+                       atol=1e-12)
+    # the input gradient of a conv is the conv with flipped, transposed taps
+    wt = np.transpose(w[::-1, ::-1], (0, 1, 3, 2))
+    gy = g.normal(size=(2, 5, 6, 4))
+    full_dg = _brute_conv(gy, wt, np.zeros(3))
+    assert np.allclose(co.conv3x3_dgrad_at(gy, w, idx), full_dg[idx[:, 0], idx[:, 1], idx[:, 2]],
+                       atol=1e-12)
+
+
+def test_pointwise_forward_matches_whole_image():
+    # every pixel, including the wall rows and wrapped columns, of a network
+    # deeper than the image is tall
+    g = _rng(32)
+    params = [(g.normal(0, 0.3, size=(3, 3, 4, 5)), g.normal(0, 0.1, size=5)),
+              (g.normal(0, 0.3, size=(3, 3, 5, 5)), g.normal(0, 0.1, size=5)),
+              (g.normal(0, 0.3, size=(3, 3, 5, 5)), g.normal(0, 0.1, size=5)),
+              (g.normal(0, 0.3, size=(3, 3, 5, 2)), g.normal(0, 0.1, size=2))]
+    x = g.normal(size=(2, 3, 7, 4))
+    out, _ = co.forward(params, x)
+    idx = np.array([[n, h, c] for n in range(2) for h in range(3) for c in range(7)])
+    got = co.forward_at(params, x, idx)
+    assert np.allclose(got, out[idx[:, 0], idx[:, 1], idx[:, 2]], atol=1e-12)

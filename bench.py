@@ -8,12 +8,19 @@ drift correction every 100 steps. One step = one full time step of the lattice
 (stream, density, stencils, force, walls, collision, store) plus its share of
 the checks.
 
+Order of the measurements: the step kernel alone (checks off) for the
+roofline, then, queued behind it on the same lattice with no idle gap, the
+--warmup and --steps of the headline with the checks; then the cost of a
+check, the other precisions on the same lattice, the batched sweep, the
+learned surrogate and the CPU oracle.
+
 The default launch runs two steps per launch (the two-step kernel keeps the
 first step's populations on chip). The roofline counts 72 algorithmic bytes
 per node update (nine populations read and written in FP32), times the
 updates of one launch, over the launch's duration; with two steps per launch
 the populations cross HBM once per two updates, so that figure is an
-effective rate and hbm_gbs_min the rate of the bytes that must cross HBM.
+effective rate, hbm_gbs_min the rate of the bytes that must cross HBM and
+hbm_gbs_measured that of the bytes the HBM counters saw.
 
 Prints one JSON line: MLUPS (million lattice-node updates per second), the
 roofline of the step kernel against the HBM peak, and the FP64 CPU oracle
@@ -37,13 +44,14 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1307_6703_amd", "csrc", "lb_device.hip
 TUNED = os.path.join(ROOT, "paper_1307_6703_amd", "tuned_launch.json")
 
 
-# The step kernels and their helpers come first in KERNEL_SOURCE; the
-# initial-state, check and conversion kernels follow this line.
-KERNEL_SECTION_END = "// ---- initial state"
+# The two-step kernel and everything it compiles from come first in
+# KERNEL_SOURCE; the one-step kernel, the initial-state, check and conversion
+# kernels follow this line.
+KERNEL_SECTION_END = "// ---- one-step kernel"
 
 
 def kernel_hash() -> str:
-    """SHA-256 prefix of the step kernels' source (KERNEL_SOURCE up to
+    """SHA-256 prefix of the two-step kernel's source (KERNEL_SOURCE up to
     KERNEL_SECTION_END) with comments and blank space removed, so that
     counters stay attached to the code they measured."""
     import re
@@ -78,21 +86,29 @@ def measured_traffic(nodes: int, steps_per_launch: int):
 
 def cpu_baseline(w, n0, fext, seconds: float):
     """The FP64 oracle as it stands, on the full lattice, for as many whole
-    steps as fit in about `seconds` (at least one)."""
+    steps as fit in about `seconds` (at least one): on all host threads, then
+    on one thread for about a third of that."""
     from oracle.lb_oracle import OracleLB, Params
-    o = OracleLB(Params(w.Lx, w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, U=w.U,
-                        y_periodic=w.y_periodic), n0, fext=fext)
-    t0 = time.perf_counter()
-    used = o.run(1)
-    t1 = time.perf_counter()
-    steps = max(0, int(seconds / max(t1 - t0, 1e-9)) - 1)
-    if steps:
-        o.run(steps)
-    dt = time.perf_counter() - t0
-    total = steps + 1
-    return {"value": round(w.nodes * total / dt / 1e6, 3), "unit": "MLUPS", "cores": used,
-            "kind": "oracle",
-            "sample": f"{total} FP64 steps of the full {w.Lx}x{w.Ly} lattice ({dt:.1f} s)"}
+
+    def timed(threads, budget):
+        o = OracleLB(Params(w.Lx, w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, U=w.U,
+                            y_periodic=w.y_periodic), n0, fext=fext)
+        t0 = time.perf_counter()
+        used = o.run(1, threads=threads)
+        t1 = time.perf_counter()
+        steps = max(0, int(budget / max(t1 - t0, 1e-9)) - 1)
+        if steps:
+            o.run(steps, threads=threads)
+        dt = time.perf_counter() - t0
+        return round(w.nodes * (steps + 1) / dt / 1e6, 3), used, steps + 1, dt
+
+    v, used, n, dt = timed(0, seconds)
+    v1, _, n1, dt1 = timed(1, seconds / 3)
+    return {"value": v, "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "sample": f"{n} FP64 steps of the full {w.Lx}x{w.Ly} lattice ({dt:.1f} s)",
+            "single_thread": {"value": v1, "unit": "MLUPS", "cores": 1,
+                              "sample": f"{n1} FP64 steps of the full lattice on one thread "
+                                        f"({dt1:.1f} s)"}}
 
 
 def batched_bench(steps: int, seed: int = 1307, launch=None):
@@ -151,6 +167,44 @@ def batched_bench(steps: int, seed: int = 1307, launch=None):
     return out
 
 
+def mode_bench(w, n0_dev, fext, prec: int, steps: int, check_every: int):
+    """Throughput of another precision on the headline lattice in its default
+    launch: `steps` timed steps with the FP64 checks, after 20 warm-up steps;
+    the step kernel's roofline at 72 (FP32 storage) or 144 (FP64) algorithmic
+    bytes per node update."""
+    import torch
+    from paper_1307_6703_amd import Lattice
+    lat = Lattice(w.Lx, w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, U=w.U, fext=fext,
+                  y_periodic=w.y_periodic, fp32=prec, check_every=check_every, drift_correct=prec != 0)
+    lat.init(n0_dev)
+    threads, rows, blocks = lat.get_launch()
+    lat.step(20)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    lat.step(steps)
+    ev[1].record()
+    lat.set_checks(0, False)
+    ev[2].record()
+    lat.step(steps)
+    ev[3].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    k_ms = ev[2].elapsed_time(ev[3]) / steps
+    bpu = BYTES_PER_UPDATE_FP64 if prec == 0 else BYTES_PER_UPDATE_FP32
+    red = lat.reduce()
+    lat.close()
+    achieved = bpu * w.nodes / (k_ms * 1e-3) / 1e9
+    return {"MLUPS": round(w.nodes / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 5),
+            "steps": steps,
+            "launch": {"threads": threads, "rows": rows, "workgroups": blocks, "steps_per_launch": 1},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "kernel": ("step_kernel<float, double, %d>" if prec == 2 else
+                                    "step_kernel<double, double, %d>") % threads,
+                         "us_per_launch": round(k_ms * 1e3, 2), "bytes_per_update": bpu},
+            "nmin": red["nmin"], "nmax": red["nmax"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +216,12 @@ def main():
                          "two-step kernel)")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape first")
     ap.add_argument("--check-every", type=int, default=100)
+    ap.add_argument("--roofline-steps", type=int, default=2000,
+                    help="steps of the step kernel alone (checks off) timed for the roofline, "
+                         "before the headline's warm-up and timed steps")
+    ap.add_argument("--mode-steps", type=int, default=400,
+                    help="timed steps of the FP32-storage FP64-arithmetic mode and of FP64 on the "
+                         "headline lattice (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--batched-steps", type=int, default=20000,
@@ -207,10 +267,11 @@ def main():
     torch.cuda.set_device(0)
     w = ls.ROOFLINE
     n0, fext = w.n0(), w.fext()
+    n0_dev = torch.from_numpy(n0).cuda()
     lat = Lattice(w.Lx, w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, U=w.U, fext=fext,
                   y_periodic=w.y_periodic, fp32=True, check_every=args.check_every,
                   drift_correct=True)
-    lat.init(n0)
+    lat.init(n0_dev)
     key = f"{w.Lx}x{w.Ly}-fp32-gfx950"
     if args.launch:
         lat.set_launch(*(int(v) for v in args.launch.split(",")))
@@ -224,38 +285,70 @@ def main():
           f"{blocks} workgroups, {spl} step(s) per launch", file=sys.stderr, flush=True)
 
     m0 = lat.reduce()["mass"]
+    # 1. the step kernel alone (checks off), for the roofline: a whole number of
+    # launches after 200 warm-up launches.
+    lat.set_checks(0, False)
+    lat.step(200 * spl)
+    k_steps = max(spl, args.roofline_steps // spl * spl)
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e2.record()
+    lat.step(k_steps)
+    e3.record()
+
+    # 2. the headline: the same lattice, W warm-up steps, then exactly K timed
+    # steps with the FP64 checks and drift correction. They are queued behind
+    # the roofline's steps with no host synchronisation in between: a device
+    # that has idled for tens of milliseconds runs its next few launches at
+    # lower clocks (a 20-step window after a 50 ms idle measured 4.4 ms
+    # against 3.6 ms queued behind work), which a window of a few launches
+    # would measure instead of the step.
+    lat.set_checks(args.check_every, True)
+    base = lat.step_count
     lat.step(args.warmup)
-    torch.cuda.synchronize()
-    # whole-job timing: steps plus their checks, on the lattice's stream
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record()
     lat.step(args.steps)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    mlups = w.nodes * args.steps / (ms * 1e-3) / 1e6
-    print(f"[bench] timed {args.steps} steps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms)",
-          file=sys.stderr, flush=True)
-    red = lat.reduce()
-
-    # the step kernel alone (checks off), same stream, for the roofline
-    lat.set_checks(0, False)
-    k_steps = max(50, args.steps // 2) // spl * spl
-    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e2.record()
-    lat.step(k_steps)
-    e3.record()
-    torch.cuda.synchronize()
     k_ms = e2.elapsed_time(e3) / (k_steps // spl)  # per launch
     # algorithmic bytes: 72 B per node update, times the updates of a launch
     alg_bytes = BYTES_PER_UPDATE_FP32 * w.nodes * spl
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     print(f"[bench] step kernel {k_ms * 1e3:.1f} us/launch ({spl} step(s)), {achieved:.0f} GB/s "
           f"algorithmic", file=sys.stderr, flush=True)
+    ms = e0.elapsed_time(e1)
+    mlups = w.nodes * args.steps / (ms * 1e-3) / 1e6
+    ce = args.check_every
+    s0 = base + args.warmup
+    checks_in = 0 if ce <= 0 else (s0 + args.steps) // ce - s0 // ce
+    print(f"[bench] timed {args.steps} steps (steps {s0 + 1} to {s0 + args.steps} of the run): "
+          f"{ms:.1f} ms (wall {wall * 1e3:.1f} ms), {checks_in} check(s) among them",
+          file=sys.stderr, flush=True)
+    red = lat.reduce()
+
+    # 3. what a check costs: 10 check intervals with and without the checks
+    # (a check adds its FP64 reduction and makes the step before it a single
+    # step); the headline's window holds checks_in of them
+    chk = None
+    if ce > 0:
+        span = 10 * ce
+        lat.step((-lat.step_count) % ce)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        lat.step(span)
+        ev[1].record()
+        lat.set_checks(0, False)
+        ev[2].record()
+        lat.step(span)
+        ev[3].record()
+        torch.cuda.synchronize()
+        per = (ev[0].elapsed_time(ev[1]) - ev[2].elapsed_time(ev[3])) / 10
+        due = args.steps / ce
+        chk = {"every": ce, "in_timed_steps": checks_in, "ms_per_check": round(per, 4),
+               "MLUPS_checks_amortised": round(
+                   w.nodes * args.steps / ((ms + (due - checks_in) * per) * 1e-3) / 1e6, 1)}
 
     # the same bytes moved by a plain device copy: the streaming rate this
     # GPU reaches in practice (read + write), for context beside the peak
@@ -271,6 +364,7 @@ def main():
     copy_gbs = 2 * src.numel() * 4 / (e4.elapsed_time(e5) / 10 * 1e-3) / 1e9
     del src, dst
 
+    traffic = measured_traffic(w.nodes, spl)
     out = {
         "metric": "MLUPS",
         "value": round(mlups, 1),
@@ -284,30 +378,39 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
+        "timed_steps_of_run": [s0 + 1, s0 + args.steps],
         "config": {"workload": w.name, "Lx": w.Lx, "Ly": w.Ly, "walls": not w.y_periodic,
                    "T": w.T, "tau": w.tau, "kappa": w.kappa, "N": w.N, "Q": w.Q, "U": w.U,
                    "V0": w.V0, "stripes": w.k, "seed": w.seed, "storage": "fp32-deviation",
+                   "arithmetic": "fp32",
                    "checks": f"fp64 every {args.check_every} steps + drift correction",
                    "launch": {"threads": threads, "rows": rows, "workgroups": blocks,
                               "steps_per_launch": spl}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(w.nodes, spl),
-                     "kernel": ("step2_kernel<%d>" if spl == 2 else "step_kernel<float,%d>") % threads,
+                     "traffic": traffic,
+                     "kernel": ("step2_kernel<%d>" if spl == 2 else "step_kernel<float, float, %d>") % threads,
                      "us_per_launch": round(k_ms * 1e3, 2),
+                     "launches_timed": k_steps // spl,
                      "node_updates_per_launch": w.nodes * spl,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      # the bytes a launch must move through HBM: each population
                      # is read and written once per launch, whatever its steps
                      "hbm_bytes_per_launch_min": BYTES_PER_UPDATE_FP32 * w.nodes,
                      "hbm_gbs_min": round(BYTES_PER_UPDATE_FP32 * w.nodes / (k_ms * 1e-3) / 1e9, 1),
-                     "note": ("two steps per launch: achieved counts 72 B per node update as the "
-                              "one-step roofline does (an effective rate); the populations cross "
-                              "HBM once per launch (hbm_gbs_min, traffic), and the kernel is bound "
-                              "by instruction issue at two waves per SIMD" if spl == 2 else
+                     "hbm_gbs_measured": (round(traffic / (k_ms * 1e-3) / 1e9, 1)
+                                          if traffic else None),
+                     "hbm_frac_measured": (round(traffic / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                           if traffic else None),
+                     "note": ("two steps per launch: achieved counts 72 B per node update, times "
+                              "the launch's two updates per node (the scope's algorithmic bytes), "
+                              "an effective rate; the populations cross HBM once per launch "
+                              "(hbm_gbs_min, hbm_gbs_measured), and the kernel is bound by "
+                              "instruction issue at two waves per SIMD" if spl == 2 else
                               "one step per launch: HBM-bound streaming of the populations"),
                      "copy_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
+        "checks": chk,
         "hbm_frac_of_peak": round(mlups * 1e6 * BYTES_PER_UPDATE_FP32 / 1e9 / HBM_PEAK_GBS, 4),
         "mass_drift": abs(red["mass"] - m0) / m0,
         "gpu": torch.cuda.get_device_name(0),
@@ -316,6 +419,13 @@ def main():
     lat.close()
     del lat
     torch.cuda.empty_cache()
+    if args.mode_steps > 0:
+        out["modes"] = {}
+        for name, prec in (("fp32_storage_fp64_arithmetic_sr", 2), ("fp64", 0)):
+            out["modes"][name] = mode_bench(w, n0_dev, fext, prec, args.mode_steps, args.check_every)
+            print(f"[bench] {name}: {out['modes'][name]['MLUPS']} MLUPS, step kernel "
+                  f"{out['modes'][name]['roofline']['us_per_launch']} us", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
     if args.batched_steps > 0:
         bl = tuple(int(v) for v in args.batched_launch.split(",")) if args.batched_launch else None
         out["batched"] = batched_bench(args.batched_steps, launch=bl)

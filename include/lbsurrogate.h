@@ -120,11 +120,16 @@ lb_status lbs_pack(const float* d_w, int32_t cir, int32_t cor, int32_t CI, int32
  *   3 backward:    g = conv + res (res may be NULL); z = g (may be NULL),
  *                  y = g SiLU'(zprev)   (x holds dL/dz of the layer above and
  *                  the weights are packed transposed)
- * bias: FP32 [co] (first / residual) or [nout] (output), may be NULL. */
+ * bias: FP32 [co] (first / residual) or [nout] (output), may be NULL.
+ * The kernel is persistent: each workgroup walks 8-row x 64-column tiles
+ * (stride: the grid). blocks caps the grid (0: one workgroup per tile, at
+ * most as many as fit on the device at once; 1 <= blocks <= 4096 forces a
+ * smaller grid, so that every workgroup walks several tiles). Results do not
+ * depend on the grid. */
 lb_status lbs_conv(int32_t mode, int32_t ci, int32_t co, const void* d_x, const void* d_wpack,
                    const float* d_bias, const void* d_res, const void* d_zprev, void* d_y,
                    void* d_z, float* d_yf, int32_t nout, int32_t B, int32_t H, int32_t W,
-                   void* hip_stream);
+                   int32_t blocks, void* hip_stream);
 
 /* Weight and bias gradients: dw[tap][ci][co] (ci < cir, co < cor; FP32) =
  * scale * sum over pixels p of x[p + offset(tap)][ci] gz[p][co], with the

@@ -28,8 +28,17 @@
  *
  * Precision: fp32 = 0 stores and computes populations in FP64. fp32 = 1 stores
  * g_i = f_i - w^_i nbar in FP32 (w^_i the rest-state weights at T, nbar the
- * mean density) and computes the step in FP32; mass and momentum checks are
- * always FP64.
+ * mean density) and computes the step in FP32. fp32 = 2 stores the same FP32
+ * deviations but computes the step in FP64 and rounds each stored value
+ * stochastically: to one of the two neighbouring floats, with the
+ * probabilities that make the expected stored value the exact one. The
+ * draws come from a counter-based hash of (column, row, step), so runs are
+ * deterministic and do not depend on the launch shape. Rounding to nearest
+ * repeats the same error at every node of a uniform phase and the lattice
+ * integrates that bias; with unbiased rounding FP32 storage stays within 1e-4
+ * of FP64 over long runs. Mass and momentum checks are always FP64. The
+ * paper fixes no precision (Sec. III gives no arithmetic); these modes are
+ * the library's.
  *
  * Ownership: the caller owns all device memory. It passes one device
  * workspace of at least lb_workspace_bytes() bytes (e.g. a torch uint8 tensor)
@@ -75,7 +84,9 @@ typedef struct {
   int32_t Lx, Ly;         /* nodes; Lx >= 1, Ly >= 4; 9*Lx*Ly*(4 or 8 bytes)
                              < 2 GiB (FP32 < 59.6M nodes, FP64 < 29.8M)       */
   int32_t y_periodic;     /* 1: periodic in y; 0: moving walls at rows 0, Ly-1 */
-  int32_t fp32;           /* 0: FP64 populations; 1: FP32 deviations          */
+  int32_t fp32;           /* 0: FP64 populations; 1: FP32 deviations, FP32
+                             arithmetic; 2: FP32 deviations, FP64 arithmetic,
+                             stochastic rounding of the stored values         */
   double T;               /* reduced temperature, 0 < T <= 1.5                */
   double tau;             /* relaxation time, paper units; sqrt(3) tau > 1/2 */
   double kappa;           /* square-gradient coefficient, paper units, >= 0  */
@@ -86,7 +97,13 @@ typedef struct {
                              at create.                                       */
   int32_t check_every;    /* run the FP64 check every this many steps; 0 = never */
   int32_t drift_correct;  /* 1: after each check, add the uniform shift that
-                             restores the initial mass (FP32 mode)           */
+                             restores the initial mass (FP32 storage)        */
+  int32_t collision;      /* 0: BGK of Eq.(evoleq); 1: regularised: the
+                             non-equilibrium part f - f_eq is replaced by its
+                             projection onto the Hermite polynomials of order
+                             <= 2 (the space of Eq.(eqfunc) and
+                             Eq.(forceterm)) before it relaxes, the step Sec. II
+                             names for tau != 1; one step per launch only    */
 } lb_params;
 
 typedef struct lb_handle lb_handle;
@@ -136,8 +153,9 @@ lb_status lb_reduce(lb_handle* h, double out[6]);
 lb_status lb_get_populations(lb_handle* h, double* f);
 
 /* Replace the state by host FP64 populations [9][Ly][Lx] and set the step
- * counter (checkpoint restore). Resets the stability flag and the reference
- * mass to the mass of f. */
+ * counter (checkpoint restore; with fp32 = 2 the stochastic rounding
+ * continues with the draws of that step). Resets the stability flag and the
+ * reference mass to the mass of f. */
 lb_status lb_set_populations(lb_handle* h, const double* f, int64_t step);
 
 /* Change the check cadence and drift correction of lb_params (applies to
@@ -214,7 +232,7 @@ lb_status lb_batch_step_subset(lb_batch* b, int64_t nsteps, const int32_t* mask)
 
 /* ---- launch shape ----------------------------------------------------------
  * The step kernel marches strips of columns along y. threads: columns a
- * workgroup loads (64, 128, 256, 320, or 512 with FP32 populations; it
+ * workgroup loads (64, 128, 256, 320, or 512 with fp32 = 1; it
  * updates threads - 6 of them); rows:
  * rows per y-chunk (>= 1). 0 keeps the default. Applies to the next step.
  * lb_create picks two steps per launch (below) for FP32 lattices of at least
@@ -223,7 +241,7 @@ lb_status lb_set_launch(lb_handle* h, int32_t threads, int32_t rows);
 lb_status lb_get_launch(lb_handle* h, int32_t* threads, int32_t* rows, int32_t* blocks);
 lb_status lb_batch_set_launch(lb_batch* b, int32_t threads, int32_t rows);
 
-/* Two time steps per launch (FP32 populations only; LB_EINVAL otherwise).
+/* Two time steps per launch (fp32 = 1 only; LB_EINVAL otherwise).
  * A workgroup of threads (64, 128, 192 or 256; 0: 128) runs the step of
  * Eq.(evoleq) twice over a strip of threads - 14 columns and a y-chunk of
  * rows (0: a default height), keeping the first step's populations in LDS,
@@ -241,7 +259,7 @@ lb_status lb_batch_set_launch_fused(lb_batch* b, int32_t threads, int32_t rows);
 lb_status lb_batch_get_steps_per_launch(lb_batch* b, int32_t* steps);
 
 /* Time nsteps steps of each candidate launch shape (one step per launch
- * and, with FP32 populations, two), pick the fastest and apply it; return
+ * and, with fp32 = 1, two), pick the fastest and apply it; return
  * it (ms_per_step may be NULL; lb_get_steps_per_launch tells which kernel
  * won). The timed steps are real steps: the lattice advances by nsteps plus
  * one or two warm-up steps per candidate. The timed steps include the
@@ -253,7 +271,7 @@ lb_status lb_batch_get_steps_per_launch(lb_batch* b, int32_t* steps);
 lb_status lb_autotune(lb_handle* h, int32_t nsteps, int32_t* threads, int32_t* rows,
                       double* ms_per_step);
 
-/* lb_autotune for a batch: candidate shapes (one and, with FP32, two steps
+/* lb_autotune for a batch: candidate shapes (one and, with fp32 = 1, two steps
  * per launch) are shared by all instances. */
 lb_status lb_batch_autotune(lb_batch* b, int32_t nsteps, int32_t* threads, int32_t* rows,
                             double* ms_per_step);

@@ -41,7 +41,8 @@ struct lb_handle {
 
 namespace {
 
-bool fp32_of(const lb_handle* h) { return h->p.fp32 != 0; }
+bool fp32_of(const lb_handle* h) { return h->p.fp32 != 0; }  // FP32 storage
+int prec(const lb_handle* h) { return prec_of(&h->p); }
 int64_t nodes(const lb_handle* h) { return (int64_t)h->p.Lx * h->p.Ly; }
 
 lb_status upload_desc(lb_handle* h) {
@@ -62,12 +63,14 @@ lb_status upload_tiles(lb_handle* h, Tile* dst, int threads, int rows, int fuse,
 
 lb_status set_tiles(lb_handle* h, int threads, int rows, int fuse = 1) {
   if (fuse == 2) {
-    if (!h->p.fp32) return fail(LB_EINVAL, "two steps per launch need FP32 storage");
+    if (prec(h) != lbk::kFP32)
+      return fail(LB_EINVAL, "two steps per launch need FP32 storage and arithmetic (fp32 = 1)");
+    if (h->p.collision != 0) return fail(LB_EINVAL, "two steps per launch need the BGK collision");
     if (!fused_threads_ok(threads))
       return fail(LB_EINVAL, "two steps per launch: threads must be 64, 128, 192 or 256 (got %d)", threads);
   } else if (threads != 64 && threads != 128 && threads != 256 && threads != 320 &&
-             !(threads == 512 && h->p.fp32)) {
-    return fail(LB_EINVAL, "threads must be 64, 128, 256, 320 or 512 (FP32 only) (got %d)", threads);
+             !(threads == 512 && prec(h) == lbk::kFP32)) {
+    return fail(LB_EINVAL, "threads must be 64, 128, 256, 320 or 512 (fp32 = 1 only) (got %d)", threads);
   }
   if (rows < 1) return fail(LB_EINVAL, "rows must be >= 1");
   rows = std::max(std::min(rows, h->p.Ly), std::min(kMinRows, h->p.Ly));
@@ -131,10 +134,10 @@ lb_status step_impl(lb_handle* h, int64_t nsteps, bool moments_last) {
     if (pair)
       HIPCHK(lbk::launch_step2(h->threads, h->ddesc, h->dtiles, h->ntiles, h->parity, flags, h->st));
     else if (h->fuse == 2)
-      HIPCHK(lbk::launch_step(fp32_of(h), h->threads1, h->ddesc, h->dtiles1, h->ntiles1, h->parity,
+      HIPCHK(lbk::launch_step(prec(h), h->p.collision != 0, h->threads1, h->ddesc, h->dtiles1, h->ntiles1, h->parity,
                               flags, h->st));
     else
-      HIPCHK(lbk::launch_step(fp32_of(h), h->threads, h->ddesc, h->dtiles, h->ntiles, h->parity,
+      HIPCHK(lbk::launch_step(prec(h), h->p.collision != 0, h->threads, h->ddesc, h->dtiles, h->ntiles, h->parity,
                               flags, h->st));
     h->pending_shift = false;
     h->parity ^= 1;
@@ -197,9 +200,11 @@ lb_status lb_create(const lb_params* p, void* dev_ws, size_t ws_bytes, void* hip
   d.fext3 = h->ws + L.fext;
   d.mom = h->dmom;
   d.shift = &h->dred->shift;
+  d.rng = h->dred->rng_step;
   d.Lx = p->Lx;
   d.Ly = p->Ly;
   d.periodic = p->y_periodic;
+  d.reg = p->collision;
   d.nbar = 0.0;
   d.T = p->T;
   d.omega = 1.0 / tau_l;
@@ -214,7 +219,7 @@ lb_status lb_create(const lb_params* p, void* dev_ws, size_t ws_bytes, void* hip
   if (p->fext_x) std::copy(p->fext_x, p->fext_x + p->Lx, h->fext.begin());
   lb_status r = LB_OK;
   auto cleanup = [&](lb_status e) { delete h; return e; };
-  if (p->fp32) {
+  if (prec_of(p) == lbk::kFP32) {
     std::vector<float> f3(p->Lx);
     for (int x = 0; x < p->Lx; ++x) f3[x] = (float)(h->fext[x] / 3.0);
     if (hipMemcpyAsync(h->ws + L.fext, f3.data(), f3.size() * 4, hipMemcpyHostToDevice, h->st) != hipSuccess ||
@@ -234,7 +239,8 @@ lb_status lb_create(const lb_params* p, void* dev_ws, size_t ws_bytes, void* hip
   if ((r = upload_desc(h)) != LB_OK) return cleanup(r);
   // default shape: two steps per launch for FP32 lattices of at least 2^20
   // nodes whose strips are mostly interior columns, else one step per launch
-  if (p->fp32 && (int64_t)p->Lx * p->Ly >= ((int64_t)1 << 20) && p->Lx >= 256) {
+  if (prec_of(p) == lbk::kFP32 && p->collision == 0 && (int64_t)p->Lx * p->Ly >= ((int64_t)1 << 20) &&
+      p->Lx >= 256) {
     if ((r = set_tiles(h, 128, fused_default_rows(p, 128), 2)) != LB_OK) return cleanup(r);
   } else {
     const int th = default_threads(p);
@@ -379,7 +385,7 @@ lb_status lb_set_populations(lb_handle* h, const double* f, int64_t step) {
   h->parity = 0;
   for (int i = 0; i < 9; ++i) {
     HIPCHK(hipMemcpyAsync(h->dstage, f + i * nn, nn * 8, hipMemcpyHostToDevice, h->st));
-    HIPCHK(lbk::launch_set_pops(fp32_of(h), h->ddesc, 0, i, i + 1, nn, h->dstage, h->st));
+    HIPCHK(lbk::launch_set_pops(fp32_of(h), h->ddesc, 0, i, i + 1, nn, h->dstage, step, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
   }
   h->step = step;
@@ -452,7 +458,7 @@ lb_status lb_autotune(lb_handle* h, int32_t nsteps, int32_t* threads, int32_t* r
   };
   std::vector<Cand> cand;
   for (int t : {128, 256, 512}) {
-    if (t == 512 && !h->p.fp32) continue;
+    if (t == 512 && prec(h) != lbk::kFP32) continue;
     if (t > 128 && h->p.Lx + 6 <= t / 2) continue;
     std::vector<int> rs = {default_rows(&h->p, t, 1), default_rows(&h->p, t, 2), 16, 64};
     std::sort(rs.begin(), rs.end());
@@ -460,7 +466,7 @@ lb_status lb_autotune(lb_handle* h, int32_t nsteps, int32_t* threads, int32_t* r
     for (int rw : rs)
       if (rw <= h->p.Ly) cand.push_back({t, rw, 1});
   }
-  if (h->p.fp32)
+  if (prec(h) == lbk::kFP32 && h->p.collision == 0)
     for (int t : {64, 128, 192, 256}) {
       if (t > 128 && h->p.Lx + 14 <= t / 2) continue;
       std::vector<int> rs = {fused_default_rows(&h->p, t, 1), fused_default_rows(&h->p, t, 2), 32};

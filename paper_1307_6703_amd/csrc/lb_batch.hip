@@ -72,7 +72,9 @@ constexpr int kGraphSteps = 64;
 
 struct lb_batch {
   int count = 0;
-  bool fp32 = false;
+  bool fp32 = false;  // FP32 storage
+  int prec = 0;       // lbk::Prec of every instance
+  int reg = 0;        // regularised collision (every instance)
   int check_every = 0, drift = 0;
   char* ws = nullptr;
   hipStream_t st = nullptr;
@@ -194,12 +196,14 @@ lb_status upload_tiles(lb_batch* b, Tile* dst, int threads, int rows, int fuse, 
 // last of an odd count, subset steps).
 lb_status batch_tiles(lb_batch* b, int threads, int rows, int fuse = 1) {
   if (fuse == 2) {
-    if (!b->fp32) return fail(LB_EINVAL, "two steps per launch need FP32 storage");
+    if (b->prec != lbk::kFP32)
+      return fail(LB_EINVAL, "two steps per launch need FP32 storage and arithmetic (fp32 = 1)");
+    if (b->reg) return fail(LB_EINVAL, "two steps per launch need the BGK collision");
     if (!fused_threads_ok(threads))
       return fail(LB_EINVAL, "two steps per launch: threads must be 64, 128, 192 or 256 (got %d)", threads);
   } else if (threads != 64 && threads != 128 && threads != 256 && threads != 320 &&
-             !(threads == 512 && b->fp32)) {
-    return fail(LB_EINVAL, "threads must be 64, 128, 256, 320 or 512 (FP32 only) (got %d)", threads);
+             !(threads == 512 && b->prec == lbk::kFP32)) {
+    return fail(LB_EINVAL, "threads must be 64, 128, 256, 320 or 512 (fp32 = 1 only) (got %d)", threads);
   }
   if (rows < 1) return fail(LB_EINVAL, "rows must be >= 1");
   int nt = 0;
@@ -258,10 +262,10 @@ lb_status enqueue_steps(lb_batch* b, int64_t n, bool moments_last, bool dry = fa
       if (pair)
         HIPCHK(lbk::launch_step2(b->threads, b->ddesc, b->dtiles, b->ntiles, b->parity, flags, b->st));
       else if (b->fuse == 2)
-        HIPCHK(lbk::launch_step(b->fp32, b->threads1, b->ddesc, b->dtiles1, b->ntiles1, b->parity,
+        HIPCHK(lbk::launch_step(b->prec, b->reg != 0, b->threads1, b->ddesc, b->dtiles1, b->ntiles1, b->parity,
                                 flags, b->st));
       else
-        HIPCHK(lbk::launch_step(b->fp32, b->threads, b->ddesc, b->dtiles, b->ntiles, b->parity,
+        HIPCHK(lbk::launch_step(b->prec, b->reg != 0, b->threads, b->ddesc, b->dtiles, b->ntiles, b->parity,
                                 flags, b->st));
     }
     b->pending_shift = false;
@@ -352,12 +356,15 @@ lb_status lb_batch_create(int32_t count, const lb_params* p, void* dev_ws, size_
     lb_status s = validate(&p[i]);
     if (s != LB_OK) return s;
     if (p[i].fp32 != p[0].fp32) return fail(LB_EINVAL, "all instances must share fp32");
+    if (p[i].collision != p[0].collision) return fail(LB_EINVAL, "all instances must share collision");
     if (p[i].check_every != p[0].check_every || p[i].drift_correct != p[0].drift_correct)
       return fail(LB_EINVAL, "all instances must share check_every and drift_correct");
   }
   lb_batch* b = new lb_batch();
   b->count = count;
   b->fp32 = p[0].fp32 != 0;
+  b->prec = prec_of(&p[0]);
+  b->reg = p[0].collision;
   b->check_every = p[0].check_every;
   b->drift = p[0].drift_correct;
   b->inst.resize(count);
@@ -392,9 +399,11 @@ lb_status lb_batch_create(int32_t count, const lb_params* p, void* dev_ws, size_
     d.fext3 = b->ws + I.L.fext;
     d.mom = (double*)(b->ws + I.L.mom);
     d.shift = &b->dred[i].shift;
+    d.rng = b->dred[i].rng_step;
     d.Lx = p[i].Lx;
     d.Ly = p[i].Ly;
     d.periodic = p[i].y_periodic;
+    d.reg = p[i].collision;
     d.nbar = 0.0;
     d.T = p[i].T;
     d.omega = 1.0 / (std::sqrt(3.0) * p[i].tau);
@@ -408,7 +417,7 @@ lb_status lb_batch_create(int32_t count, const lb_params* p, void* dev_ws, size_
     if (p[i].fext_x)
       for (int x = 0; x < p[i].Lx; ++x) f[x] = p[i].fext_x[x] / 3.0;
     hipError_t e;
-    if (b->fp32) {
+    if (b->prec == lbk::kFP32) {
       std::vector<float> f32(f.begin(), f.end());
       e = hipMemcpyAsync(b->ws + I.L.fext, f32.data(), f32.size() * 4, hipMemcpyHostToDevice, b->st);
       if (e == hipSuccess) e = hipStreamSynchronize(b->st);
@@ -578,8 +587,8 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t nsteps, int32_t* threads, int32
   std::vector<Cand> cand;
   for (int t : {128, 256, 512})
     for (int rw : {16, 32, 64, 128, 256})
-      if (t != 512 || b->fp32) cand.push_back({t, rw, 1});
-  if (b->fp32)
+      if (t != 512 || b->prec == lbk::kFP32) cand.push_back({t, rw, 1});
+  if (b->prec == lbk::kFP32 && !b->reg)
     for (int t : {64, 128, 192, 256})
       for (int rw : {16, 32, 48, 64, 128, 256}) cand.push_back({t, rw, 2});
   hipEvent_t e0, e1;
@@ -714,7 +723,7 @@ lb_status lb_batch_step_subset(lb_batch* b, int64_t nsteps, const int32_t* mask)
       if (kind == 2)
         HIPCHK(lbk::launch_step2(th, b->ddesc, b->dsub, (int)t.size(), par, flags, b->st));
       else
-        HIPCHK(lbk::launch_step(b->fp32, th, b->ddesc, b->dsub, (int)t.size(), par, flags, b->st));
+        HIPCHK(lbk::launch_step(b->prec, b->reg != 0, th, b->ddesc, b->dsub, (int)t.size(), par, flags, b->st));
     }
   }
   lb_status r = enqueue_checks(b, 0, -1, mask);

@@ -10,6 +10,14 @@
 // is 0 in FP64 mode (g = f) and the mean density in FP32 mode, so the stored
 // values are small deviations that keep FP32 resolution.
 //
+// Three precisions: FP64 storage and arithmetic; FP32 storage and
+// arithmetic; FP32 storage with FP64 arithmetic, where each stored value is
+// rounded stochastically (up or down with the probabilities that make the
+// expected stored value the exact one). Rounding to nearest repeats the same
+// error every step once a pattern is steady, and the lattice integrates that
+// bias over the relaxation time of its slowest modes; unbiased rounding turns
+// it into noise that does not accumulate.
+//
 // Step kernel design. A workgroup of NT threads owns a strip of NT-6 columns
 // and a chunk of rows; thread t works on column x0-3+t. It marches along y:
 // each iteration loads one new row (9 coalesced pulls per node) and moves four
@@ -97,6 +105,7 @@ template <typename R>
 struct Coll {
   R keep, om, oneT, s3;      // 1 - omega, omega, 1 - T, 3 s
   R owr0, owra, owrd;        // omega w^_i
+  R wr0, wra, wrd;           // w^_i
   R w0, wa, wd;              // w_i
   R w0s, was, wds;           // w_i s
 };
@@ -112,6 +121,9 @@ __device__ __forceinline__ Coll<R> make_coll(const Desc& d) {
   c.owr0 = (R)(om * rest_weight_hd(0, d.T));
   c.owra = (R)(om * rest_weight_hd(1, d.T));
   c.owrd = (R)(om * rest_weight_hd(5, d.T));
+  c.wr0 = (R)rest_weight_hd(0, d.T);
+  c.wra = (R)rest_weight_hd(1, d.T);
+  c.wrd = (R)rest_weight_hd(5, d.T);
   c.w0 = (R)(4.0 / 9.0);
   c.wa = (R)(1.0 / 9.0);
   c.wd = (R)(1.0 / 36.0);
@@ -383,179 +395,6 @@ __device__ __forceinline__ void stage_wall(R g[9], int wall, R dn, R n, R Fx, R 
 template <typename R>
 __device__ __forceinline__ R slot_sum(const R v[9]) {
   return ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])) + v[8];
-}
-
-// Rows of populations in flight ahead of stage A, and the waves per SIMD the
-// register budget is sized for (FP32; FP64 always sizes for one wave). Two
-// rows at 3 waves per SIMD (about 140 VGPRs, no spills) measured fastest on
-// the 8192 x 2048 lattice: one 512-thread workgroup per CU, 255 workgroups.
-#ifndef LB_PREFETCH
-#define LB_PREFETCH 2
-#endif
-#ifndef LB_WAVES_PER_SIMD
-#define LB_WAVES_PER_SIMD 3
-#endif
-constexpr int kPrefetch = LB_PREFETCH;
-static_assert(kPrefetch == 1 || kPrefetch == 2 || kPrefetch == 4, "prefetch depth must divide 8");
-
-template <typename R, int NT, bool MOM>
-__global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void step_kernel(
-    const Desc* __restrict__ descs, const Tile* __restrict__ tiles, int ntiles, int parity,
-    int flags) {
-  // Workgroups are dealt round-robin over the 8 XCDs; give each XCD a
-  // contiguous run of tiles so vertically adjacent chunks share its L2.
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int q = nb >> 3, rm = nb & 7, xcd = b & 7;
-  const int logical = xcd * q + (xcd < rm ? xcd : rm) + (b >> 3);
-  if (logical >= ntiles) return;  // uniform per block
-  const Tile tile = tiles[logical];
-  const int inst = tile.inst & 0x7fffffff;
-  const int dir = (tile.inst < 0) ? -1 : 1;  // march direction along y
-  const Desc& d = descs[inst];
-  const int Lx = d.Lx, Ly = d.Ly, periodic = d.periodic;
-  const int64_t nn = (int64_t)Lx * Ly;
-  const int rowb = 9 * Lx * (int)sizeof(R);        // bytes of one row (nine planes)
-  const int arrb = (int)(9 * nn * (int64_t)sizeof(R));  // bytes of the nine planes (< 2 GiB)
-  const __amdgpu_buffer_rsrc_t Sin = make_rsrc(d.S[parity], arrb);
-  const __amdgpu_buffer_rsrc_t Sout = make_rsrc(d.S[parity ^ 1], arrb);
-  const __amdgpu_buffer_rsrc_t Snone = make_rsrc(d.S[parity ^ 1], 0);  // drops every access
-  const R* __restrict__ fext3 = (const R*)d.fext3;
-  const Coll<R> cl = make_coll<R>(d);
-  const Sten<R> c = make_sten<R>(d, dir);
-  R shift = (R)0;
-  if ((flags & kApplyShift) && d.shift) shift = (R)(*d.shift);
-  const R sh0 = shift * (R)rest_weight_hd(0, d.T), sha = shift * (R)rest_weight_hd(1, d.T),
-          shd = shift * (R)rest_weight_hd(5, d.T);
-
-  const int t = threadIdx.x;
-  const int W = min(NT - 6, Lx - tile.x0);  // columns this strip updates
-  int xc = (tile.x0 - 3 + t) % Lx;
-  if (xc < 0) xc += Lx;
-  const int xm = xc == 0 ? Lx - 1 : xc - 1;  // source of c_x = +1
-  const int xp = xc == Lx - 1 ? 0 : xc + 1;  // source of c_x = -1
-  const bool actA = t < W + 6;
-  const bool actB = t >= 1 && t < W + 5;
-  const bool actC = t >= 2 && t < W + 4;
-  const bool actD = t >= 3 && t < W + 3;
-  // per-lane byte offsets; lanes outside the strip use the array bound (dropped)
-  const int vc = actA ? xc * (int)sizeof(R) : arrb;
-  const int vm = actA ? xm * (int)sizeof(R) : arrb;
-  const int vp = actA ? xp * (int)sizeof(R) : arrb;
-  const R fx3 = actC ? fext3[xc] : (R)0;
-  const uint32_t pbytes = (uint32_t)Lx * (uint32_t)sizeof(R);  // plane stride within a row
-
-  // LDS rings indexed by pipeline row j (row a_j = a_0 + dir j): slot j % 8
-  // for n, j % 4 for the others. With the loop unrolled by 8 every slot is a
-  // compile-time offset. One padding entry on each side keeps the stencil
-  // reads of edge lanes inside the arrays.
-  __shared__ R nR[8][NT + 2];          // density deviation dn
-  __shared__ Pair<R> LP[4][NT + 2];    // (Laplacian of n, p^i - p^w)
-  __shared__ Quad<R> JR[4][NT + 2];    // (j*_x, j*_y, F_x, F_y)
-  const int u = t + 1;                 // padded column index
-
-  constexpr int P = kPrefetch;
-  R f[4][9];     // pulled populations, slot j % 4
-  R pf[P][9];    // the next P rows' pulled populations, in flight (slot j % P)
-#pragma unroll
-  for (int s = 0; s < 4; ++s)
-#pragma unroll
-    for (int i = 0; i < 9; ++i) f[s][i] = (R)0;
-
-  const int y0 = tile.y0, y1 = tile.y1;
-  // Pipeline rows j = 0 .. K-1 are rows y0-3 .. y1+2 in march order. At
-  // iteration k: A on row j = k, B on k-1, C on k-2, D on k-3. Valid: A for
-  // k < K, B for 2 <= k < K, C for 4 <= k < K, D for 6 <= k < K. Iterations
-  // past K (at most 7, only when the chunk height is not 2 mod 8) run with
-  // their memory accesses dropped. Every load and store is issued on every
-  // iteration, outside branches, so the compiler can count them exactly
-  // when it waits for the prefetched row.
-  const int K = (y1 - y0) + 6;
-  const int a0 = dir > 0 ? y0 - 3 : y1 + 2;
-
-#pragma unroll
-  for (int j = 0; j < P; ++j)
-    pull_row<R>(pf[j], j < K ? Sin : Snone, pbytes, (uint32_t)rowb, Ly, periodic,
-                map_row_any(a0 + dir * j, Ly, periodic), vc, vm, vp);
-
-  for (int kb = 0; kb < K; kb += 8) {
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int k = kb + s;
-      const int a = a0 + dir * k;
-      // ---- stage A: row a (its loads were issued P iterations ago) -----------
-      if (k < K) {
-        R* v = f[s & 3];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) v[i] = pf[s % P][i];
-        if (shift != (R)0) {
-          v[0] += sh0;
-#pragma unroll
-          for (int i = 1; i <= 4; ++i) v[i] += sha;
-#pragma unroll
-          for (int i = 5; i <= 8; ++i) v[i] += shd;
-        }
-        nR[s][u] = slot_sum<R>(v);
-      }
-      // prefetch row a + P dir into the slot just consumed (dropped past the
-      // last pipeline row)
-      pull_row<R>(pf[s % P], (k + P < K) ? Sin : Snone, pbytes, (uint32_t)rowb, Ly, periodic,
-                  map_row_any(a + P * dir, Ly, periodic), vc, vm, vp);
-      __syncthreads();
-      // ---- stage B: row a - dir: Laplacian and pressure term -----------------
-      if (k >= 2 && k < K && actB)
-        LP[(s + 3) & 3][u] = stage_lp<R>(nR[(s + 6) & 7], nR[(s + 7) & 7], nR[s], u, c);
-      __syncthreads();
-      // ---- stage C: row a - 2 dir: force and j* ------------------------------
-      if (k >= 4 && k < K && actC) {
-        const R n = c.nbar + nR[(s + 6) & 7][u];
-        R Fx, Fy, jx, jy;
-        stage_force<R>(LP[(s + 1) & 3], LP[(s + 2) & 3], LP[(s + 3) & 3], u, n, fx3, c, Fx, Fy);
-        // momentum of the pulled populations of this row, still in the ring
-        const RowMap m = map_row(a - 2 * dir, Ly, periodic);
-        stage_mom<R>(f[(s + 2) & 3], m.wall, m.ysgn, n, Fx, Fy, c, jx, jy);
-        JR[(s + 2) & 3][u] = Quad<R>{jx, jy, Fx, Fy};
-      }
-      __syncthreads();
-      // ---- stage D: row a - 3 dir: walls, collision, store -------------------
-      const int dd = a - 3 * dir;
-      const bool validD = k >= 6 && k < K;
-      // rows without a valid D stage store nothing (their stores are dropped)
-      R g[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) g[i] = f[(s + 1) & 3][i];
-      R n = (R)1, ux = (R)0, uy = (R)0;
-      if (validD) {
-        R dnx, dny, D;
-        stage_grad<R>(nR[(s + 4) & 7], nR[(s + 5) & 7], nR[(s + 6) & 7], JR[s & 3],
-                      JR[(s + 1) & 3], JR[(s + 2) & 3], u, (R)1, (R)1, c, dnx, dny, D);
-        const Quad<R> mC = JR[(s + 1) & 3][u];
-        const R dn = nR[(s + 5) & 7][u];
-        n = c.nbar + dn;
-        const R rn = fast_rcp<R>(n);
-        ux = mC.jx * rn;
-        uy = mC.jy * rn;
-        const int wall = periodic ? 0 : (dd == 0 ? 1 : (dd == Ly - 1 ? 2 : 0));
-        stage_wall<R>(g, wall, dn, n, mC.Fx, mC.Fy, c);
-        collide<R>(g, cl, n, dn, mC.jx, mC.jy, rn, mC.Fx, mC.Fy, dnx, dny, D);
-      }
-      {
-        const __amdgpu_buffer_rsrc_t so = validD ? Sout : Snone;
-        const uint32_t roff = validD ? (uint32_t)dd * (uint32_t)rowb : 0u;
-        const int vst = actD ? vc : arrb;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) buf_st(g[i], so, vst, (int)((uint32_t)i * pbytes + roff));
-        if (MOM) {
-          const int momb = (int)(3 * nn * 8);
-          const __amdgpu_buffer_rsrc_t mo = make_rsrc(d.mom, validD ? momb : 0);
-          const int vo = actD ? xc * 8 : momb;
-          const int ro = validD ? dd * Lx * 8 : 0;
-          buf_st((double)n, mo, vo, ro);
-          buf_st((double)ux, mo, vo, (int)(nn * 8) + ro);
-          buf_st((double)uy, mo, vo, (int)(2 * nn * 8) + ro);
-        }
-      }
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -903,33 +742,379 @@ hipError_t launch_step2(int threads, const Desc* d_descs, const Tile* d_tiles, i
   return hipErrorInvalidValue;
 }
 
-template <typename R, int NT>
+// ---------------------------------------------------------------------------
+// ---- one-step kernel: step_kernel in three precisions, the stochastic
+// rounding and the regularised collision. The code above this section is
+// everything the two-step kernel compiles from.
+// ---------------------------------------------------------------------------
+
+// Counter-based random numbers for the stochastic rounding: the pcg4d hash of
+// Jarzynski and Olano ("Hash Functions for GPU Rendering", JCGT 9(3), 2020),
+// applied to (column, row, step, 0), so every node, step and population gets
+// its own draw and the stream does not depend on the launch shape.
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 pcg4d(U4 v) {
+  v.x = v.x * 1664525u + 1013904223u;
+  v.y = v.y * 1664525u + 1013904223u;
+  v.z = v.z * 1664525u + 1013904223u;
+  v.w = v.w * 1664525u + 1013904223u;
+  v.x += v.y * v.w;
+  v.y += v.z * v.x;
+  v.z += v.x * v.y;
+  v.w += v.y * v.z;
+  v.x ^= v.x >> 16;
+  v.y ^= v.y >> 16;
+  v.z ^= v.z >> 16;
+  v.w ^= v.w >> 16;
+  v.x += v.y * v.w;
+  v.y += v.z * v.x;
+  v.z += v.x * v.y;
+  v.w += v.y * v.z;
+  return v;
+}
+
+// Nine 14-bit draws from one hash: two from the low 28 bits of each word,
+// the ninth from the words' top 4 bits.
+__device__ __forceinline__ void draws14(U4 h, uint32_t q[9]) {
+  q[0] = h.x & 0x3fffu; q[1] = (h.x >> 14) & 0x3fffu;
+  q[2] = h.y & 0x3fffu; q[3] = (h.y >> 14) & 0x3fffu;
+  q[4] = h.z & 0x3fffu; q[5] = (h.z >> 14) & 0x3fffu;
+  q[6] = h.w & 0x3fffu; q[7] = (h.w >> 14) & 0x3fffu;
+  q[8] = ((h.x >> 28) | ((h.y >> 28) << 4) | ((h.z >> 28) << 8) | ((h.w >> 30) << 12)) & 0x3fffu;
+}
+
+// Unbiased rounding of v to float. The magnitude goes to its nearest float
+// or to the neighbouring float on the other side of it, the latter with
+// probability |remainder| / gap, so the expected result is v (up to the
+// 14-bit resolution of the draw q, a bias below 2^-15 of a float ulp).
+__device__ __forceinline__ float round_stochastic(double v, uint32_t q) {
+  const double a = fabs(v);
+  const float fn = (float)a;          // nearest, ties to even
+  const double r = a - (double)fn;    // exact
+  const uint32_t b = __float_as_uint(fn);
+  // r < 0 implies fn > 0, so b - 1 stays a finite non-negative float
+  const float fo = __uint_as_float(r > 0.0 ? b + 1u : b - 1u);
+  const double gap = fabs((double)fo - (double)fn);
+  const float m = ((double)q + 0.5) * (1.0 / 16384.0) * gap < fabs(r) ? fo : fn;
+  return v < 0.0 ? -m : m;
+}
+
+// Regularised collision (Sec. II names the step that re-projects the
+// post-collision populations onto the Hermite space): the non-equilibrium
+// part h = g - geq is replaced by its projection onto the Hermite
+// polynomials of order <= 2 before it relaxes,
+//   g_i <- geq_i + (1 - omega) P[h]_i + F_i,
+//   P[h]_i = w_i [a0 + 3 a1.c_i + 9/2 a2 : (c_i c_i - I/3)],
+// a0 = sum h, a1 = sum h c, a2 = sum h (c c - I/3); geq and F as in collide.
+template <typename R>
+__device__ __forceinline__ void collide_reg(R g[9], const Coll<R>& c, R n, R dn, R jx, R jy,
+                                            R rn, R Fx, R Fy, R dnx, R dny, R D) {
+  const R ux = jx * rn, uy = jy * rn;
+  const R usq = (R)1.5 * (ux * ux + uy * uy);
+  const R Xxx = (R)6 * ux * Fx + c.oneT * ((R)2 * ux * dnx + D);
+  const R Xyy = (R)6 * uy * Fy + c.oneT * ((R)2 * uy * dny + D);
+  const R Xxy = (R)3 * (ux * Fy + uy * Fx) + c.oneT * (ux * dny + uy * dnx);
+  const R trX = Xxx + Xyy;
+  // equilibrium deviations and forcing, by direction
+  R eq[9], fo[9];
+  eq[0] = c.wr0 * dn - c.w0 * (n * usq);
+  fo[0] = -c.w0s * ((R)0.5 * trX);
+  {
+    const R e = c.wra * dn + c.wa * (n * ((R)4.5 * ux * ux - usq)), a = (R)3 * c.wa * jx;
+    const R fs = c.was * (Xxx - (R)0.5 * Xyy), fa = c.wa * c.s3 * Fx;
+    eq[1] = e + a; eq[3] = e - a; fo[1] = fs + fa; fo[3] = fs - fa;
+  }
+  {
+    const R e = c.wra * dn + c.wa * (n * ((R)4.5 * uy * uy - usq)), a = (R)3 * c.wa * jy;
+    const R fs = c.was * (Xyy - (R)0.5 * Xxx), fa = c.wa * c.s3 * Fy;
+    eq[2] = e + a; eq[4] = e - a; fo[2] = fs + fa; fo[4] = fs - fa;
+  }
+  {
+    const R cu = ux + uy;
+    const R e = c.wrd * dn + c.wd * (n * ((R)4.5 * cu * cu - usq)), a = (R)3 * c.wd * (jx + jy);
+    const R fs = c.wds * (trX + (R)3 * Xxy), fa = c.wd * c.s3 * (Fx + Fy);
+    eq[5] = e + a; eq[7] = e - a; fo[5] = fs + fa; fo[7] = fs - fa;
+  }
+  {
+    const R cu = uy - ux;
+    const R e = c.wrd * dn + c.wd * (n * ((R)4.5 * cu * cu - usq)), a = (R)3 * c.wd * (jy - jx);
+    const R fs = c.wds * (trX - (R)3 * Xxy), fa = c.wd * c.s3 * (Fy - Fx);
+    eq[6] = e + a; eq[8] = e - a; fo[6] = fs + fa; fo[8] = fs - fa;
+  }
+  R h[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) h[i] = g[i] - eq[i];
+  const R a0 = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+  const R a1x = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
+  const R a1y = (h[2] - h[4]) + (h[5] - h[8]) + (h[6] - h[7]);
+  const R dg = (h[5] + h[6]) + (h[7] + h[8]);
+  const R a2xx = (h[1] + h[3]) + dg - a0 * (R)(1.0 / 3.0);
+  const R a2yy = (h[2] + h[4]) + dg - a0 * (R)(1.0 / 3.0);
+  const R a2xy = (h[5] - h[6]) + (h[7] - h[8]);
+  // P[h] by direction, times 1 - omega: w_i [a0 + 3 a1.c + 9/2 a2:(cc - I/3)]
+  const R k0 = c.keep * c.w0, ka = c.keep * c.wa, kd = c.keep * c.wd;
+  g[0] = eq[0] + k0 * (a0 - (R)1.5 * (a2xx + a2yy)) + fo[0];
+  {
+    const R s = a0 + (R)3 * a2xx - (R)1.5 * a2yy, t = (R)3 * a1x;
+    g[1] = eq[1] + ka * (s + t) + fo[1];
+    g[3] = eq[3] + ka * (s - t) + fo[3];
+  }
+  {
+    const R s = a0 + (R)3 * a2yy - (R)1.5 * a2xx, t = (R)3 * a1y;
+    g[2] = eq[2] + ka * (s + t) + fo[2];
+    g[4] = eq[4] + ka * (s - t) + fo[4];
+  }
+  {
+    const R s = a0 + (R)3 * (a2xx + a2yy), x9 = (R)9 * a2xy;
+    const R t5 = (R)3 * (a1x + a1y), t6 = (R)3 * (a1y - a1x);
+    g[5] = eq[5] + kd * (s + x9 + t5) + fo[5];
+    g[7] = eq[7] + kd * (s + x9 - t5) + fo[7];
+    g[6] = eq[6] + kd * (s - x9 + t6) + fo[6];
+    g[8] = eq[8] + kd * (s - x9 - t6) + fo[8];
+  }
+}
+
+// Rows of populations in flight ahead of stage A, and the waves per SIMD the
+// register budget is sized for (FP32; FP64 always sizes for one wave). Two
+// rows at 3 waves per SIMD (about 140 VGPRs, no spills) measured fastest on
+// the 8192 x 2048 lattice: one 512-thread workgroup per CU, 255 workgroups.
+#ifndef LB_PREFETCH
+#define LB_PREFETCH 2
+#endif
+#ifndef LB_WAVES_PER_SIMD
+#define LB_WAVES_PER_SIMD 3
+#endif
+constexpr int kPrefetch = LB_PREFETCH;
+static_assert(kPrefetch == 1 || kPrefetch == 2 || kPrefetch == 4, "prefetch depth must divide 8");
+
+// S: storage type of the populations, R: arithmetic type. S = float with
+// R = double stores through round_stochastic. REG: regularised collision.
+template <typename S, typename R, int NT, bool MOM, bool REG>
+__global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void step_kernel(
+    const Desc* __restrict__ descs, const Tile* __restrict__ tiles, int ntiles, int parity,
+    int flags) {
+  constexpr bool kSR = sizeof(S) < sizeof(R);
+  // Workgroups are dealt round-robin over the 8 XCDs; give each XCD a
+  // contiguous run of tiles so vertically adjacent chunks share its L2.
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb >> 3, rm = nb & 7, xcd = b & 7;
+  const int logical = xcd * q + (xcd < rm ? xcd : rm) + (b >> 3);
+  if (logical >= ntiles) return;  // uniform per block
+  const Tile tile = tiles[logical];
+  const int inst = tile.inst & 0x7fffffff;
+  const int dir = (tile.inst < 0) ? -1 : 1;  // march direction along y
+  const Desc& d = descs[inst];
+  const int Lx = d.Lx, Ly = d.Ly, periodic = d.periodic;
+  const int64_t nn = (int64_t)Lx * Ly;
+  const int rowb = 9 * Lx * (int)sizeof(S);        // bytes of one row (nine planes)
+  const int arrb = (int)(9 * nn * (int64_t)sizeof(S));  // bytes of the nine planes (< 2 GiB)
+  const __amdgpu_buffer_rsrc_t Sin = make_rsrc(d.S[parity], arrb);
+  const __amdgpu_buffer_rsrc_t Sout = make_rsrc(d.S[parity ^ 1], arrb);
+  const __amdgpu_buffer_rsrc_t Snone = make_rsrc(d.S[parity ^ 1], 0);  // drops every access
+  const R* __restrict__ fext3 = (const R*)d.fext3;
+  const Coll<R> cl = make_coll<R>(d);
+  const Sten<R> c = make_sten<R>(d, dir);
+  // Stochastic rounding: this launch's step number comes from the counter of
+  // the buffer it reads; the workgroup of the lattice's first tile writes the
+  // next one into the counter of the buffer it writes (read by the next
+  // launch, untouched by this one).
+  uint32_t rstep = 0;
+  if constexpr (kSR) {
+    rstep = d.rng[parity];
+    if (tile.x0 == 0 && tile.y0 == 0 && threadIdx.x == 0) d.rng[parity ^ 1] = rstep + 1u;
+  }
+  R shift = (R)0;
+  if ((flags & kApplyShift) && d.shift) shift = (R)(*d.shift);
+  const R sh0 = shift * (R)rest_weight_hd(0, d.T), sha = shift * (R)rest_weight_hd(1, d.T),
+          shd = shift * (R)rest_weight_hd(5, d.T);
+
+  const int t = threadIdx.x;
+  const int W = min(NT - 6, Lx - tile.x0);  // columns this strip updates
+  int xc = (tile.x0 - 3 + t) % Lx;
+  if (xc < 0) xc += Lx;
+  const int xm = xc == 0 ? Lx - 1 : xc - 1;  // source of c_x = +1
+  const int xp = xc == Lx - 1 ? 0 : xc + 1;  // source of c_x = -1
+  const bool actA = t < W + 6;
+  const bool actB = t >= 1 && t < W + 5;
+  const bool actC = t >= 2 && t < W + 4;
+  const bool actD = t >= 3 && t < W + 3;
+  // per-lane byte offsets; lanes outside the strip use the array bound (dropped)
+  const int vc = actA ? xc * (int)sizeof(S) : arrb;
+  const int vm = actA ? xm * (int)sizeof(S) : arrb;
+  const int vp = actA ? xp * (int)sizeof(S) : arrb;
+  const R fx3 = actC ? fext3[xc] : (R)0;
+  const uint32_t pbytes = (uint32_t)Lx * (uint32_t)sizeof(S);  // plane stride within a row
+
+  // LDS rings indexed by pipeline row j (row a_j = a_0 + dir j): slot j % 8
+  // for n, j % 4 for the others. With the loop unrolled by 8 every slot is a
+  // compile-time offset. One padding entry on each side keeps the stencil
+  // reads of edge lanes inside the arrays.
+  __shared__ R nR[8][NT + 2];          // density deviation dn
+  __shared__ Pair<R> LP[4][NT + 2];    // (Laplacian of n, p^i - p^w)
+  __shared__ Quad<R> JR[4][NT + 2];    // (j*_x, j*_y, F_x, F_y)
+  const int u = t + 1;                 // padded column index
+
+  constexpr int P = kPrefetch;
+  R f[4][9];     // pulled populations, slot j % 4
+  S pf[P][9];    // the next P rows' pulled populations, in flight (slot j % P)
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[s][i] = (R)0;
+
+  const int y0 = tile.y0, y1 = tile.y1;
+  // Pipeline rows j = 0 .. K-1 are rows y0-3 .. y1+2 in march order. At
+  // iteration k: A on row j = k, B on k-1, C on k-2, D on k-3. Valid: A for
+  // k < K, B for 2 <= k < K, C for 4 <= k < K, D for 6 <= k < K. Iterations
+  // past K (at most 7, only when the chunk height is not 2 mod 8) run with
+  // their memory accesses dropped. Every load and store is issued on every
+  // iteration, outside branches, so the compiler can count them exactly
+  // when it waits for the prefetched row.
+  const int K = (y1 - y0) + 6;
+  const int a0 = dir > 0 ? y0 - 3 : y1 + 2;
+
+#pragma unroll
+  for (int j = 0; j < P; ++j)
+    pull_row<S>(pf[j], j < K ? Sin : Snone, pbytes, (uint32_t)rowb, Ly, periodic,
+                map_row_any(a0 + dir * j, Ly, periodic), vc, vm, vp);
+
+  for (int kb = 0; kb < K; kb += 8) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = kb + s;
+      const int a = a0 + dir * k;
+      // ---- stage A: row a (its loads were issued P iterations ago) -----------
+      if (k < K) {
+        R* v = f[s & 3];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) v[i] = (R)pf[s % P][i];
+        if (shift != (R)0) {
+          v[0] += sh0;
+#pragma unroll
+          for (int i = 1; i <= 4; ++i) v[i] += sha;
+#pragma unroll
+          for (int i = 5; i <= 8; ++i) v[i] += shd;
+        }
+        nR[s][u] = slot_sum<R>(v);
+      }
+      // prefetch row a + P dir into the slot just consumed (dropped past the
+      // last pipeline row)
+      pull_row<S>(pf[s % P], (k + P < K) ? Sin : Snone, pbytes, (uint32_t)rowb, Ly, periodic,
+                  map_row_any(a + P * dir, Ly, periodic), vc, vm, vp);
+      __syncthreads();
+      // ---- stage B: row a - dir: Laplacian and pressure term -----------------
+      if (k >= 2 && k < K && actB)
+        LP[(s + 3) & 3][u] = stage_lp<R>(nR[(s + 6) & 7], nR[(s + 7) & 7], nR[s], u, c);
+      __syncthreads();
+      // ---- stage C: row a - 2 dir: force and j* ------------------------------
+      if (k >= 4 && k < K && actC) {
+        const R n = c.nbar + nR[(s + 6) & 7][u];
+        R Fx, Fy, jx, jy;
+        stage_force<R>(LP[(s + 1) & 3], LP[(s + 2) & 3], LP[(s + 3) & 3], u, n, fx3, c, Fx, Fy);
+        // momentum of the pulled populations of this row, still in the ring
+        const RowMap m = map_row(a - 2 * dir, Ly, periodic);
+        stage_mom<R>(f[(s + 2) & 3], m.wall, m.ysgn, n, Fx, Fy, c, jx, jy);
+        JR[(s + 2) & 3][u] = Quad<R>{jx, jy, Fx, Fy};
+      }
+      __syncthreads();
+      // ---- stage D: row a - 3 dir: walls, collision, store -------------------
+      const int dd = a - 3 * dir;
+      const bool validD = k >= 6 && k < K;
+      // rows without a valid D stage store nothing (their stores are dropped)
+      R g[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) g[i] = f[(s + 1) & 3][i];
+      R n = (R)1, ux = (R)0, uy = (R)0;
+      if (validD) {
+        R dnx, dny, D;
+        stage_grad<R>(nR[(s + 4) & 7], nR[(s + 5) & 7], nR[(s + 6) & 7], JR[s & 3],
+                      JR[(s + 1) & 3], JR[(s + 2) & 3], u, (R)1, (R)1, c, dnx, dny, D);
+        const Quad<R> mC = JR[(s + 1) & 3][u];
+        const R dn = nR[(s + 5) & 7][u];
+        n = c.nbar + dn;
+        const R rn = fast_rcp<R>(n);
+        ux = mC.jx * rn;
+        uy = mC.jy * rn;
+        const int wall = periodic ? 0 : (dd == 0 ? 1 : (dd == Ly - 1 ? 2 : 0));
+        stage_wall<R>(g, wall, dn, n, mC.Fx, mC.Fy, c);
+        if constexpr (REG)
+          collide_reg<R>(g, cl, n, dn, mC.jx, mC.jy, rn, mC.Fx, mC.Fy, dnx, dny, D);
+        else
+          collide<R>(g, cl, n, dn, mC.jx, mC.jy, rn, mC.Fx, mC.Fy, dnx, dny, D);
+      }
+      {
+        const __amdgpu_buffer_rsrc_t so = validD ? Sout : Snone;
+        const uint32_t roff = validD ? (uint32_t)dd * (uint32_t)rowb : 0u;
+        const int vst = actD ? vc : arrb;
+        if constexpr (kSR) {
+          uint32_t q[9];
+          draws14(pcg4d(U4{(uint32_t)xc, (uint32_t)dd, rstep, 0u}), q);
+#pragma unroll
+          for (int i = 0; i < 9; ++i)
+            buf_st(round_stochastic(g[i], q[i]), so, vst, (int)((uint32_t)i * pbytes + roff));
+        } else {
+#pragma unroll
+          for (int i = 0; i < 9; ++i) buf_st(g[i], so, vst, (int)((uint32_t)i * pbytes + roff));
+        }
+        if (MOM) {
+          const int momb = (int)(3 * nn * 8);
+          const __amdgpu_buffer_rsrc_t mo = make_rsrc(d.mom, validD ? momb : 0);
+          const int vo = actD ? xc * 8 : momb;
+          const int ro = validD ? dd * Lx * 8 : 0;
+          buf_st((double)n, mo, vo, ro);
+          buf_st((double)ux, mo, vo, (int)(nn * 8) + ro);
+          buf_st((double)uy, mo, vo, (int)(2 * nn * 8) + ro);
+        }
+      }
+    }
+  }
+}
+
+template <typename S, typename R, int NT, bool REG>
 static hipError_t launch_step_t(const Desc* dd, const Tile* dt, int ntiles, int parity, int flags,
                                 hipStream_t st) {
   if (flags & kWriteMoments)
-    hipLaunchKernelGGL((step_kernel<R, NT, true>), dim3(ntiles), dim3(NT), 0, st, dd, dt, ntiles,
-                       parity, flags);
+    hipLaunchKernelGGL((step_kernel<S, R, NT, true, REG>), dim3(ntiles), dim3(NT), 0, st, dd, dt,
+                       ntiles, parity, flags);
   else
-    hipLaunchKernelGGL((step_kernel<R, NT, false>), dim3(ntiles), dim3(NT), 0, st, dd, dt, ntiles,
-                       parity, flags);
+    hipLaunchKernelGGL((step_kernel<S, R, NT, false, REG>), dim3(ntiles), dim3(NT), 0, st, dd,
+                       dt, ntiles, parity, flags);
   return hipGetLastError();
 }
 
-hipError_t launch_step(bool fp32, int threads, const Desc* d_descs, const Tile* d_tiles,
+template <typename S, typename R, bool REG>
+static hipError_t launch_step_p(int threads, const Desc* dd, const Tile* dt, int ntiles,
+                                int parity, int flags, hipStream_t st) {
+  if (threads == 64) return launch_step_t<S, R, 64, REG>(dd, dt, ntiles, parity, flags, st);
+  if (threads == 128) return launch_step_t<S, R, 128, REG>(dd, dt, ntiles, parity, flags, st);
+  if (threads == 256) return launch_step_t<S, R, 256, REG>(dd, dt, ntiles, parity, flags, st);
+  if (threads == 320) return launch_step_t<S, R, 320, REG>(dd, dt, ntiles, parity, flags, st);
+  if constexpr (sizeof(R) == 4)
+    if (threads == 512) return launch_step_t<S, R, 512, REG>(dd, dt, ntiles, parity, flags, st);
+  return hipErrorInvalidValue;
+}
+
+template <typename S, typename R>
+static hipError_t launch_step_c(bool reg, int threads, const Desc* dd, const Tile* dt, int ntiles,
+                                int parity, int flags, hipStream_t st) {
+  return reg ? launch_step_p<S, R, true>(threads, dd, dt, ntiles, parity, flags, st)
+             : launch_step_p<S, R, false>(threads, dd, dt, ntiles, parity, flags, st);
+}
+
+hipError_t launch_step(int prec, bool reg, int threads, const Desc* d_descs, const Tile* d_tiles,
                        int ntiles, int parity, int flags, hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
-  if (fp32) {
-    if (threads == 64) return launch_step_t<float, 64>(d_descs, d_tiles, ntiles, parity, flags, stream);
-    if (threads == 128) return launch_step_t<float, 128>(d_descs, d_tiles, ntiles, parity, flags, stream);
-    if (threads == 256) return launch_step_t<float, 256>(d_descs, d_tiles, ntiles, parity, flags, stream);
-    if (threads == 320) return launch_step_t<float, 320>(d_descs, d_tiles, ntiles, parity, flags, stream);
-    if (threads == 512) return launch_step_t<float, 512>(d_descs, d_tiles, ntiles, parity, flags, stream);
-  } else {
-    if (threads == 64) return launch_step_t<double, 64>(d_descs, d_tiles, ntiles, parity, flags, stream);
-    if (threads == 128) return launch_step_t<double, 128>(d_descs, d_tiles, ntiles, parity, flags, stream);
-    if (threads == 256) return launch_step_t<double, 256>(d_descs, d_tiles, ntiles, parity, flags, stream);
-    if (threads == 320) return launch_step_t<double, 320>(d_descs, d_tiles, ntiles, parity, flags, stream);
-  }
+  if (prec == kFP32)
+    return launch_step_c<float, float>(reg, threads, d_descs, d_tiles, ntiles, parity, flags, stream);
+  if (prec == kFP32SR)
+    return launch_step_c<float, double>(reg, threads, d_descs, d_tiles, ntiles, parity, flags,
+                                        stream);
+  if (prec == kFP64)
+    return launch_step_c<double, double>(reg, threads, d_descs, d_tiles, ntiles, parity, flags,
+                                         stream);
   return hipErrorInvalidValue;
 }
 
@@ -940,6 +1125,7 @@ __global__ void init_kernel(const Desc* __restrict__ desc, int parity, const dou
                             int64_t nn) {
   const Desc& d = *desc;
   R* S = (R*)d.S[parity];
+  if (d.rng && blockIdx.x == 0 && threadIdx.x == 0) d.rng[parity] = 0u;
   const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nn;
        k += (int64_t)gridDim.x * blockDim.x) {
@@ -1191,9 +1377,10 @@ __global__ void get_pops_kernel(const Desc* __restrict__ desc, int parity, int p
 
 template <typename R>
 __global__ void set_pops_kernel(const Desc* __restrict__ desc, int parity, int p0, int p1,
-                                int64_t nn, const double* __restrict__ in) {
+                                int64_t nn, const double* __restrict__ in, uint32_t step) {
   const Desc& d = *desc;
   R* S = (R*)d.S[parity];
+  if (d.rng && blockIdx.x == 0 && threadIdx.x == 0) d.rng[parity] = step;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nn;
        k += (int64_t)gridDim.x * blockDim.x)
     for (int i = p0; i < p1; ++i)
@@ -1213,13 +1400,13 @@ hipError_t launch_get_pops(bool fp32, const Desc* d_desc, int parity, int p0, in
 }
 
 hipError_t launch_set_pops(bool fp32, const Desc* d_desc, int parity, int p0, int p1, int64_t nn,
-                           const double* d_f, hipStream_t stream) {
+                           const double* d_f, int64_t step, hipStream_t stream) {
   if (fp32)
     hipLaunchKernelGGL(set_pops_kernel<float>, dim3(grid_for(nn, 256)), dim3(256), 0, stream,
-                       d_desc, parity, p0, p1, nn, d_f);
+                       d_desc, parity, p0, p1, nn, d_f, (uint32_t)step);
   else
     hipLaunchKernelGGL(set_pops_kernel<double>, dim3(grid_for(nn, 256)), dim3(256), 0, stream,
-                       d_desc, parity, p0, p1, nn, d_f);
+                       d_desc, parity, p0, p1, nn, d_f, (uint32_t)step);
   return hipGetLastError();
 }
 

@@ -50,7 +50,7 @@ inline lb_status validate(const lb_params* p) {
   if ((int64_t)p->Lx * p->Ly * 9 * (p->fp32 ? 4 : 8) >= ((int64_t)1 << 31))
     return fail(LB_EINVAL, "9*Lx*Ly*(4|8) bytes must be < 2 GiB (FP32: < 59652323 nodes)");
   if (p->y_periodic != 0 && p->y_periodic != 1) return fail(LB_EINVAL, "y_periodic must be 0 or 1");
-  if (p->fp32 != 0 && p->fp32 != 1) return fail(LB_EINVAL, "fp32 must be 0 or 1");
+  if (p->fp32 < 0 || p->fp32 > 2) return fail(LB_EINVAL, "fp32 must be 0, 1 or 2 (got %d)", p->fp32);
   if (!(p->T > 0.0 && p->T <= 1.5)) return fail(LB_EINVAL, "T must be in (0, 1.5] (got %g)", p->T);
   if (!(std::sqrt(3.0) * p->tau > 0.5) || !std::isfinite(p->tau))
     return fail(LB_EINVAL, "need sqrt(3)*tau > 1/2 (got tau=%g)", p->tau);
@@ -59,6 +59,7 @@ inline lb_status validate(const lb_params* p) {
   if (!(std::fabs(p->U) < 0.3)) return fail(LB_EINVAL, "|U| must be < 0.3 (got %g)", p->U);
   if (p->check_every < 0) return fail(LB_EINVAL, "check_every must be >= 0");
   if (p->drift_correct != 0 && p->drift_correct != 1) return fail(LB_EINVAL, "drift_correct must be 0 or 1");
+  if (p->collision != 0 && p->collision != 1) return fail(LB_EINVAL, "collision must be 0 or 1");
   if (p->fext_x)
     for (int x = 0; x < p->Lx; ++x)
       if (!std::isfinite(p->fext_x[x])) return fail(LB_EINVAL, "fext_x[%d] is not finite", x);
@@ -85,7 +86,7 @@ inline Layout layout_for(const lb_params* p, size_t base = 0) {
   L.red = o; o = align_up(o + sizeof(ReduceOut));
   L.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)L.max_tiles);
   L.tiles1 = o; o = align_up(o + sizeof(Tile) * (size_t)L.max_tiles);
-  L.fext = o; o = align_up(o + rs * (size_t)p->Lx);
+  L.fext = o; o = align_up(o + sizeof(double) * (size_t)p->Lx);  // FP32 or FP64 table
   L.part = o; o = align_up(o + sizeof(double) * 6 * (size_t)lbk::reduce_blocks((int64_t)nn));
   L.mom = o; o = align_up(o + sizeof(double) * 3 * nn);
   L.stage = o; o = align_up(o + sizeof(double) * nn);
@@ -95,12 +96,17 @@ inline Layout layout_for(const lb_params* p, size_t base = 0) {
   return L;
 }
 
+// Precision of a parameter set: lbk::kFP64, kFP32 or kFP32SR.
+inline int prec_of(const lb_params* p) { return p->fp32; }
+// FP64 arithmetic (FP64, or FP32 storage with stochastic rounding).
+inline bool arith64(const lb_params* p) { return p->fp32 != lbk::kFP32; }
+
 // Strip width: one strip per row for narrow lattices; 512-thread strips
 // (one workgroup per CU) once the lattice fills the device with them.
 inline int default_threads(const lb_params* p) {
   if (p->Lx + 6 <= 64) return 64;
-  // FP64 (two waves per SIMD): 256-thread strips once the lattice is large
-  if (!p->fp32) return ((int64_t)p->Lx * p->Ly >= ((int64_t)1 << 22) && p->Lx + 6 > 128) ? 256 : 128;
+  // FP64 arithmetic (two waves per SIMD): 256-thread strips once the lattice is large
+  if (arith64(p)) return ((int64_t)p->Lx * p->Ly >= ((int64_t)1 << 22) && p->Lx + 6 > 128) ? 256 : 128;
   if (p->Lx + 6 <= 128) return 128;
   if (p->Lx + 6 <= 256) return 256;
   if (p->Lx + 6 <= 320) return 320;  // one strip per row (e.g. 256-wide lattices)
@@ -109,7 +115,7 @@ inline int default_threads(const lb_params* p) {
 }
 
 // Workgroups of the step kernel that fit on the device at once: FP32 runs at
-// 3 waves per SIMD (about 140 VGPRs), FP64 at 2.
+// 3 waves per SIMD (about 140 VGPRs), FP64 arithmetic at 2.
 inline int resident_slots(const lb_params* p, int threads) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
@@ -117,7 +123,7 @@ inline int resident_slots(const lb_params* p, int threads) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
       cus = v;
   }
-  const int waves_per_cu = (p->fp32 ? 3 : 2) * 4;
+  const int waves_per_cu = (arith64(p) ? 2 : 3) * 4;
   return cus * std::max(1, waves_per_cu / ((threads + 63) / 64));
 }
 

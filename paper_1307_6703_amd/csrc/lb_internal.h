@@ -16,7 +16,9 @@ struct Desc {
   const void* fext3;     // per-column F_ext,x / 3 (lattice units), Lx values
   double* mom;           // n, ux, uy planes (FP64) of the last step, or null
   const double* shift;   // pending uniform density shift, or null
-  int32_t Lx, Ly, periodic, pad;
+  uint32_t* rng;         // step counters of the stochastic rounding (two words,
+                         // indexed by buffer parity), or null
+  int32_t Lx, Ly, periodic, reg;  // reg: regularised collision
   double nbar;           // reference density subtracted in storage (0 in FP64)
   double T, omega, kappa3, N, M, Q, R, U;
 };
@@ -36,11 +38,17 @@ struct ReduceOut {
   double shift;      // shift to apply at the next step (drift correction)
   uint32_t status;   // sticky: bit 0 set once a check failed
   uint32_t has_ref;  // mass_ref valid
-  uint32_t pad[2];
+  uint32_t rng_step[2];  // stochastic-rounding step counter, by buffer parity
 };
 
-// Launchers (all asynchronous on `stream`). fp32 selects the storage type.
-hipError_t launch_step(bool fp32, int threads, const Desc* d_descs, const Tile* d_tiles,
+// Precision of a lattice (lb_params.fp32): FP64 storage and arithmetic; FP32
+// deviations with FP32 arithmetic; FP32 deviations with FP64 arithmetic and
+// stochastic rounding of the stored values.
+enum Prec : int { kFP64 = 0, kFP32 = 1, kFP32SR = 2 };
+
+// Launchers (all asynchronous on `stream`). fp32 selects the storage type,
+// prec the kernel; reg the regularised collision (every listed lattice).
+hipError_t launch_step(int prec, bool reg, int threads, const Desc* d_descs, const Tile* d_tiles,
                        int ntiles, int parity, int flags, hipStream_t stream);
 // Two steps per launch (FP32 only; threads 64, 128, 192 or 256): tiles of
 // threads-14 columns, reads S[parity], writes S[parity ^ 1].
@@ -67,8 +75,9 @@ hipError_t launch_reduce_final(const double* d_part, int nb, int64_t nn, ReduceO
 // adding the pending shift when add_shift != 0.
 hipError_t launch_get_pops(bool fp32, const Desc* d_desc, int parity, int p0, int p1,
                            int64_t nn, double* d_f, int add_shift, hipStream_t stream);
+// Also sets the stochastic-rounding step counter of S[parity] to `step`.
 hipError_t launch_set_pops(bool fp32, const Desc* d_desc, int parity, int p0, int p1,
-                           int64_t nn, const double* d_f, hipStream_t stream);
+                           int64_t nn, const double* d_f, int64_t step, hipStream_t stream);
 // Batch helpers (all instances of the same size nn): gather the moment blocks
 // into out[count][3][nn]; write equilibrium populations from fields
 // [count][3][nn] for instances with d_mask[i] != 0 (device array), or, with

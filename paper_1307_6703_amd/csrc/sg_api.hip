@@ -107,9 +107,10 @@ bool wgrad_supported(int ci, int co) {
   return (ci == 8 && co == 48) || (ci == 48 && co == 48) || (ci == 48 && co == 16);
 }
 
-int conv_grid(int B, int H, int W) {
+int conv_grid(int B, int H, int W, int cap = 0) {
   const int64_t tiles = (int64_t)((W + sg::TW - 1) / sg::TW) * ((H + sg::TR - 1) / sg::TR) * B;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kConvGridMax));
+  const int64_t lim = cap > 0 ? cap : kConvGridMax;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, lim));
 }
 
 lb_status check_image(int B, int H, int W) {
@@ -123,7 +124,7 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 lb_status conv(int mode, int ci, int co, const void* x, const void* wp, const float* bias,
                const void* res, const void* zprev, void* y, void* z, float* yf, int nout, int B,
-               int H, int W, hipStream_t st) {
+               int H, int W, hipStream_t st, int blocks = 0) {
   sg::ConvArgs a;
   a.x = (const sg::bf16*)x;
   a.w = (const sg::bf16*)wp;
@@ -137,7 +138,7 @@ lb_status conv(int mode, int ci, int co, const void* x, const void* wp, const fl
   a.B = B;
   a.H = H;
   a.W = W;
-  HIPCHK(sg::launch_conv(ci, co, mode, a, conv_grid(B, H, W), st));
+  HIPCHK(sg::launch_conv(ci, co, mode, a, conv_grid(B, H, W, blocks), st));
   return LB_OK;
 }
 
@@ -404,8 +405,9 @@ lb_status lbs_pack(const float* d_w, int32_t cir, int32_t cor, int32_t CI, int32
 lb_status lbs_conv(int32_t mode, int32_t ci, int32_t co, const void* d_x, const void* d_wpack,
                    const float* d_bias, const void* d_res, const void* d_zprev, void* d_y,
                    void* d_z, float* d_yf, int32_t nout, int32_t B, int32_t H, int32_t W,
-                   void* hip_stream) {
+                   int32_t blocks, void* hip_stream) {
   if (mode < 0 || mode > 3) return fail(LB_EINVAL, "mode must be 0..3 (got %d)", mode);
+  if (blocks < 0 || blocks > 4096) return fail(LB_EINVAL, "blocks must be in [0, 4096]");
   if (!conv_supported(ci, co)) return fail(LB_EINVAL, "unsupported channel pair (%d, %d)", ci, co);
   lb_status r = check_image(B, H, W);
   if (r != LB_OK) return r;
@@ -422,7 +424,7 @@ lb_status lbs_conv(int32_t mode, int32_t ci, int32_t co, const void* d_x, const 
   if (mode == sg::FWD_RES && !d_res) return fail(LB_EINVAL, "residual mode needs res");
   if (mode == sg::BWD && !d_zprev) return fail(LB_EINVAL, "backward mode needs zprev");
   return conv(mode, ci, co, d_x, d_wpack, d_bias, d_res, d_zprev, d_y, d_z, d_yf, nout, B, H, W,
-              (hipStream_t)hip_stream);
+              (hipStream_t)hip_stream, blocks);
 }
 
 lb_status lbs_wgrad_scratch_floats(int32_t ci, int32_t co, int32_t cir, int32_t cor, int32_t blocks,

@@ -33,7 +33,8 @@ class lb_params(ctypes.Structure):
                 ("T", ctypes.c_double), ("tau", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("N", ctypes.c_double), ("Q", ctypes.c_double), ("U", ctypes.c_double),
                 ("fext_x", ctypes.POINTER(ctypes.c_double)),
-                ("check_every", ctypes.c_int32), ("drift_correct", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("drift_correct", ctypes.c_int32),
+                ("collision", ctypes.c_int32)]
 
 
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -95,7 +96,7 @@ SIGNATURES = {
                                 ctypes.c_int32, _VP, _VP]),
     "lbs_conv": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP, _VP,
                                 _VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                ctypes.c_int32, _VP]),
+                                ctypes.c_int32, ctypes.c_int32, _VP]),
     "lbs_wgrad": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
                                  _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                                  _VP, ctypes.c_int32, _VP, _VP, _VP]),
@@ -168,13 +169,31 @@ def _require(t, dtype, numel: int):
                          f"got {t.dtype} {tuple(t.shape)} on {t.device}")
 
 
+# lb_params.fp32: FP64 populations; FP32 deviations with FP32 arithmetic; FP32
+# deviations with FP64 arithmetic and stochastic rounding of the stored values
+FP64, FP32, FP32_SR = 0, 1, 2
+
+
+def precision(fp32) -> int:
+    """lb_params.fp32 from False / True (FP64 / FP32), 0, 1, 2 or "sr"."""
+    if isinstance(fp32, str):
+        if fp32 != "sr":
+            raise ValueError(f"unknown precision {fp32!r}")
+        return FP32_SR
+    v = int(fp32)
+    if v not in (FP64, FP32, FP32_SR):
+        raise ValueError(f"fp32 must be 0, 1, 2, False, True or 'sr' (got {fp32!r})")
+    return v
+
+
 def make_params(Lx, Ly, T=0.95, tau=1.0, kappa=0.3, N=0.3, Q=2.0, U=0.0, fext=None,
-                y_periodic=False, fp32=False, check_every=0, drift_correct=False):
+                y_periodic=False, fp32=False, check_every=0, drift_correct=False,
+                regularized=False):
     """Fill an lb_params; returns (params, fext array kept alive by the caller)."""
     fx = _host(fext, (Lx,)) if fext is not None else None
-    p = lb_params(int(Lx), int(Ly), int(bool(y_periodic)), int(bool(fp32)), float(T), float(tau),
+    p = lb_params(int(Lx), int(Ly), int(bool(y_periodic)), precision(fp32), float(T), float(tau),
                   float(kappa), float(N), float(Q), float(U), _dptr(fx), int(check_every),
-                  int(bool(drift_correct)))
+                  int(bool(drift_correct)), int(bool(regularized)))
     return p, fx
 
 
@@ -189,12 +208,14 @@ class Lattice:
 
     def __init__(self, Lx, Ly, *, T=0.95, tau=1.0, kappa=0.3, N=0.3, Q=2.0, U=0.0, fext=None,
                  y_periodic=False, fp32=False, check_every=0, drift_correct=False,
-                 device="cuda", stream=None):
+                 regularized=False, device="cuda", stream=None):
         import torch
         lib = load_library()
-        self.Lx, self.Ly, self.fp32 = int(Lx), int(Ly), bool(fp32)
+        self.Lx, self.Ly = int(Lx), int(Ly)
+        self.precision = precision(fp32)
+        self.fp32 = self.precision != FP64  # FP32 storage
         self._p, self._fext = make_params(Lx, Ly, T, tau, kappa, N, Q, U, fext, y_periodic, fp32,
-                                          check_every, drift_correct)
+                                          check_every, drift_correct, regularized)
         nbytes = ctypes.c_size_t()
         _check(lib.lb_workspace_bytes(ctypes.byref(self._p), ctypes.byref(nbytes)))
         self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)
@@ -303,11 +324,11 @@ class Batch:
     """Many independent lattices advanced together (lb_batch_*).
 
     instances: list of dicts with the keyword arguments of Lattice (Lx, Ly,
-    T, tau, kappa, N, Q, U, fext, y_periodic); fp32, check_every and
-    drift_correct are shared by all instances."""
+    T, tau, kappa, N, Q, U, fext, y_periodic); fp32, check_every,
+    drift_correct and regularized are shared by all instances."""
 
     def __init__(self, instances, *, fp32=True, check_every=0, drift_correct=False,
-                 device="cuda", stream=None):
+                 regularized=False, device="cuda", stream=None):
         import torch
         lib = load_library()
         self.count = len(instances)
@@ -318,7 +339,7 @@ class Batch:
             kw = dict(kw)
             Lx, Ly = kw.pop("Lx"), kw.pop("Ly")
             p, fx = make_params(Lx, Ly, fp32=fp32, check_every=check_every,
-                                drift_correct=drift_correct, **kw)
+                                drift_correct=drift_correct, regularized=regularized, **kw)
             arr[i] = p
             self._fext.append(fx)
             self.shapes.append((int(Ly), int(Lx)))

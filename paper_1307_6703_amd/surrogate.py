@@ -193,9 +193,9 @@ def pack(w, cir, cor, CI, CO, transposed=False):
     return out
 
 
-def conv(mode, ci, co, x, wpack, bias=None, res=None, zprev=None, want_z=False, nout=0):
+def conv(mode, ci, co, x, wpack, bias=None, res=None, zprev=None, want_z=False, nout=0, blocks=0):
     """One convolution (lbs_conv). Returns (y, z) for modes 0, 1, 3 and the
-    FP32 output for mode 2."""
+    FP32 output for mode 2. blocks > 0 caps the persistent grid."""
     import torch
     B, H, W, _ = x.shape
     y = z = yf = None
@@ -206,7 +206,8 @@ def conv(mode, ci, co, x, wpack, bias=None, res=None, zprev=None, want_z=False, 
         if want_z:
             z = torch.empty_like(y)
     _check(load_library().lbs_conv(mode, ci, co, _vp(x), _vp(wpack), _vp(bias), _vp(res), _vp(zprev),
-                               _vp(y), _vp(z), _vp(yf), int(nout), B, H, W, _stream()))
+                               _vp(y), _vp(z), _vp(yf), int(nout), B, H, W, int(blocks),
+                               _stream()))
     return yf if mode == FWD_OUT else (y, z)
 
 

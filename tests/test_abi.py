@@ -130,9 +130,9 @@ def test_surrogate_sizes_and_validation(lib):
     assert b_inf.value >= 2 * act and b_tr.value >= 14 * act
     assert lib.lbs_workspace_bytes(0, 128, 256, 0, ctypes.byref(b_inf)) == lbvdw.LB_EINVAL
     # unsupported channel pair and bad mode are rejected before any launch
-    st = lib.lbs_conv(0, 8, 32, None, None, None, None, None, None, None, None, 0, 1, 4, 4, None)
+    st = lib.lbs_conv(0, 8, 32, None, None, None, None, None, None, None, None, 0, 1, 4, 4, 0, None)
     assert st == lbvdw.LB_EINVAL and "channel pair" in lib.lb_last_error().decode()
-    st = lib.lbs_conv(7, 8, 48, None, None, None, None, None, None, None, None, 0, 1, 4, 4, None)
+    st = lib.lbs_conv(7, 8, 48, None, None, None, None, None, None, None, None, 0, 1, 4, 4, 0, None)
     assert st == lbvdw.LB_EINVAL and "mode" in lib.lb_last_error().decode()
     st = lib.lbs_wgrad(16, 48, 16, 48, None, None, 1, 4, 4, 1.0, None, 1, None, None, None)
     assert st == lbvdw.LB_EINVAL

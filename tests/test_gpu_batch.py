@@ -49,19 +49,19 @@ def _single(inst, fp32, steps, check_every=0, drift=False, launch=None):
     return g
 
 
-@pytest.mark.parametrize("fp32", [True, False])
+@pytest.mark.parametrize("fp32", [True, False, "sr"])
 def test_batch_equals_single_runs_bitwise(torch_cuda, fp32):
     from paper_1307_6703_amd import Batch
     _say("batch vs single", "fp32" if fp32 else "fp64")
     insts = _instances(fp32)
     b = Batch([{k: v for k, v in d.items() if k != "seed"} for d in insts], fp32=fp32,
-              check_every=20, drift_correct=fp32)
+              check_every=20, drift_correct=bool(fp32))
     for i, d in enumerate(insts):
         b.init(i, ls.noisy_density(d["Lx"], d["Ly"], d["seed"]))
     steps = 150  # graph runs of 64 steps, checks every 20, eager tail
     b.step(steps)
     for i, d in enumerate(insts):
-        g = _single(d, fp32, steps, check_every=20, drift=fp32)
+        g = _single(d, fp32, steps, check_every=20, drift=bool(fp32))
         nb, uxb, uyb = b.moments(i)
         n, ux, uy = g.moments()
         assert np.array_equal(nb, n) and np.array_equal(uxb, ux) and np.array_equal(uyb, uy), i

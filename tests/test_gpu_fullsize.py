@@ -32,15 +32,19 @@ def setup():
     return w, n0, fext, o
 
 
-@pytest.mark.parametrize("fp32,tol", [(True, 1e-4), (False, 1e-10)])
+def _key(w, fp32):
+    return f"{w.Lx}x{w.Ly}-{ {True: 'fp32', False: 'fp64', 'sr': 'fp32sr'}[fp32]}-gfx950"
+
+
+@pytest.mark.parametrize("fp32,tol", [(True, 1e-4), (False, 1e-10), ("sr", 1e-4)])
 def test_full_size_parity(setup, fp32, tol):
     import bench
     from paper_1307_6703_amd import Lattice
     w, n0, fext, o = setup
-    _say("full size", w.name, "fp32" if fp32 else "fp64")
+    _say("full size", w.name, fp32)
     g = Lattice(w.Lx, w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, U=w.U, fext=fext,
-                fp32=fp32, check_every=100, drift_correct=fp32)
-    launch = bench.tuned_launch(f"{w.Lx}x{w.Ly}-{'fp32' if fp32 else 'fp64'}-gfx950")
+                fp32=fp32, check_every=100, drift_correct=bool(fp32))
+    launch = bench.tuned_launch(_key(w, fp32))
     if launch:
         g.set_launch(*launch)
     g.init(n0).step(3)
@@ -79,7 +83,7 @@ def _oracle_window(w, n0, fext, x0):
 
 
 @pytest.mark.parametrize("x0", [4000, 20])   # an interior window and one across x = 0
-@pytest.mark.parametrize("fp32,tol", [(True, 1e-4), (False, 1e-10)])
+@pytest.mark.parametrize("fp32,tol", [(True, 1e-4), (False, 1e-10), ("sr", 1e-4)])
 def test_full_size_100_steps_on_exact_windows(fp32, tol, x0):
     import torch
     if not torch.cuda.is_available():
@@ -89,10 +93,10 @@ def test_full_size_100_steps_on_exact_windows(fp32, tol, x0):
     w = ls.ROOFLINE
     n0, fext = w.n0(), w.fext()
     cols, o = _oracle_window(w, n0, fext, x0)
-    _say("full size", w.name, "fp32" if fp32 else "fp64", WINDOW_STEPS, "steps")
+    _say("full size", w.name, fp32, WINDOW_STEPS, "steps")
     g = Lattice(w.Lx, w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, U=w.U, fext=fext,
-                fp32=fp32, check_every=100, drift_correct=fp32)
-    launch = bench.tuned_launch(f"{w.Lx}x{w.Ly}-{'fp32' if fp32 else 'fp64'}-gfx950")
+                fp32=fp32, check_every=100, drift_correct=bool(fp32))
+    launch = bench.tuned_launch(_key(w, fp32))
     if launch:
         g.set_launch(*launch)
     g.init(n0).step(WINDOW_STEPS)

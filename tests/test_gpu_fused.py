@@ -122,6 +122,12 @@ def test_fused_launch_is_validated(torch_cuda):
     with pytest.raises(LBError):
         g.set_launch(128, 0, steps_per_launch=2)  # FP64 storage
     g.close()
+    g = Lattice(64, 16, fp32="sr")
+    with pytest.raises(LBError):
+        g.set_launch(128, 0, steps_per_launch=2)  # FP64 arithmetic, stochastic rounding
+    with pytest.raises(LBError):
+        g.set_launch(512, 0)  # 512-thread strips: FP32 arithmetic only
+    g.close()
     g = _lattice(64, 16, False, seed=1)
     for t in (96, 320, 512):
         with pytest.raises(LBError):

@@ -56,14 +56,13 @@ CONV_CASES = [
 SHAPES = [(2, 9, 80), (1, 5, 40), (1, 4, 64), (3, 1, 130), (1, 3, 1)]
 
 
-@pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("case", CONV_CASES)
-def test_conv_matches_reference(torch_cuda, case, shape):
+def _conv_case(torch, case, shape, blocks=0, sample=None):
+    """Run one layer kernel on seeded bf16-exact data and compare it with the
+    FP64 reference: on every pixel, or (sample = count) on that many seeded
+    pixels computed one by one."""
     from paper_1307_6703_amd import surrogate as sg
-    torch = torch_cuda
     ci, cout, cir, cor, mode = case
     B, H, W = shape
-    _say("conv", case, shape)
     g = _rng(hash((ci, cout, mode, B, H, W)) % 2**32)
     x_d, x = _bf16(torch, g.normal(size=(B, H, W, ci)))
     if mode == 3:
@@ -77,36 +76,72 @@ def test_conv_matches_reference(torch_cuda, case, shape):
     w64 = w.astype(np.float64)
     bias = g.normal(0, 0.1, size=cor).astype(np.float32)
     bias_d = torch.from_numpy(bias).cuda()
+    b64 = bias.astype(np.float64)
+    idx = None
+    if sample:
+        idx = np.stack([g.integers(0, B, sample), g.integers(0, H, sample),
+                        g.integers(0, W, sample)], axis=1)
+    at = (lambda a: a) if idx is None else (lambda a: a[idx[:, 0], idx[:, 1], idx[:, 2]])
+    conv = (lambda xx, ww, bb: co.conv3x3(xx, ww, bb)) if idx is None else \
+        (lambda xx, ww, bb: co.conv3x3_at(xx, ww, bb, idx))
     if mode == 0:
-        y, z = sg.conv(0, ci, cout, x_d, wp, bias_d, want_z=True)
-        v = co.conv3x3(x[..., :cir], w64, bias.astype(np.float64))
+        y, z = sg.conv(0, ci, cout, x_d, wp, bias_d, want_z=True, blocks=blocks)
+        v = conv(x[..., :cir], w64, b64)
         exp_y, exp_z = co.silu(v), v
     elif mode == 1:
         r_d, r = _bf16(torch, g.normal(size=(B, H, W, cout)))
-        y, z = sg.conv(1, ci, cout, x_d, wp, bias_d, res=r_d, want_z=True)
-        v = co.conv3x3(x, w64, bias.astype(np.float64))
-        exp_y, exp_z = r + co.silu(v), v
+        y, z = sg.conv(1, ci, cout, x_d, wp, bias_d, res=r_d, want_z=True, blocks=blocks)
+        v = conv(x, w64, b64)
+        exp_y, exp_z = at(r) + co.silu(v), v
     elif mode == 2:
-        yf = sg.conv(2, ci, cout, x_d, wp, bias_d, nout=cor)
+        yf = sg.conv(2, ci, cout, x_d, wp, bias_d, nout=cor, blocks=blocks)
         torch.cuda.synchronize()
-        exp = co.conv3x3(x, w64, bias.astype(np.float64))
-        got = _f64(yf)
+        exp = conv(x, w64, b64)
+        got = at(_f64(yf))
         assert got.shape == exp.shape
         assert np.max(np.abs(got - exp)) <= 1e-5 * np.max(np.abs(exp))
         return
     else:
         r_d, r = _bf16(torch, g.normal(size=(B, H, W, cout)))
         zp_d, zp = _bf16(torch, g.normal(size=(B, H, W, cout)))
-        y, z = sg.conv(3, ci, cout, x_d, wp, None, res=r_d, zprev=zp_d, want_z=True)
-        gsum = co.conv3x3_dgrad(x[..., :cor], w64) + r
-        exp_y, exp_z = gsum * co.silu_grad(zp), gsum
+        y, z = sg.conv(3, ci, cout, x_d, wp, None, res=r_d, zprev=zp_d, want_z=True, blocks=blocks)
+        dg = co.conv3x3_dgrad(x[..., :cor], w64) if idx is None else \
+            co.conv3x3_dgrad_at(x[..., :cor], w64, idx)
+        gsum = dg + at(r)
+        exp_y, exp_z = gsum * co.silu_grad(at(zp)), gsum
     torch.cuda.synchronize()
     for got_t, exp in ((y, exp_y), (z, exp_z)):
-        got = _f64(got_t)
+        got = at(_f64(got_t))
         scale = np.max(np.abs(exp))
         # bf16 output: half an ulp of rounding (2^-9 relative) plus FP32 accumulation
         assert np.all(np.abs(got - exp) <= 2.0 ** -8 * np.abs(exp) + 1e-5 * scale), \
             np.max(np.abs(got - exp) - 2.0 ** -8 * np.abs(exp))
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("case", CONV_CASES)
+def test_conv_matches_reference(torch_cuda, case, shape):
+    _say("conv", case, shape)
+    _conv_case(torch_cuda, case, shape)
+
+
+# Images of 16 tiles or more (8-row x 64-column tiles, ragged in both
+# directions) on grids of 1-3 workgroups: every workgroup walks several tiles,
+# so the next-tile prefetch and the reuse of the LDS tile run under the check.
+@pytest.mark.parametrize("blocks", [1, 2, 3])
+@pytest.mark.parametrize("shape", [(2, 17, 130), (1, 32, 256)])
+@pytest.mark.parametrize("case", CONV_CASES)
+def test_conv_multi_tile_walk(torch_cuda, case, shape, blocks):
+    _say("conv walk", case, shape, blocks)
+    _conv_case(torch_cuda, case, shape, blocks=blocks)
+
+
+# Full size (8 lattices of 128 x 256, 512 tiles) in the default persistent
+# grid, checked on 2048 seeded pixels computed one by one.
+@pytest.mark.parametrize("case", CONV_CASES)
+def test_conv_full_size_sampled(torch_cuda, case):
+    _say("conv full size", case)
+    _conv_case(torch_cuda, case, (8, 128, 256), sample=2048)
 
 
 def test_pack_layout_is_bitwise(torch_cuda):
@@ -267,6 +302,31 @@ def test_network_forward_and_gradients(torch_cuda):
     e1, _, _ = co.adam_step(p.astype(np.float64), grads, np.zeros_like(grads), np.zeros_like(grads), 1,
                             lr=1e-3)
     assert np.allclose(p1, e1, rtol=1e-5, atol=1e-7)
+    net.close()
+
+
+def test_network_forward_full_size_sampled(torch_cuda):
+    # 8 lattices of 128 x 256 (the evaluation's image size) in the default
+    # launch; 512 seeded pixels against the FP64 network run on each pixel's
+    # receptive field only
+    from paper_1307_6703_amd import surrogate as sg
+    torch = torch_cuda
+    _say("network forward full size")
+    g = _rng(22)
+    B, H, W = 8, 128, 256
+    p = _bf16_params(torch, g)
+    net = sg.Net(B, H, W, train=False)
+    net.set_params(p)
+    x_d, x = _bf16(torch, g.normal(size=(B, H, W, 8)))
+    out = _f64(net.forward(x_d))
+    idx = np.stack([g.integers(0, B, 512), g.integers(0, H, 512), g.integers(0, W, 512)], axis=1)
+    # rows next to the walls are among them
+    idx[:8, 1] = [0, 1, 2, H - 1, H - 2, H - 3, 0, H - 1]
+    exp = co.forward_at(sg.split_params(p), x[..., :6], idx)
+    got = out[idx[:, 0], idx[:, 1], idx[:, 2]]
+    # bf16 activations between the layers: a few parts in 1e3
+    assert np.max(np.abs(got - exp)) <= 2e-2 * np.max(np.abs(exp))
+    assert np.linalg.norm(got - exp) <= 1e-2 * np.linalg.norm(exp)
     net.close()
 
 

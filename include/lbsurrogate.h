@@ -144,6 +144,19 @@ lb_status lbs_wgrad(int32_t ci, int32_t co, int32_t cir, int32_t cor, const void
                     const void* d_gz, int32_t B, int32_t H, int32_t W, float scale, float* d_part,
                     int32_t blocks, float* d_dw, float* d_db, void* hip_stream);
 
+/* lbs_wgrad without a caller scratch, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, kernels and results as lbs_wgrad, with
+ * the per-workgroup partial sums in a static device array of 4 Mi floats
+ * (16 MiB, one per GPU, held until the process ends). LB_EINVAL when
+ * lbs_wgrad_scratch_floats(ci, co, cir, cor, blocks) exceeds it (for
+ * (48, 48, 48, 48), blocks <= 169). The call allocates nothing. Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams or threads) race and must be serialised by the caller. */
+lb_status lbs_wgrad_noalloc(int32_t ci, int32_t co, int32_t cir, int32_t cor, const void* d_x,
+                            const void* d_gz, int32_t B, int32_t H, int32_t W, float scale,
+                            int32_t blocks, float* d_dw, float* d_db, void* hip_stream);
+
 /* Bias gradient db[c] = scale * sum_p gz[p][c] for c < nreal; gz [npix][C]
  * bf16, C <= 64; d_part: 1024 C FP32 of scratch. */
 lb_status lbs_bias_grad(const void* d_gz, int64_t npix, int32_t C, int32_t nreal, float scale,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 
 #include "lb_host.h"
 #include "lbsurrogate.h"
@@ -449,6 +450,63 @@ lb_status lbs_wgrad(int32_t ci, int32_t co, int32_t cir, int32_t cor, const void
   if (blocks < 1 || blocks > 4096) return fail(LB_EINVAL, "blocks must be in [1, 4096]");
   if ((uintptr_t)d_part % 4) return fail(LB_EINVAL, "d_part must be 4-byte aligned");
   return wgrad(ci, co, cir, cor, d_x, d_gz, B, H, W, scale, d_part, blocks, d_dw, d_db,
+               (hipStream_t)hip_stream);
+}
+
+}  // extern "C"
+
+// Scratch of lbs_wgrad_noalloc: a file-scope device array, one copy per GPU,
+// held until the process ends. Its name is a host-side stand-in in host code:
+// kernels get the device address that hipGetSymbolAddress returns, looked up
+// once per device with that device current.
+constexpr int64_t kNoallocScratchFloats = (int64_t)4 << 20;  // 16 MiB
+static __device__ __align__(256) float scratch[kNoallocScratchFloats];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+lb_status scratch_of_current_device(float** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(LB_EDEVICE, "device ordinal %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LB_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = (float*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LB_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lb_status lbs_wgrad_noalloc(int32_t ci, int32_t co, int32_t cir, int32_t cor, const void* d_x,
+                            const void* d_gz, int32_t B, int32_t H, int32_t W, float scale,
+                            int32_t blocks, float* d_dw, float* d_db, void* hip_stream) {
+  if (!wgrad_supported(ci, co)) return fail(LB_EINVAL, "unsupported channel pair (%d, %d)", ci, co);
+  if (cir < 1 || cir > ci || cor < 1 || cor > co) return fail(LB_EINVAL, "need 1 <= cir <= ci, 1 <= cor <= co");
+  lb_status r = check_image(B, H, W);
+  if (r != LB_OK) return r;
+  if (!d_x || !d_gz || !d_dw) return fail(LB_EINVAL, "NULL argument");
+  if (!aligned16(d_x) || !aligned16(d_gz)) return fail(LB_EINVAL, "x and gz must be 16-byte aligned");
+  if (blocks < 1 || blocks > 4096) return fail(LB_EINVAL, "blocks must be in [1, 4096]");
+  const int64_t need = wgrad_scratch_floats(ci, co, cir, cor, blocks);
+  if (need > kNoallocScratchFloats)
+    return fail(LB_EINVAL,
+                "blocks = %d needs %lld scratch floats; the static scratch holds %lld: use fewer "
+                "blocks or lbs_wgrad with a caller workspace", blocks, (long long)need,
+                (long long)kNoallocScratchFloats);
+  float* part = nullptr;
+  if ((r = scratch_of_current_device(&part)) != LB_OK) return r;
+  // every workgroup writes its whole partial block before the reduction
+  // reads it, so nothing needs clearing
+  return wgrad(ci, co, cir, cor, d_x, d_gz, B, H, W, scale, part, blocks, d_dw, d_db,
                (hipStream_t)hip_stream);
 }
 

@@ -103,6 +103,10 @@ SIGNATURES = {
     "lbs_wgrad_scratch_floats": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_int64)]),
+    "lbs_wgrad_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, _VP, _VP, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_float, ctypes.c_int32, _VP, _VP,
+                                         _VP]),
     "lbs_bias_grad": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_float, _VP, _VP, _VP]),
     "lbs_mse": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _VP, _VP,

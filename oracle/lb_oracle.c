@@ -192,6 +192,16 @@ void lbo_apply_stencils(const lbo_params *p, const double *phi, double par,
     }
 }
 
+/* D = div(n u*) of Eq.(coeff) with the gradient stencil, as the step uses
+ * it: the ghost of j*_x is even and that of j*_y odd at the walls (reading of
+ * the neutral-wetting mirror for a y-component). */
+void lbo_divergence(const lbo_params *p, const double *jx, const double *jy,
+                    double *D) {
+  for (int y = 0; y < p->Ly; y++)
+    for (int x = 0; x < p->Lx; x++)
+      D[(size_t)y * p->Lx + x] = grad_x(jx, p, x, y, 1) + grad_y(jy, p, x, y, -1);
+}
+
 /* ---------------------------------------------------------------------- */
 /* Initial state and one time step.                                        */
 /* ---------------------------------------------------------------------- */
@@ -233,8 +243,9 @@ int lbo_step(const lbo_params *p, const double *fext, const double *S_in,
   double *Fy = malloc(nn * sizeof(double));
   double *jx = malloc(nn * sizeof(double));
   double *jy = malloc(nn * sizeof(double));
-  if (!f || !n || !L || !P || !Fx || !Fy || !jx || !jy) {
-    free(f); free(n); free(L); free(P); free(Fx); free(Fy); free(jx); free(jy);
+  double *Dv = malloc(nn * sizeof(double));
+  if (!f || !n || !L || !P || !Fx || !Fy || !jx || !jy || !Dv) {
+    free(f); free(n); free(L); free(P); free(Fx); free(Fy); free(jx); free(jy); free(Dv);
     return -1;
   }
 
@@ -342,6 +353,8 @@ int lbo_step(const lbo_params *p, const double *fext, const double *S_in,
       jy[k] = sy + 0.5 * Fy[k];
     }
 
+  lbo_divergence(p, jx, jy, Dv);
+
   /* 9-12. Per node: grad n and D = div(n u*) with the same stencil (ghosts:
    *       n and jx even, jy odd), equilibrium, forcing, BGK collision
    *       (Eq.(evoleq)) on all nodes including the walls; with collision = 1
@@ -355,7 +368,7 @@ int lbo_step(const lbo_params *p, const double *fext, const double *S_in,
       double nk = n[k];
       double ux = jx[k] / nk, uy = jy[k] / nk;
       double dnx = grad_x(n, p, x, y, 1), dny = grad_y(n, p, x, y, 1);
-      double D = grad_x(jx, p, x, y, 1) + grad_y(jy, p, x, y, -1);
+      double D = Dv[k];
       double fe[9], fo[9];
       lbo_feq(nk, ux, uy, T, fe);
       lbo_forcing(ux, uy, Fx[k], Fy[k], dnx, dny, D, T, tau_l, fo);
@@ -375,7 +388,7 @@ int lbo_step(const lbo_params *p, const double *fext, const double *S_in,
     }
 #undef Fv
 
-  free(f); free(n); free(L); free(P); free(Fx); free(Fy); free(jx); free(jy);
+  free(f); free(n); free(L); free(P); free(Fx); free(Fy); free(jx); free(jy); free(Dv);
   return 0;
 }
 

@@ -52,6 +52,7 @@ def _lib():
         lib.lbo_pressure_term.argtypes = [ctypes.c_double, ctypes.c_double]
         lib.lbo_pressure_term.restype = ctypes.c_double
         lib.lbo_apply_stencils.argtypes = [pp, dp, ctypes.c_double, dp, dp, dp]
+        lib.lbo_divergence.argtypes = [pp, dp, dp, dp]
         lib.lbo_init.argtypes = [pp, dp, dp, dp, dp]
         lib.lbo_step.argtypes = [pp, dp, dp, dp, dp, dp, dp]
         lib.lbo_step.restype = ctypes.c_int
@@ -125,6 +126,16 @@ def stencils(p: Params, phi: np.ndarray, parity: float = 1.0):
     c = p.c()
     _lib().lbo_apply_stencils(ctypes.byref(c), _ptr(phi), parity, _ptr(gx), _ptr(gy), _ptr(lap))
     return gx, gy, lap
+
+
+def divergence(p: Params, jx: np.ndarray, jy: np.ndarray) -> np.ndarray:
+    """D = div(j*) of a [Ly, Lx] momentum field as the step computes it."""
+    jx = np.ascontiguousarray(jx, dtype=np.float64)
+    jy = np.ascontiguousarray(jy, dtype=np.float64)
+    D = np.zeros_like(jx)
+    c = p.c()
+    _lib().lbo_divergence(ctypes.byref(c), _ptr(jx), _ptr(jy), _ptr(D))
+    return D
 
 
 class OracleLB:

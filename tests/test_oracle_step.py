@@ -157,6 +157,27 @@ def test_flat_interface_approaches_maxwell():
     assert rel[2] < 1e-2
 
 
+def test_flat_interface_converges_with_kappa():
+    # Sec. III: the scheme's coexistence densities differ from the Maxwell
+    # values by a discretisation error of the interface, which shrinks as the
+    # interface widens (width ~ sqrt(kappa)). At T = 0.95 with the (0.3, 2.0)
+    # stencil the planar interface stays stable up to kappa ~ 0.7; doubling
+    # kappa from 0.3 to 0.6 cuts both errors by a third or more.
+    import math
+    T = 0.95
+    nl, nv, _ = cf.maxwell(T)
+    err = []
+    for kappa in (0.3, 0.6):
+        Lx = 240
+        w = 0.5 * math.sqrt(2 * kappa / (1 / T - 1))
+        p = Params(Lx, 4, T=T, kappa=kappa, N=0.3, Q=2.0, y_periodic=True)
+        o = OracleLB(p, ls.flat_interface(Lx, 4, nv, nl, axis="x", width=w))
+        o.run(60000, threads=8)
+        err.append((abs(o.n[0, Lx // 2] - nl), abs(o.n[0, 0] - nv)))
+    assert err[1][0] < err[0][0] / 1.3 and err[1][1] < err[0][1] / 1.3
+    assert err[1][0] < 1e-2  # the liquid side within the gate at kappa = 0.6
+
+
 def test_maxwell_matches_printed_values():
     # Caption of Fig. 4: n_L_th = 1.461727, n_V_th = 0.579015 at T = 0.95.
     rows = np.loadtxt(os.path.join(GOLDEN, "maxwell_T095.txt"))
@@ -290,3 +311,44 @@ def test_window_runs_are_exact_inside_the_dependency_cone():
         assert np.array_equal(a[:, keep], b[:, cols[keep]])
     # the cut edges do differ: the window is not trivially equal
     assert np.abs(win.n[:, :5] - full.n[:, cols[:5]]).max() > 1e-6
+
+
+@pytest.mark.parametrize("T", [1.2, 0.95])
+def test_wall_ghost_of_jy_follows_continuity(T):
+    # Reading c10: at the walls the stencils see a mirror image of the field,
+    # even for scalars and x-components, odd for y-components. For D = div j*
+    # of Eq.(coeff) the choice for j*_y decides whether D feels the flux
+    # between the wall row and the next: by Eq.(conteqn) D must track
+    # -dn/dt there. A density wave bouncing between walls at rest (single
+    # phase at T = 1.2, two-phase quench at 0.95): the oracle's D (odd ghost)
+    # follows -dn/dt at the wall nodes with the sign and scale of the flux;
+    # an even ghost would give D = 0 there whatever the flux.
+    from oracle.lb_oracle import divergence, stencils
+    Ly, Lx = 32, 4
+    p = Params(Lx, Ly, T=T, N=0.3, Q=2.0, U=0.0)
+    y = np.arange(Ly)[:, None]
+    n0 = (0.6 + 0.02 * np.cos(2 * math.pi * y / (Ly - 1)) + 0.01 * np.sin(math.pi * y / (Ly - 1))
+          ) * np.ones((1, Lx))
+    o = OracleLB(p, n0)
+    ns, js = [], []
+    for _ in range(60):
+        o.run(1)
+        ns.append(o.n.copy())
+        js.append((o.n * o.ux, o.n * o.uy))
+    wall, interior, even = [], [], []
+    for t in range(1, 59):
+        dndt = (ns[t + 1] - ns[t - 1]) / 2
+        D = divergence(p, *js[t])
+        wall.append(np.stack([D[[0, Ly - 1]].ravel(), -dndt[[0, Ly - 1]].ravel()]))
+        interior.append(np.stack([D[5:-5].ravel(), -dndt[5:-5].ravel()]))
+        gx, _, _ = stencils(p, js[t][0], 1.0)
+        _, gy, _ = stencils(p, js[t][1], 1.0)
+        even.append((gx + gy)[[0, Ly - 1]].ravel())
+    for A, corr_min, lo, hi in ((np.concatenate(interior, 1), 0.9999, 0.98, 1.02),
+                                (np.concatenate(wall, 1), 0.98, 0.5, 2.0)):
+        d, m = A
+        assert np.corrcoef(d, m)[0, 1] >= corr_min
+        assert lo <= (d @ m) / (m @ m) <= hi
+    w = np.concatenate(wall, 1)
+    assert np.abs(w[1]).max() > 1e-5                      # there is a flux to see
+    assert np.abs(np.concatenate(even)).max() < 1e-15     # the even ghost cannot see it

@@ -99,77 +99,72 @@ __device__ __forceinline__ Sten<R> make_sten(const Desc& d, int dir) {
 //   geq_i = w^_i dn + w_i n [3 c.u + 9/2 (c.u)^2 - 3/2 u^2],
 //   F_i   = w_i s [3 c.F + X:(3 c c - I)/2],  s = 1 - omega/2,
 //   X = 3 (u F + F u) + (1 - T)(u grad n + grad n u + D I).
-// Opposite directions share the even part (sym) and flip the odd part
-// (asym); omega n (c.u) is written omega (c.j) with j = n u.
+// Both are expansions in the same Hermite polynomials, so omega geq_i + F_i
+// = omega w^_i dn + w_i [3 B.c_i + 9/2 A:(c_i c_i - I/3)] with
+//   B = omega j + s F,   A = omega n u u + (s/3) X,
+// j = n u. Per direction pair the even part comes from A (and dn), the odd
+// part from B.
 template <typename R>
 struct Coll {
-  R keep, om, oneT, s3;      // 1 - omega, omega, 1 - T, 3 s
+  R keep, om, s;             // 1 - omega, omega, s
+  R k1, k2, k3;              // 2 s, 2 s (1 - T)/3, s (1 - T)/3
   R owr0, owra, owrd;        // omega w^_i
-  R wr0, wra, wrd;           // w^_i
-  R w0, wa, wd;              // w_i
-  R w0s, was, wds;           // w_i s
+  R w0t15, wa3, wa15, wd3, wd9;  // 3/2 w_0, 3 w_a, 3/2 w_a, 3 w_d, 9 w_d
 };
 
 template <typename R>
 __device__ __forceinline__ Coll<R> make_coll(const Desc& d) {
   Coll<R> c;
-  const double om = d.omega, s = 1.0 - 0.5 * d.omega;
+  const double om = d.omega, s = 1.0 - 0.5 * d.omega, oneT = 1.0 - d.T;
   c.keep = (R)(1.0 - om);
   c.om = (R)om;
-  c.oneT = (R)(1.0 - d.T);
-  c.s3 = (R)(3.0 * s);
+  c.s = (R)s;
+  c.k1 = (R)(2.0 * s);
+  c.k2 = (R)(2.0 / 3.0 * s * oneT);
+  c.k3 = (R)(s / 3.0 * oneT);
   c.owr0 = (R)(om * rest_weight_hd(0, d.T));
   c.owra = (R)(om * rest_weight_hd(1, d.T));
   c.owrd = (R)(om * rest_weight_hd(5, d.T));
-  c.wr0 = (R)rest_weight_hd(0, d.T);
-  c.wra = (R)rest_weight_hd(1, d.T);
-  c.wrd = (R)rest_weight_hd(5, d.T);
-  c.w0 = (R)(4.0 / 9.0);
-  c.wa = (R)(1.0 / 9.0);
-  c.wd = (R)(1.0 / 36.0);
-  c.w0s = (R)(4.0 / 9.0 * s);
-  c.was = (R)(1.0 / 9.0 * s);
-  c.wds = (R)(1.0 / 36.0 * s);
+  c.w0t15 = (R)(1.5 * 4.0 / 9.0);
+  c.wa3 = (R)(3.0 / 9.0);
+  c.wa15 = (R)(1.5 / 9.0);
+  c.wd3 = (R)(3.0 / 36.0);
+  c.wd9 = (R)(9.0 / 36.0);
   return c;
 }
 
+// A_xx = u_x (omega n u_x + 2 s F_x + 2 s (1-T)/3 dn_x) + s (1-T)/3 D, and
+// so on; the even part of direction i is w_i [9/2 A:c c - 3/2 tr A].
 template <typename R>
 __device__ __forceinline__ void collide(R g[9], const Coll<R>& c, R n, R dn, R jx, R jy, R rn,
                                         R Fx, R Fy, R dnx, R dny, R D) {
   const R ux = jx * rn, uy = jy * rn;
-  const R usq = (R)1.5 * (ux * ux + uy * uy);
-  const R Xxx = (R)6 * ux * Fx + c.oneT * ((R)2 * ux * dnx + D);
-  const R Xyy = (R)6 * uy * Fy + c.oneT * ((R)2 * uy * dny + D);
-  const R Xxy = (R)3 * (ux * Fy + uy * Fx) + c.oneT * (ux * dny + uy * dnx);
   const R on = c.om * n;
-  const R ojx = c.om * jx, ojy = c.om * jy;
-  const R trX = Xxx + Xyy;
-  g[0] = c.keep * g[0] + (c.owr0 * dn - c.w0 * (on * usq) - c.w0s * ((R)0.5 * trX));
+  const R Axx = ux * (on * ux + c.k1 * Fx + c.k2 * dnx) + c.k3 * D;
+  const R Ayy = uy * (on * uy + c.k1 * Fy + c.k2 * dny) + c.k3 * D;
+  const R Axy = ux * (on * uy + c.s * Fy + c.k3 * dny) + uy * (c.s * Fx + c.k3 * dnx);
+  const R Bx = c.om * jx + c.s * Fx, By = c.om * jy + c.s * Fy;
+  const R tr = Axx + Ayy;
+  const R da = c.owra * dn, dd = c.owrd * dn;
+  g[0] = c.keep * g[0] + (c.owr0 * dn - c.w0t15 * tr);
   {
-    const R es = c.owra * dn + c.wa * (on * ((R)4.5 * ux * ux - usq)) + c.was * (Xxx - (R)0.5 * Xyy);
-    const R ea = (R)3 * c.wa * ojx + c.wa * c.s3 * Fx;
+    const R es = da + c.wa3 * Axx - c.wa15 * Ayy, ea = c.wa3 * Bx;
     g[1] = c.keep * g[1] + (es + ea);
     g[3] = c.keep * g[3] + (es - ea);
   }
   {
-    const R es = c.owra * dn + c.wa * (on * ((R)4.5 * uy * uy - usq)) + c.was * (Xyy - (R)0.5 * Xxx);
-    const R ea = (R)3 * c.wa * ojy + c.wa * c.s3 * Fy;
+    const R es = da + c.wa3 * Ayy - c.wa15 * Axx, ea = c.wa3 * By;
     g[2] = c.keep * g[2] + (es + ea);
     g[4] = c.keep * g[4] + (es - ea);
   }
   {
-    const R cu = ux + uy;
-    const R es = c.owrd * dn + c.wd * (on * ((R)4.5 * cu * cu - usq)) + c.wds * (trX + (R)3 * Xxy);
-    const R ea = (R)3 * c.wd * (ojx + ojy) + c.wd * c.s3 * (Fx + Fy);
-    g[5] = c.keep * g[5] + (es + ea);
-    g[7] = c.keep * g[7] + (es - ea);
-  }
-  {
-    const R cu = uy - ux;
-    const R es = c.owrd * dn + c.wd * (on * ((R)4.5 * cu * cu - usq)) + c.wds * (trX - (R)3 * Xxy);
-    const R ea = (R)3 * c.wd * (ojy - ojx) + c.wd * c.s3 * (Fy - Fx);
-    g[6] = c.keep * g[6] + (es + ea);
-    g[8] = c.keep * g[8] + (es - ea);
+    const R t = dd + c.wd3 * tr, x = c.wd9 * Axy;
+    const R e5 = t + x, e6 = t - x;
+    const R a5 = c.wd3 * (Bx + By), a6 = c.wd3 * (By - Bx);
+    g[5] = c.keep * g[5] + (e5 + a5);
+    g[7] = c.keep * g[7] + (e5 - a5);
+    g[6] = c.keep * g[6] + (e6 + a6);
+    g[8] = c.keep * g[8] + (e6 - a6);
   }
 }
 
@@ -362,12 +357,13 @@ __device__ __forceinline__ void stage_grad(const R* nb, const R* n0, const R* na
   const R nd1 = na[u + 1] - nb[u - 1], nd2 = nb[u + 1] - na[u - 1];
   dnx = c.N * (n0[u + 1] - n0[u - 1]) + c.M * (nd1 + nd2);
   dny = c.Ny * (na[u] - nb[u]) + c.My * (nd1 - nd2);
-  const Pair<R> aE = {Ja[u + 1].jx, sa * Ja[u + 1].jy}, aW = {Ja[u - 1].jx, sa * Ja[u - 1].jy};
-  const Pair<R> bE = {Jb[u + 1].jx, sb * Jb[u + 1].jy}, bW = {Jb[u - 1].jx, sb * Jb[u - 1].jy};
-  const R aCy = sa * Ja[u].jy, bCy = sb * Jb[u].jy;
+  // the y-derivative of j*_y as sa Ta - sb Tb: the rows ahead and behind
+  // each carry their mirror sign once
+  const R Ta = c.Ny * Ja[u].jy + c.My * (Ja[u + 1].jy + Ja[u - 1].jy);
+  const R Tb = c.Ny * Jb[u].jy + c.My * (Jb[u + 1].jy + Jb[u - 1].jy);
   const R mEx = J0[u + 1].jx, mWx = J0[u - 1].jx;
-  D = c.N * (mEx - mWx) + c.M * ((aE.x - aW.x) + (bE.x - bW.x)) + c.Ny * (aCy - bCy) +
-      c.My * ((aE.y - bE.y) + (aW.y - bW.y));
+  D = c.N * (mEx - mWx) + c.M * ((Ja[u + 1].jx - Ja[u - 1].jx) + (Jb[u + 1].jx - Jb[u - 1].jx)) +
+      (sa * Ta - sb * Tb);
 }
 
 // Moving-wall rule (Sec. II) for the populations of a wall node whose source
@@ -808,9 +804,37 @@ __device__ __forceinline__ float round_stochastic(double v, uint32_t q) {
 // polynomials of order <= 2 before it relaxes,
 //   g_i <- geq_i + (1 - omega) P[h]_i + F_i,
 //   P[h]_i = w_i [a0 + 3 a1.c_i + 9/2 a2 : (c_i c_i - I/3)],
-// a0 = sum h, a1 = sum h c, a2 = sum h (c c - I/3); geq and F as in collide.
+// a0 = sum h, a1 = sum h c, a2 = sum h (c c - I/3); geq and F as in collide,
+// formed separately here.
 template <typename R>
-__device__ __forceinline__ void collide_reg(R g[9], const Coll<R>& c, R n, R dn, R jx, R jy,
+struct CollReg {
+  R keep, oneT, s3;          // 1 - omega, 1 - T, 3 s
+  R wr0, wra, wrd;           // w^_i
+  R w0, wa, wd;              // w_i
+  R w0s, was, wds;           // w_i s
+};
+
+template <typename R>
+__device__ __forceinline__ CollReg<R> make_coll_reg(const Desc& d) {
+  CollReg<R> c;
+  const double s = 1.0 - 0.5 * d.omega;
+  c.keep = (R)(1.0 - d.omega);
+  c.oneT = (R)(1.0 - d.T);
+  c.s3 = (R)(3.0 * s);
+  c.wr0 = (R)rest_weight_hd(0, d.T);
+  c.wra = (R)rest_weight_hd(1, d.T);
+  c.wrd = (R)rest_weight_hd(5, d.T);
+  c.w0 = (R)(4.0 / 9.0);
+  c.wa = (R)(1.0 / 9.0);
+  c.wd = (R)(1.0 / 36.0);
+  c.w0s = (R)(4.0 / 9.0 * s);
+  c.was = (R)(1.0 / 9.0 * s);
+  c.wds = (R)(1.0 / 36.0 * s);
+  return c;
+}
+
+template <typename R>
+__device__ __forceinline__ void collide_reg(R g[9], const CollReg<R>& c, R n, R dn, R jx, R jy,
                                             R rn, R Fx, R Fy, R dnx, R dny, R D) {
   const R ux = jx * rn, uy = jy * rn;
   const R usq = (R)1.5 * (ux * ux + uy * uy);
@@ -916,6 +940,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
   const __amdgpu_buffer_rsrc_t Snone = make_rsrc(d.S[parity ^ 1], 0);  // drops every access
   const R* __restrict__ fext3 = (const R*)d.fext3;
   const Coll<R> cl = make_coll<R>(d);
+  const CollReg<R> clr = make_coll_reg<R>(d);
   const Sten<R> c = make_sten<R>(d, dir);
   // Stochastic rounding: this launch's step number comes from the counter of
   // the buffer it reads; the workgroup of the lattice's first tile writes the
@@ -1041,7 +1066,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
         const int wall = periodic ? 0 : (dd == 0 ? 1 : (dd == Ly - 1 ? 2 : 0));
         stage_wall<R>(g, wall, dn, n, mC.Fx, mC.Fy, c);
         if constexpr (REG)
-          collide_reg<R>(g, cl, n, dn, mC.jx, mC.jy, rn, mC.Fx, mC.Fy, dnx, dny, D);
+          collide_reg<R>(g, clr, n, dn, mC.jx, mC.jy, rn, mC.Fx, mC.Fy, dnx, dny, D);
         else
           collide<R>(g, cl, n, dn, mC.jx, mC.jy, rn, mC.Fx, mC.Fy, dnx, dny, D);
       }

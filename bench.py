@@ -405,8 +405,8 @@ def main():
                      "note": ("two steps per launch: achieved counts 72 B per node update, times "
                               "the launch's two updates per node (the scope's algorithmic bytes), "
                               "an effective rate; the populations cross HBM once per launch "
-                              "(hbm_gbs_min, hbm_gbs_measured), and the kernel is bound by "
-                              "instruction issue at two waves per SIMD" if spl == 2 else
+                              "(hbm_gbs_min, hbm_gbs_measured); the launch takes as long as its "
+                              "strips' memory access pattern, not HBM bandwidth or arithmetic" if spl == 2 else
                               "one step per launch: HBM-bound streaming of the populations"),
                      "copy_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},

@@ -289,11 +289,27 @@ lb_status lbs_forward(lbs_net* n, int32_t B, const void* d_x, float* d_out) {
                 bias_of(n, 0), nullptr, nullptr, buf[0], nullptr, nullptr, 0, B, H, W, n->st)) != LB_OK)
     return r;
   int cur = 0;
-  for (int l = 1; l <= LBS_BLOCKS; ++l) {
-    if ((r = conv(sg::FWD_RES, LBS_WIDTH, LBS_WIDTH, buf[cur], n->at<void>(n->L.wf[l]), bias_of(n, l),
-                  buf[cur], nullptr, buf[cur ^ 1], nullptr, nullptr, 0, B, H, W, n->st)) != LB_OK)
-      return r;
-    cur ^= 1;
+  if (LBS_BLOCKS == 4 && W % sg::SK_ST == 0) {
+    // the four residual layers in one pass, activations kept on chip
+    sg::StackArgs sa;
+    sa.x = (const sg::bf16*)buf[0];
+    for (int l = 1; l <= 4; ++l) {
+      sa.w[l - 1] = n->at<sg::bf16>(n->L.wf[l]);
+      sa.bias[l - 1] = bias_of(n, l);
+    }
+    sa.y = (sg::bf16*)buf[1];
+    sa.B = B;
+    sa.H = H;
+    sa.W = W;
+    HIPCHK(sg::launch_stack(sa, n->st));
+    cur = 1;
+  } else {
+    for (int l = 1; l <= LBS_BLOCKS; ++l) {
+      if ((r = conv(sg::FWD_RES, LBS_WIDTH, LBS_WIDTH, buf[cur], n->at<void>(n->L.wf[l]), bias_of(n, l),
+                    buf[cur], nullptr, buf[cur ^ 1], nullptr, nullptr, 0, B, H, W, n->st)) != LB_OK)
+        return r;
+      cur ^= 1;
+    }
   }
   return conv(sg::FWD_OUT, LBS_WIDTH, LBS_OUT_CHANNELS, buf[cur], n->at<void>(n->L.wf[kLayers - 1]),
               bias_of(n, kLayers - 1), nullptr, nullptr, nullptr, nullptr, d_out, LBS_OUT, B, H, W,

@@ -193,18 +193,35 @@ __global__ __launch_bounds__(CNT) void conv_kernel(ConvArgs a) {
     const int h = h0 + wave;
     if (MODE == FWD_OUT) {
       if (h < a.H) {
+        if (a.nout == 3 && NS == 1) {
+          // the network's three output channels: lanes lg = 0 hold them
+          // (channels 0 .. 3 of their pixel), one 12-byte store each, the 16
+          // pixels of a subtile contiguous
+          if (lg == 0) {
 #pragma unroll
-        for (int ms = 0; ms < 4; ++ms) {
-          const int xx = x0 + ms * 16 + lm;
-          if (xx >= a.W) continue;
-          const int64_t q = ((int64_t)img * a.H + h) * a.W + xx;
-#pragma unroll
-          for (int ns = 0; ns < NS; ++ns)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int co = ns * 16 + lg * 4 + r;
-              if (co < a.nout) a.yf[q * a.nout + co] = acc[ms][ns][r] + bv[ns][r];
+            for (int ms = 0; ms < 4; ++ms) {
+              const int xx = x0 + ms * 16 + lm;
+              if (xx >= a.W) continue;
+              float* p = a.yf + (((int64_t)img * a.H + h) * a.W + xx) * 3;
+              p[0] = acc[ms][0][0] + bv[0][0];
+              p[1] = acc[ms][0][1] + bv[0][1];
+              p[2] = acc[ms][0][2] + bv[0][2];
             }
+          }
+        } else {
+#pragma unroll
+          for (int ms = 0; ms < 4; ++ms) {
+            const int xx = x0 + ms * 16 + lm;
+            if (xx >= a.W) continue;
+            const int64_t q = ((int64_t)img * a.H + h) * a.W + xx;
+#pragma unroll
+            for (int ns = 0; ns < NS; ++ns)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int co = ns * 16 + lg * 4 + r;
+                if (co < a.nout) a.yf[q * a.nout + co] = acc[ms][ns][r] + bv[ns][r];
+              }
+          }
         }
       }
     } else {
@@ -293,6 +310,160 @@ hipError_t launch_conv(int ci, int co, int mode, const ConvArgs& a, int grid, hi
   SG_CONV(16, 48)
 #undef SG_CONV
   return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// The residual stack h_l = h_(l-1) + SiLU(conv_l(h_(l-1))), l = 1..4, in one
+// pass over HBM: h0 is read once and h4 written once, the activations in
+// between stay in LDS. A workgroup owns a strip of SK_ST columns of one image
+// and marches down its rows. Every layer keeps a ring of four rows of
+// SK_ST + 8 pixels (x periodic: the strip and 4 halo columns on each side;
+// layer l computes pixels l .. SK_ST + 7 - l of its ring, one fewer on each
+// side per layer). Layer l computes row y at step y + 2 l from rows
+// y - 1 .. y + 1 of layer l - 1, which were finished by the step before, so
+// one barrier per step orders the rings (a slot is rewritten the step after
+// its last reader). Rows outside the image are zeros, the walls' padding:
+// the loader and every layer write them as such.
+//
+// Two waves per layer keep that layer's packed weights in registers (42
+// fragments of 16 bytes per lane) and split its 16-pixel subtiles 3 + 2
+// (layers 1-3: 70, 68, 66 pixels in five subtiles, the fifth overlapping
+// the fourth; layer 4: 64 pixels in 2 + 2). The roles are dealt so that
+// waves w and w + 4 (the same SIMD when waves go to the SIMDs in turn) pair
+// a 3-subtile part with a 2-subtile one. The product, its k order
+// and the epilogue are conv_kernel's (W X^T, FP32 accumulation, bias, SiLU,
+// the residual from the layer's input, bf16 rounding), so the stack gives
+// the same bits as four FWD_RES launches.
+// ---------------------------------------------------------------------------
+constexpr int SK_RW = SK_ST + 8;        // ring pixels per row
+constexpr int SK_PX = 56;               // LDS pixel stride (elements)
+constexpr int SK_KP = kpad<48>();       // 448
+constexpr int SK_NKC = SK_KP / 32;      // 14 steps of k
+constexpr int SK_NT = 512;              // 8 waves
+constexpr int SK_LD = SK_RW * 6;        // 16-byte chunks of an input row (432)
+
+__global__ __launch_bounds__(SK_NT) void stack_kernel(StackArgs a) {
+  __shared__ __attribute__((aligned(16))) bf16 ring[4][4][SK_RW * SK_PX];
+  __shared__ __attribute__((aligned(16))) float sbias[4][48];
+  const int tid = threadIdx.x, lane = tid & 63, lm = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: the role is scalar
+  const int strips = a.W / SK_ST;
+  const int img = blockIdx.x / strips, x0 = (blockIdx.x % strips) * SK_ST;
+
+  // role of the wave: layer L (1..4), first (3 subtiles; layer 4: 2) or
+  // second part (2 subtiles)
+  const int L = (0x43243211 >> (4 * wave)) & 15;
+  const bool first = (0x71 >> wave) & 1;
+  const int nm = (L < 4 && first) ? 3 : 2;
+  const int k0 = first ? 0 : (L < 4 ? 3 : 2);
+  int cs[3], wmin[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const int k = k0 + m;
+    const bool last = L < 4 && k == 4;
+    cs[m] = last ? SK_RW - 16 - L : L + 16 * k;  // first pixel of the subtile
+    wmin[m] = last ? L + 64 : 0;                 // pixels below this were written by subtile 3
+  }
+
+  bf16x8 wr[3][SK_NKC];
+  {
+    const bf16* wl = a.w[L - 1];
+#pragma unroll
+    for (int ns = 0; ns < 3; ++ns)
+#pragma unroll
+      for (int kc = 0; kc < SK_NKC; ++kc)
+        wr[ns][kc] = *(const bf16x8*)&wl[(ns * 16 + lm) * SK_KP + kc * 32 + lg * 8];
+  }
+  if (tid < 4 * 48) sbias[tid / 48][tid % 48] = a.bias[tid / 48] ? a.bias[tid / 48][tid % 48] : 0.f;
+  for (int i = tid; i < 4 * 4 * SK_RW * SK_PX / 8; i += SK_NT)
+    ((uint4*)&ring[0][0][0])[i] = uint4{0u, 0u, 0u, 0u};
+
+  // loader: thread tid < 432 moves chunk tid % 6 (8 channels) of ring pixel
+  // tid / 6 of every input row
+  const int lpx = tid / 6, lch = tid % 6;
+  int lx = x0 - 4 + lpx;
+  lx = lx < 0 ? lx + a.W : (lx >= a.W ? lx - a.W : lx);
+  const bf16* xin = a.x + (int64_t)img * a.H * a.W * 48 + (int64_t)lx * 48 + lch * 8;
+  uint4 pre = {0u, 0u, 0u, 0u};
+  if (tid < SK_LD && a.H > 0) pre = *(const uint4*)xin;
+  __syncthreads();  // the rings are zero
+
+  bf16* const rin = &ring[L - 1][0][0];
+  bf16* const rout = &ring[L < 4 ? L : 0][0][0];
+  constexpr int SLOT = SK_RW * SK_PX;
+  for (int t = 0; t < a.H + 8; ++t) {
+    if (tid < SK_LD) *(uint4*)&ring[0][t & 3][lpx * SK_PX + lch * 8] = pre;
+    pre = uint4{0u, 0u, 0u, 0u};
+    if (tid < SK_LD && t + 1 < a.H) pre = *(const uint4*)(xin + (int64_t)(t + 1) * a.W * 48);
+
+    const int y = t - 2 * L;
+    if (y < 0 || y >= a.H) {
+      if (L < 4) {  // the padding row: zeros over the wave's pixels
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          if (m >= nm) continue;
+          const int c = cs[m] + lm;
+          if (c < wmin[m]) continue;
+          uint2* o = (uint2*)&rout[(y & 3) * SLOT + c * SK_PX + lg * 12];
+          o[0] = uint2{0u, 0u};
+          o[1] = uint2{0u, 0u};
+          o[2] = uint2{0u, 0u};
+        }
+      }
+    } else {
+      f32x4 acc[3][3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int ns = 0; ns < 3; ++ns) acc[m][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kc = 0; kc < SK_NKC; ++kc) {
+        // this lane's 8 consecutive k = 8 j (one tap): j = 6 tap + ci0 / 8
+        const int j = 4 * kc + lg;
+        const bool kv = j < 54;
+        const int tap = kv ? (j * 43) >> 8 : 0;   // j / 6 for j < 56
+        const int ci0 = kv ? 8 * (j - 6 * tap) : 0;
+        const int ty = (tap * 11) >> 5;           // tap / 3 for tap < 9
+        const int dy = ty - 1, dx = tap - 3 * ty - 1;
+        const bf16* src = rin + ((y + dy) & 3) * SLOT + (lm + dx) * SK_PX + ci0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          if (m >= nm) continue;
+          bf16x8 xfr = *(const bf16x8*)&src[cs[m] * SK_PX];
+          if (!kv) xfr = bf16x8{};
+#pragma unroll
+          for (int ns = 0; ns < 3; ++ns)
+            acc[m][ns] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[ns][kc], xfr, acc[m][ns], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        if (m >= nm) continue;
+        const int c = cs[m] + lm;
+        if (c < wmin[m]) continue;
+        const bf16* rrow = rin + (y & 3) * SLOT + c * SK_PX + lg * 4;
+#pragma unroll
+        for (int ns = 0; ns < 3; ++ns) {
+          const bf16x4 rr = *(const bf16x4*)&rrow[ns * 16];
+          const f32x4 bv = *(const f32x4*)&sbias[L - 1][ns * 16 + lg * 4];
+          bf16x4 yo;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) yo[r] = f2bf(bf2f(rr[r]) + silu(acc[m][ns][r] + bv[r]));
+          if (L < 4)
+            *(bf16x4*)&rout[(y & 3) * SLOT + c * SK_PX + ns * 16 + lg * 4] = yo;
+          else
+            *(bf16x4*)(a.y + (((int64_t)img * a.H + y) * a.W + x0 + c - 4) * 48 + ns * 16 + lg * 4) = yo;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_stack(const StackArgs& a, hipStream_t st) {
+  if (a.B < 1 || a.H < 1 || a.W < SK_ST || a.W % SK_ST) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(stack_kernel, dim3(a.B * (a.W / SK_ST)), dim3(SK_NT), 0, st, a);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -33,6 +33,18 @@ struct ConvArgs {
   int B, H, W;
 };
 
+// The four residual layers in one pass (stack_kernel): strips of SK_ST
+// columns, W a multiple of SK_ST.
+constexpr int SK_ST = 64;
+
+struct StackArgs {
+  const bf16* x;         // h0 [B,H,W,48]
+  const bf16* w[4];      // packed weights of residual layers 1..4, each [48][kpad(48)]
+  const float* bias[4];  // [48] each, or null
+  bf16* y;               // h4 [B,H,W,48]
+  int B, H, W;
+};
+
 struct WgradArgs {
   const bf16* x;       // layer input [B,H,W,CI]
   const bf16* gz;      // dL/dz [B,H,W,CO]
@@ -47,6 +59,7 @@ struct Scales {
 
 hipError_t launch_conv(int ci, int co, int mode, const ConvArgs& a, int grid, hipStream_t st);
 hipError_t launch_wgrad(int ci, int co, const WgradArgs& a, int grid, hipStream_t st);
+hipError_t launch_stack(const StackArgs& a, hipStream_t st);
 // Per-workgroup partial sums of the weight gradient: [grid][9 CI CO + CO]
 // (the last CO entries: bias partials). tmp: 16 (9 cir cor + cor) doubles.
 hipError_t launch_wgrad_reduce(const float* part, int nblk, int CI, int CO, int cir, int cor,

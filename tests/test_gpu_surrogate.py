@@ -330,6 +330,53 @@ def test_network_forward_full_size_sampled(torch_cuda):
     net.close()
 
 
+def _layer_chain(torch, sg, p_dev, x_d):
+    # the network as six single-layer launches (lbs_conv), weights packed
+    # from the flat parameters the way the network packs them
+    outs, o = [], 0
+    shapes = sg.layer_shapes()
+    h = x_d
+    for l, (cir, cor) in enumerate(shapes):
+        CI = sg.IN_CHANNELS if l == 0 else sg.WIDTH
+        CO = sg.OUT_CHANNELS if l == len(shapes) - 1 else sg.WIDTH
+        w = p_dev[o:o + 9 * cir * cor]
+        o += 9 * cir * cor
+        b = p_dev[o:o + cor].contiguous()
+        o += cor
+        wp = sg.pack(w.contiguous(), cir, cor, CI, CO)
+        if l == 0:
+            h, _ = sg.conv(sg.FWD_FIRST, CI, CO, h, wp, bias=b)
+        elif l < len(shapes) - 1:
+            h, _ = sg.conv(sg.FWD_RES, CI, CO, h, wp, bias=b, res=h)
+        else:
+            outs = sg.conv(sg.FWD_OUT, CI, CO, h, wp, bias=b, nout=sg.OUT)
+    return outs
+
+
+@pytest.mark.parametrize("shape,train", [((2, 12, 64), False), ((3, 9, 128), False), ((1, 1, 64), False),
+                                         ((2, 3, 192), True), ((4, 128, 256), False), ((2, 10, 72), False)])
+def test_fused_residual_stack_equals_layer_chain(torch_cuda, shape, train):
+    # The forward runs the four residual layers as one pass with the
+    # activations kept on chip when W is a multiple of 64 (one strip: the
+    # periodic halo wraps onto the strip itself; one row: both neighbours are
+    # wall padding); the same products in the same order as the single-layer
+    # kernel, so the output is the same bits. W = 72 takes the per-layer path.
+    from paper_1307_6703_amd import surrogate as sg
+    torch = torch_cuda
+    B, H, W = shape
+    _say("fused residual stack vs layer chain", shape, train)
+    g = _rng(31)
+    p = _bf16_params(torch, g)
+    net = sg.Net(B, H, W, train=train)
+    net.set_params(p)
+    x_d, _ = _bf16(torch, g.normal(size=(B, H, W, 8)))
+    out = net.forward(x_d)
+    ref = _layer_chain(torch, sg, torch.from_numpy(np.asarray(p, dtype=np.float32)).cuda(), x_d)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref), float((out - ref).abs().max())
+    net.close()
+
+
 def _draws(count, Lx, Ly, seed):
     return ls.surrogate_draws(count, seed=seed, Lx=Lx, Ly=Ly)
 

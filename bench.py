@@ -71,15 +71,17 @@ def tuned_launch(key: str):
         return None
 
 
-def measured_traffic(nodes: int, steps_per_launch: int):
+def measured_traffic(nodes: int, steps_per_launch: int, threads: int, rows: int):
     """HBM bytes per launch from committed rocprofv3 counters, if they were
-    taken on the current kernel source for the kernel that runs."""
+    taken on the current kernel source for the kernel and launch shape that
+    run."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if (t.get("kernel_source_sha256") != kernel_hash() or t.get("nodes") != nodes
-            or t.get("steps_per_launch", 1) != steps_per_launch):
+            or t.get("steps_per_launch", 1) != steps_per_launch
+            or t.get("launch") != [threads, rows]):
         return None
     return t.get("traffic_bytes_per_launch")
 
@@ -364,7 +366,7 @@ def main():
     copy_gbs = 2 * src.numel() * 4 / (e4.elapsed_time(e5) / 10 * 1e-3) / 1e9
     del src, dst
 
-    traffic = measured_traffic(w.nodes, spl)
+    traffic = measured_traffic(w.nodes, spl, threads, rows)
     out = {
         "metric": "MLUPS",
         "value": round(mlups, 1),

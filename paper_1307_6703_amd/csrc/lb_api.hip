@@ -132,7 +132,8 @@ lb_status step_impl(lb_handle* h, int64_t nsteps, bool moments_last) {
     if (moments_last && s + n == nsteps) flags |= lbk::kWriteMoments;
     if (h->pending_shift) flags |= lbk::kApplyShift;
     if (pair)
-      HIPCHK(lbk::launch_step2(h->threads, h->ddesc, h->dtiles, h->ntiles, h->parity, flags, h->st));
+      HIPCHK(lbk::launch_step2(h->threads, h->ddesc, h->dtiles, h->ntiles, h->parity,
+                               flags | (h->p.y_periodic ? lbk::kYPeriodic : lbk::kYWalls), h->st));
     else if (h->fuse == 2)
       HIPCHK(lbk::launch_step(prec(h), h->p.collision != 0, h->threads1, h->ddesc, h->dtiles1, h->ntiles1, h->parity,
                               flags, h->st));
@@ -238,10 +239,14 @@ lb_status lb_create(const lb_params* p, void* dev_ws, size_t ws_bytes, void* hip
     return cleanup(fail(LB_EDEVICE, "clearing the check block failed"));
   if ((r = upload_desc(h)) != LB_OK) return cleanup(r);
   // default shape: two steps per launch for FP32 lattices of at least 2^20
-  // nodes whose strips are mostly interior columns, else one step per launch
+  // nodes whose strips are mostly interior columns, else one step per launch;
+  // 256-thread strips where their last strip is nearly full (wider strips
+  // stream longer pieces of each row), else 128
   if (prec_of(p) == lbk::kFP32 && p->collision == 0 && (int64_t)p->Lx * p->Ly >= ((int64_t)1 << 20) &&
       p->Lx >= 256) {
-    if ((r = set_tiles(h, 128, fused_default_rows(p, 128), 2)) != LB_OK) return cleanup(r);
+    const int64_t cols256 = (int64_t)((p->Lx + 241) / 242) * 242;
+    const int th = cols256 * 100 <= (int64_t)p->Lx * 103 ? 256 : 128;
+    if ((r = set_tiles(h, th, fused_default_rows(p, th), 2)) != LB_OK) return cleanup(r);
   } else {
     const int th = default_threads(p);
     if ((r = set_tiles(h, th, default_rows(p, th))) != LB_OK) return cleanup(r);

@@ -75,6 +75,7 @@ struct lb_batch {
   bool fp32 = false;  // FP32 storage
   int prec = 0;       // lbk::Prec of every instance
   int reg = 0;        // regularised collision (every instance)
+  int yflags = 0;     // lbk::kYWalls / kYPeriodic when every instance has that y boundary
   int check_every = 0, drift = 0;
   char* ws = nullptr;
   hipStream_t st = nullptr;
@@ -260,7 +261,8 @@ lb_status enqueue_steps(lb_batch* b, int64_t n, bool moments_last, bool dry = fa
     if (b->pending_shift) flags |= lbk::kApplyShift;
     if (!dry) {
       if (pair)
-        HIPCHK(lbk::launch_step2(b->threads, b->ddesc, b->dtiles, b->ntiles, b->parity, flags, b->st));
+        HIPCHK(lbk::launch_step2(b->threads, b->ddesc, b->dtiles, b->ntiles, b->parity,
+                                 flags | b->yflags, b->st));
       else if (b->fuse == 2)
         HIPCHK(lbk::launch_step(b->prec, b->reg != 0, b->threads1, b->ddesc, b->dtiles1, b->ntiles1, b->parity,
                                 flags, b->st));
@@ -365,6 +367,11 @@ lb_status lb_batch_create(int32_t count, const lb_params* p, void* dev_ws, size_
   b->fp32 = p[0].fp32 != 0;
   b->prec = prec_of(&p[0]);
   b->reg = p[0].collision;
+  {
+    int np = 0;
+    for (int i = 0; i < count; ++i) np += p[i].y_periodic != 0;
+    b->yflags = np == count ? lbk::kYPeriodic : (np == 0 ? lbk::kYWalls : 0);
+  }
   b->check_every = p[0].check_every;
   b->drift = p[0].drift_correct;
   b->inst.resize(count);
@@ -721,7 +728,7 @@ lb_status lb_batch_step_subset(lb_batch* b, int64_t nsteps, const int32_t* mask)
       const int flags = (launch == launches - 1) ? lbk::kWriteMoments : 0;
       const int par = b->parity ^ (int)(launch & 1);
       if (kind == 2)
-        HIPCHK(lbk::launch_step2(th, b->ddesc, b->dsub, (int)t.size(), par, flags, b->st));
+        HIPCHK(lbk::launch_step2(th, b->ddesc, b->dsub, (int)t.size(), par, flags | b->yflags, b->st));
       else
         HIPCHK(lbk::launch_step(b->prec, b->reg != 0, th, b->ddesc, b->dsub, (int)t.size(), par, flags, b->st));
     }

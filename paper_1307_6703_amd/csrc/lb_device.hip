@@ -419,7 +419,7 @@ __device__ __forceinline__ R slot_sum(const R v[9]) {
 // iteration. Ring slots are row mod ring size, so those of the second step
 // are the first step's shifted by 9.
 // ---------------------------------------------------------------------------
-template <int NT, bool MOM>
+template <int NT, bool MOM, int YB>
 __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ descs,
                                                       const Tile* __restrict__ tiles, int ntiles,
                                                       int parity, int flags) {
@@ -432,7 +432,8 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
   const int inst = tile.inst & 0x7fffffff;
   const int dir = (tile.inst < 0) ? -1 : 1;
   const Desc& d = descs[inst];
-  const int Lx = d.Lx, Ly = d.Ly, periodic = d.periodic;
+  // YB: 1 walls, 2 periodic in y for every tile of the launch, 0 read per lattice
+  const int Lx = d.Lx, Ly = d.Ly, periodic = YB == 0 ? d.periodic : (YB == 2 ? 1 : 0);
   const int64_t nn = (int64_t)Lx * Ly;
   const int rowb = 9 * Lx * (int)sizeof(R);
   const int arrb = (int)(9 * nn * (int64_t)sizeof(R));
@@ -576,12 +577,21 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
         v[0] = rc[0];
         v[1] = Oc[0 * ps + u - 1];
         v[3] = Oc[1 * ps + u + 1];
-        v[2] = lo ? rc[2] : s2;
-        v[5] = lo ? Oc[4 * ps + u] : Os[2 * ps + u - 1];
-        v[6] = lo ? Oc[5 * ps + u] : Os[3 * ps + u + 1];
-        v[4] = hi ? rc[1] : n4;
-        v[7] = hi ? Oc[2 * ps + u] : On[4 * ps + u + 1];
-        v[8] = hi ? Oc[3 * ps + u] : On[5 * ps + u - 1];
+        if (lo || hi) {  // a wall row (uniform): the node's own outgoing populations
+          v[2] = lo ? rc[2] : s2;
+          v[5] = lo ? Oc[4 * ps + u] : Os[2 * ps + u - 1];
+          v[6] = lo ? Oc[5 * ps + u] : Os[3 * ps + u + 1];
+          v[4] = hi ? rc[1] : n4;
+          v[7] = hi ? Oc[2 * ps + u] : On[4 * ps + u + 1];
+          v[8] = hi ? Oc[3 * ps + u] : On[5 * ps + u - 1];
+        } else {
+          v[2] = s2;
+          v[5] = Os[2 * ps + u - 1];
+          v[6] = Os[3 * ps + u + 1];
+          v[4] = n4;
+          v[7] = On[4 * ps + u + 1];
+          v[8] = On[5 * ps + u - 1];
+        }
         nR2[(s + 7) & 7][u] = slot_sum<R>(v);
       }
       {
@@ -597,8 +607,15 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
         }
         nR[s][u] = slot_sum<R>(v);
       }
-      pull_row<R>(pf[s % P], (k + P < K1) ? Sin : Snone, pbytes, (uint32_t)rowb, Ly, periodic,
-                  map_row_any(a + P * dir, Ly, periodic), vc, vm, vp);
+      {
+        const RowMap mp = map_row_any(a + P * dir, Ly, periodic);
+        const __amdgpu_buffer_rsrc_t Sp = (k + P < K1) ? Sin : Snone;
+        if (mp.wall == 0)  // interior rows (uniform): no wall slots
+          pull_row<R>(pf[s % P], Sp, pbytes, (uint32_t)rowb, Ly, periodic, RowMap{mp.phys, 0, 1}, vc,
+                      vm, vp);
+        else
+          pull_row<R>(pf[s % P], Sp, pbytes, (uint32_t)rowb, Ly, periodic, mp, vc, vm, vp);
+      }
       __syncthreads();
       // ---- phase 2: B1 (row a - dir), B2 (relative row k-10) -----------------
       LP[(s + 3) & 3][u] = stage_lp<R>(nR[(s + 6) & 7], nR[(s + 7) & 7], nR[s], u, c);
@@ -626,8 +643,15 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
         const RowMap m = map_row(a - 2 * dir, Ly, periodic);
         const int y = S1 + dir * r;
         const int wall2 = periodic ? 0 : (y == 0 ? 1 : (y == Ly - 1 ? 2 : 0));
-        stage_mom<R>(f[(s + 2) & 3], m.wall, m.ysgn, n1, Fx1, Fy1, c, jx1, jy1);
-        stage_mom<R>(f2[(s + 1) & 3], wall2, 1, n2, Fx2, Fy2, c, jx2, jy2);
+        // interior rows (uniform) take the body without the wall selects
+        if (m.wall == 0 && m.ysgn > 0)
+          stage_mom<R>(f[(s + 2) & 3], 0, 1, n1, Fx1, Fy1, c, jx1, jy1);
+        else
+          stage_mom<R>(f[(s + 2) & 3], m.wall, m.ysgn, n1, Fx1, Fy1, c, jx1, jy1);
+        if (wall2 == 0)
+          stage_mom<R>(f2[(s + 1) & 3], 0, 1, n2, Fx2, Fy2, c, jx2, jy2);
+        else
+          stage_mom<R>(f2[(s + 1) & 3], wall2, 1, n2, Fx2, Fy2, c, jx2, jy2);
         JR[(s + 2) & 3][u] = Mom<R>{jx1, jy1};
         JR2[(s + 1) & 3][u] = Mom<R>{jx2, jy2};
         Fr[s & 1][0] = Fx1;
@@ -716,15 +740,26 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
   }
 }
 
+template <int NT, int YB>
+static void launch_step2_y(const Desc* dd, const Tile* dt, int ntiles, int parity, int flags,
+                           hipStream_t st) {
+  if (flags & kWriteMoments)
+    hipLaunchKernelGGL((step2_kernel<NT, true, YB>), dim3(ntiles), dim3(NT), 0, st, dd, dt,
+                       ntiles, parity, flags);
+  else
+    hipLaunchKernelGGL((step2_kernel<NT, false, YB>), dim3(ntiles), dim3(NT), 0, st, dd, dt,
+                       ntiles, parity, flags);
+}
+
 template <int NT>
 static hipError_t launch_step2_t(const Desc* dd, const Tile* dt, int ntiles, int parity,
                                  int flags, hipStream_t st) {
-  if (flags & kWriteMoments)
-    hipLaunchKernelGGL((step2_kernel<NT, true>), dim3(ntiles), dim3(NT), 0, st, dd, dt, ntiles,
-                       parity, flags);
+  if (flags & kYWalls)
+    launch_step2_y<NT, 1>(dd, dt, ntiles, parity, flags, st);
+  else if (flags & kYPeriodic)
+    launch_step2_y<NT, 2>(dd, dt, ntiles, parity, flags, st);
   else
-    hipLaunchKernelGGL((step2_kernel<NT, false>), dim3(ntiles), dim3(NT), 0, st, dd, dt, ntiles,
-                       parity, flags);
+    launch_step2_y<NT, 0>(dd, dt, ntiles, parity, flags, st);
   return hipGetLastError();
 }
 

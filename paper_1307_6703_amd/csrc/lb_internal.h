@@ -29,7 +29,9 @@ struct Tile {
   int32_t inst, x0, y0, y1;
 };
 
-enum StepFlags : int { kWriteMoments = 1, kApplyShift = 2 };
+// kYWalls / kYPeriodic: every listed lattice has walls / is periodic in y
+// (the two-step kernel then compiles the other case out); neither: per lattice.
+enum StepFlags : int { kWriteMoments = 1, kApplyShift = 2, kYWalls = 4, kYPeriodic = 8 };
 
 // Reduction results per lattice (FP64), laid out in device memory.
 struct ReduceOut {

@@ -14,7 +14,11 @@ def test_traffic_record_matches_the_step_kernel_source():
     t = json.load(open(bench.TRAFFIC_FILE))
     assert t["kernel_source_sha256"] == bench.kernel_hash(), \
         "the step kernels changed since the counters were taken: take them again"
-    assert bench.measured_traffic(t["nodes"], t["steps_per_launch"]) == t["traffic_bytes_per_launch"]
+    assert bench.measured_traffic(t["nodes"], t["steps_per_launch"], *t["launch"]) == \
+        t["traffic_bytes_per_launch"]
+    # and only for the launch shape they were taken on
+    assert bench.measured_traffic(t["nodes"], t["steps_per_launch"], t["launch"][0],
+                                  t["launch"][1] + 8) is None
     # the counters see about the algorithmic bytes or more, never far less
     assert 0.5 * t["algorithmic_bytes_per_launch"] / t["steps_per_launch"] <= \
         t["traffic_bytes_per_launch"] <= 2 * t["algorithmic_bytes_per_launch"]

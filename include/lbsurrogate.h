@@ -81,7 +81,9 @@ lb_status lbs_set_params(lbs_net* net, const float* d_params);
 lb_status lbs_get_params(lbs_net* net, float* d_params);
 
 /* Inference: d_x [B][H][W][LBS_IN_CHANNELS] bf16 -> d_out [B][H][W][LBS_OUT]
- * FP32, 1 <= B <= max_batch. */
+ * FP32, 1 <= B <= max_batch. When W is a multiple of 64 the LBS_BLOCKS
+ * residual layers run as one pass over HBM (their activations stay on chip);
+ * the result is the same bits as running them layer by layer. */
 lb_status lbs_forward(lbs_net* net, int32_t B, const void* d_x, float* d_out);
 
 /* One training step on a batch: forward, loss = mean over nodes and the

@@ -53,7 +53,8 @@ lb_status upload_desc(lb_handle* h) {
 
 // Upload the tiles of a shape; fuse = steps per launch (1 or 2).
 lb_status upload_tiles(lb_handle* h, Tile* dst, int threads, int rows, int fuse, int* ntiles) {
-  std::vector<Tile> t = make_tiles(0, h->p.Lx, h->p.Ly, threads, rows, fuse == 2 ? 7 : 3);
+  std::vector<Tile> t = make_tiles(0, h->p.Lx, h->p.Ly, threads, rows, fuse == 2 ? 7 : 3, false,
+                                   fuse == 2 && !h->p.y_periodic);
   if ((int)t.size() > h->L.max_tiles) return fail(LB_EINVAL, "too many tiles for the workspace");
   HIPCHK(hipMemcpyAsync(dst, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice, h->st));
   HIPCHK(hipStreamSynchronize(h->st));

@@ -419,20 +419,18 @@ __device__ __forceinline__ R slot_sum(const R v[9]) {
 // iteration. Ring slots are row mod ring size, so those of the second step
 // are the first step's shifted by 9.
 // ---------------------------------------------------------------------------
+// One tile of the two-step kernel. YB: 1 the lattice has walls, 2 it is
+// periodic in y, or every row of the tile's pipeline lies at least one row
+// inside the walls (then the rows map as if periodic, which there is the
+// identity, and no wall rule applies: the same arithmetic on the same values
+// as the walls body, so the same bits); 0 read per lattice.
 template <int NT, bool MOM, int YB>
-__global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ descs,
-                                                      const Tile* __restrict__ tiles, int ntiles,
-                                                      int parity, int flags) {
+__device__ __forceinline__ void step2_tile(const Desc& __restrict__ d, const Tile& tile, int dir,
+                                           int parity, int flags, float (&nR)[8][NT + 2],
+                                           Pair<float> (&LP)[4][NT + 2], Mom<float> (&JR)[4][NT + 2],
+                                           float (&nR2)[8][NT + 2], Pair<float> (&LP2)[4][NT + 2],
+                                           Mom<float> (&JR2)[4][NT + 2], float (&O)[4][6][NT + 2]) {
   using R = float;
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int q = nb >> 3, rm = nb & 7, xcd = b & 7;
-  const int logical = xcd * q + (xcd < rm ? xcd : rm) + (b >> 3);
-  if (logical >= ntiles) return;  // uniform per block
-  const Tile tile = tiles[logical];
-  const int inst = tile.inst & 0x7fffffff;
-  const int dir = (tile.inst < 0) ? -1 : 1;
-  const Desc& d = descs[inst];
-  // YB: 1 walls, 2 periodic in y for every tile of the launch, 0 read per lattice
   const int Lx = d.Lx, Ly = d.Ly, periodic = YB == 0 ? d.periodic : (YB == 2 ? 1 : 0);
   const int64_t nn = (int64_t)Lx * Ly;
   const int rowb = 9 * Lx * (int)sizeof(R);
@@ -502,19 +500,6 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
   const int rds = dir * (ofirst - S1), rde = dir * (olast - S1);
   const int K = rde + 13;  // D2 runs on relative row k - 12
 
-  // LDS: 288 (NT + 2) bytes, so eight 64-thread, four 128-thread or two
-  // 256-thread workgroups fit on a CU. The force F goes from stage C to stage D of the
-  // next iteration in registers (Fr); of the first step's post-collision
-  // populations only those that move along x (1, 3, 5, 6, 7, 8) go through
-  // LDS (O, planes in that order), populations 0, 2 and 4 stay in the
-  // thread's registers (Or).
-  __shared__ R nR[8][NT + 2];
-  __shared__ Pair<R> LP[4][NT + 2];
-  __shared__ Mom<R> JR[4][NT + 2];
-  __shared__ R nR2[8][NT + 2];
-  __shared__ Pair<R> LP2[4][NT + 2];
-  __shared__ Mom<R> JR2[4][NT + 2];
-  __shared__ R O[4][6][NT + 2];
   const int u = t + 1;
 
   // one row in flight: an iteration of two steps outlasts the load latency,
@@ -738,6 +723,43 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
       }
     }
   }
+}
+
+// YB: 1 every lattice of the launch has walls (tiles whose pipeline stays at
+// least one row inside the walls take the wall-free body), 2 every lattice is
+// periodic in y, 0 read per lattice.
+template <int NT, bool MOM, int YB>
+__global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ descs,
+                                                      const Tile* __restrict__ tiles, int ntiles,
+                                                      int parity, int flags) {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb >> 3, rm = nb & 7, xcd = b & 7;
+  const int logical = xcd * q + (xcd < rm ? xcd : rm) + (b >> 3);
+  if (logical >= ntiles) return;  // uniform per block
+  const Tile tile = tiles[logical];
+  const int inst = tile.inst & 0x7fffffff;
+  const int dir = (tile.inst < 0) ? -1 : 1;
+  const Desc& d = descs[inst];
+  // LDS rings: 288 (NT + 2) bytes, so eight 64-thread, four 128-thread or
+  // two 256-thread workgroups fit on a CU. The force F goes from stage C to
+  // stage D of the next iteration in registers; of the first step's
+  // post-collision populations only those that move along x (1, 3, 5, 6, 7,
+  // 8) go through LDS (O, planes in that order), populations 0, 2 and 4 stay
+  // in the thread's registers.
+  __shared__ float nR[8][NT + 2];
+  __shared__ Pair<float> LP[4][NT + 2];
+  __shared__ Mom<float> JR[4][NT + 2];
+  __shared__ float nR2[8][NT + 2];
+  __shared__ Pair<float> LP2[4][NT + 2];
+  __shared__ Mom<float> JR2[4][NT + 2];
+  __shared__ float O[4][6][NT + 2];
+  // inner: the first step's pipeline rows, y0 - 7 .. y1 + 6, lie within
+  // [1, Ly - 2], so none is a wall or ghost row and their pulls read rows
+  // 0 .. Ly - 1 as they are
+  if (YB == 1 && NT == 256 && tile.y0 >= 8 && tile.y1 <= d.Ly - 8)
+    step2_tile<NT, MOM, 2>(d, tile, dir, parity, flags, nR, LP, JR, nR2, LP2, JR2, O);
+  else
+    step2_tile<NT, MOM, YB>(d, tile, dir, parity, flags, nR, LP, JR, nR2, LP2, JR2, O);
 }
 
 template <int NT, int YB>

@@ -171,14 +171,23 @@ inline int fused_default_rows(const lb_params* p, int threads, int rounds = 1) {
 // Tiles of one lattice: strips of `threads - 2 halo` columns (halo 3 for the
 // one-step kernel, 7 for the two-step kernel), chunks of `rows` rows (the
 // last one ragged) or, with `balanced` and Ly a multiple of 8, as many
-// chunks with heights that are multiples of 8 and differ by at most 8;
+// chunks with heights that are multiples of 8 and differ by at most 8, or,
+// with `short_ends`, the rows the last chunk would lack taken from the first
+// and the last chunk alike (the two-step kernel runs the chunks at the walls
+// in its slower general body, the others in the wall-free one);
 // strip-major so consecutive tiles are vertical neighbours. Odd chunks march
 // downwards (sign bit of inst), so two neighbouring chunks reach their
 // shared boundary rows at the same time and share those loads in L2.
 inline std::vector<Tile> make_tiles(int inst, int Lx, int Ly, int threads, int rows,
-                                    int halo = 3, bool balanced = false) {
+                                    int halo = 3, bool balanced = false, bool short_ends = false) {
   std::vector<int> y0s;
-  if (balanced && Ly % 8 == 0 && rows >= 8) {
+  const int nch = (Ly + rows - 1) / rows;
+  if (short_ends && nch >= 3) {
+    const int spare = nch * rows - Ly;  // < rows
+    const int s1 = (spare / 2) / 8 * 8;
+    y0s.push_back(0);
+    for (int j = 1, y = rows - s1; j < nch; ++j, y += rows) y0s.push_back(y);
+  } else if (balanced && Ly % 8 == 0 && rows >= 8) {
     const int n = (Ly + rows - 1) / rows, units = Ly / 8;
     for (int j = 0, y = 0; j < n; ++j) {
       y0s.push_back(y);

@@ -59,6 +59,14 @@ CASES = [
     (300, 70, False, (64, 8), 41),       # one-wave workgroups: strips of 50 columns
     (101, 37, True, (64, 17), 20),       # one column past two strips
     (3, 9, False, (64, 8), 14),
+    # 256-thread strips with walls: chunks whose pipeline stays at least one
+    # row inside the walls run the wall-free body (the first such chunk
+    # starts at row 8), the chunks at the walls the general one; the rows the
+    # last chunk would lack come off the first and the last chunk
+    (600, 64, False, (256, 8), 30),
+    (600, 100, False, (256, 24), 41),
+    (600, 96, False, (256, 16), 40),
+    (600, 40, True, (256, 16), 20),
 ]
 
 

@@ -236,8 +236,8 @@ lb_status lb_batch_step_subset(lb_batch* b, int64_t nsteps, const int32_t* mask)
  * updates threads - 6 of them); rows:
  * rows per y-chunk (>= 1). 0 keeps the default. Applies to the next step.
  * lb_create picks two steps per launch (below) for FP32 lattices of at least
- * 2^20 nodes and 256 columns (256-thread strips when the last strip is at
- * least about 97% full, else 128), one step per launch otherwise. */
+ * 2^20 nodes and 256 columns (256-thread strips when their columns exceed
+ * Lx by at most 3%, else 128), one step per launch otherwise. */
 lb_status lb_set_launch(lb_handle* h, int32_t threads, int32_t rows);
 lb_status lb_get_launch(lb_handle* h, int32_t* threads, int32_t* rows, int32_t* blocks);
 lb_status lb_batch_set_launch(lb_batch* b, int32_t threads, int32_t rows);

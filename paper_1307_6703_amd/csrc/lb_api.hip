@@ -241,8 +241,8 @@ lb_status lb_create(const lb_params* p, void* dev_ws, size_t ws_bytes, void* hip
   if ((r = upload_desc(h)) != LB_OK) return cleanup(r);
   // default shape: two steps per launch for FP32 lattices of at least 2^20
   // nodes whose strips are mostly interior columns, else one step per launch;
-  // 256-thread strips where their last strip is nearly full (wider strips
-  // stream longer pieces of each row), else 128
+  // 256-thread strips where their columns exceed Lx by at most 3% (wider
+  // strips stream longer pieces of each row), else 128
   if (prec_of(p) == lbk::kFP32 && p->collision == 0 && (int64_t)p->Lx * p->Ly >= ((int64_t)1 << 20) &&
       p->Lx >= 256) {
     const int64_t cols256 = (int64_t)((p->Lx + 241) / 242) * 242;

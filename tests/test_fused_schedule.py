@@ -193,3 +193,56 @@ def test_three_barriers_per_iteration_suffice():
 @pytest.mark.parametrize("dropped", [1, 2, 3])
 def test_each_barrier_is_needed(dropped):
     assert _hazards({1, 2, 3} - {dropped}) > 0
+
+
+# ---- interior chunks on lattices with walls ----------------------------------
+
+
+def _inner(Ly, y0, y1):
+    # the kernel's rule (step2_kernel): such a chunk takes the body compiled
+    # as if periodic
+    return y0 >= 8 and y1 <= Ly - 8
+
+
+def _stage_rows(g, d):
+    """Every row a valid stage of the chunk touches: the first step's
+    pipeline rows and their pull neighbours, the second step's rows."""
+    S1, K1, a0 = g["S1"], g["K1"], g["a0"]
+    rows = set()
+    for k in range(K1):
+        a = a0 + d * k
+        rows.update((a - 1, a, a + 1))
+    for r in range(g["r2s"], g["r2e"] + 1):
+        rows.add(S1 + d * r)
+    return rows
+
+
+@pytest.mark.parametrize("Ly", [16, 17, 40, 64, 2048])
+def test_inner_chunks_see_no_wall_row(Ly):
+    # For a chunk the rule calls inner, the walls and the periodic reading
+    # give the same schedule (no clipping at a wall, no mirrored row), and
+    # every row its valid stages touch lies in 0 .. Ly - 1 with the first
+    # step's pipeline in 1 .. Ly - 2: no wall or ghost row, so the wall-free
+    # body computes what the general one does. The rule is tight: a chunk
+    # starting one row higher reaches the wall row.
+    seen = 0
+    for y0 in range(0, Ly):
+        for h in (1, 8, 9, 24, 144):
+            y1 = min(Ly, y0 + h)
+            for d in (1, -1):
+                gw = _regions(Ly, False, y0, y1, d)
+                if not _inner(Ly, y0, y1):
+                    continue
+                seen += 1
+                gp = _regions(Ly, True, y0, y1, d)
+                assert gw == gp, (y0, y1, d)
+                rows = _stage_rows(gw, d)
+                assert min(rows) >= 0 and max(rows) <= Ly - 1, (y0, y1, d)
+                pipe = [gw["a0"] + d * k for k in range(gw["K1"])]
+                assert min(pipe) >= 1 and max(pipe) <= Ly - 2, (y0, y1, d)
+    if Ly >= 17:
+        assert seen > 0
+    # tightness: y0 = 7 puts the wall row 0 into the pipeline
+    if Ly >= 24:
+        g = _regions(Ly, False, 7, 16, 1)
+        assert min(g["a0"] + k for k in range(g["K1"])) == 0

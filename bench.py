@@ -2,7 +2,7 @@
 """Throughput of the fused lattice Boltzmann step on one MI355X.
 
 Workload (synthetic, seeded): 8192 x 2048 lattice between walls moving at
-+-0.08, T = 0.9 T_c, periodic potential V0 = 0.1 with 32 stripes, density noise
++-0.08, T = 0.9 T_c, periodic potential V0 = 0.01 with 32 stripes, density noise
 +-0.01 around n = 1, FP32 deviation storage, FP64 mass/momentum check with
 drift correction every 100 steps. One step = one full time step of the lattice
 (stream, density, stencils, force, walls, collision, store) plus its share of
@@ -23,8 +23,10 @@ effective rate, hbm_gbs_min the rate of the bytes that must cross HBM and
 hbm_gbs_measured that of the bytes the HBM counters saw.
 
 Prints one JSON line: MLUPS (million lattice-node updates per second), the
-roofline of the step kernel against the HBM peak, and the FP64 CPU oracle
-timed on the host cores on a bounded sample of the same workload.
+roofline of the step kernel against the HBM peak, the FP64 CPU oracle timed
+on the host cores on a bounded sample of the same workload, and the headline
+path's difference from the oracle after the sample's steps from the same
+fields (error_vs_oracle).
 """
 import argparse
 import hashlib
@@ -102,15 +104,35 @@ def cpu_baseline(w, n0, fext, seconds: float):
         if steps:
             o.run(steps, threads=threads)
         dt = time.perf_counter() - t0
-        return round(w.nodes * (steps + 1) / dt / 1e6, 3), used, steps + 1, dt
+        return round(w.nodes * (steps + 1) / dt / 1e6, 3), used, steps + 1, dt, o
 
-    v, used, n, dt = timed(0, seconds)
-    v1, _, n1, dt1 = timed(1, seconds / 3)
+    v, used, n, dt, o = timed(0, seconds)
+    v1, _, n1, dt1, _ = timed(1, seconds / 3)
     return {"value": v, "unit": "MLUPS", "cores": used, "kind": "oracle",
             "sample": f"{n} FP64 steps of the full {w.Lx}x{w.Ly} lattice ({dt:.1f} s)",
             "single_thread": {"value": v1, "unit": "MLUPS", "cores": 1,
                               "sample": f"{n1} FP64 steps of the full lattice on one thread "
-                                        f"({dt1:.1f} s)"}}
+                                        f"({dt1:.1f} s)"}}, o, n
+
+
+def error_vs_oracle(w, n0, fext, o, steps: int, check_every: int):
+    """The headline path (FP32 deviations, its default launch) run for the
+    same steps from the same fields as the oracle's all-thread sample: the
+    largest relative density and absolute velocity differences over the
+    lattice."""
+    import numpy as np
+    from paper_1307_6703_amd import Lattice
+    lat = Lattice(w.Lx, w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, U=w.U, fext=fext,
+                  y_periodic=w.y_periodic, fp32=True, check_every=check_every, drift_correct=True)
+    lat.init(n0)
+    lat.step(steps)
+    n, ux, uy = lat.moments()
+    launch = lat.get_launch()
+    spl = lat.steps_per_launch()
+    lat.close()
+    return {"steps": steps, "max_rel_density": float(np.max(np.abs(n - o.n) / o.n)),
+            "max_abs_velocity": float(max(np.abs(ux - o.ux).max(), np.abs(uy - o.uy).max())),
+            "tolerance": 1e-4, "path": f"fp32, launch {launch[0]} x {launch[1]}, {spl} step(s) per launch"}
 
 
 def batched_bench(steps: int, seed: int = 1307, launch=None):
@@ -439,7 +461,11 @@ def main():
             log=lambda m: print(f"[bench] surrogate {m}", file=sys.stderr, flush=True))
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, n0, fext, args.cpu_seconds)
+        out["cpu_baseline"], orc, orc_steps = cpu_baseline(w, n0, fext, args.cpu_seconds)
+        out["error_vs_oracle"] = error_vs_oracle(w, n0, fext, orc, orc_steps, args.check_every)
+        del orc
+        print(f"[bench] against the FP64 oracle after {orc_steps} steps: max relative density "
+              f"difference {out['error_vs_oracle']['max_rel_density']:.2e}", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

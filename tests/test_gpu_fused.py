@@ -193,9 +193,13 @@ def test_batch_fused_equals_one_step_batch(torch_cuda, check_every, launch):
 
 def test_default_shape(torch_cuda):
     from paper_1307_6703_amd import Lattice
-    big = Lattice(2048, 512, fp32=True)
-    assert big.steps_per_launch() == 2 and big.get_launch()[0] == 128
-    big.close()
+    # 256-thread strips (242 columns) when they cover Lx with at most 3% to
+    # spare, else 128: 2048 needs 9 x 242 = 2178 (6% over), 8192 34 x 242
+    # = 8228 (0.4%), 4096 17 x 242 = 4114 (0.4%)
+    for Lx, Ly, th in ((2048, 512, 128), (8192, 128, 256), (4096, 256, 256)):
+        big = Lattice(Lx, Ly, fp32=True)
+        assert big.steps_per_launch() == 2 and big.get_launch()[0] == th, (Lx, Ly, big.get_launch())
+        big.close()
     for kw in (dict(Lx=2048, Ly=512, fp32=False), dict(Lx=300, Ly=70, fp32=True),
                dict(Lx=128, Ly=8192, fp32=True)):
         g = Lattice(kw.pop("Lx"), kw.pop("Ly"), **kw)

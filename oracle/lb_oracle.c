@@ -30,22 +30,13 @@
 #include <omp.h>
 #endif
 
+#include "lb_oracle.h"
+
 /* D2Q9 abscissas and weights (Sec. II, the Gauss-Hermite velocity set). */
 static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 static const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-
-typedef struct {
-  int32_t Lx, Ly;
-  int32_t y_periodic; /* 1: periodic in y; 0: moving walls at rows 0, Ly-1 */
-  int32_t collision;  /* 0: BGK, Eq.(evoleq); 1: regularised (lbo_regularize) */
-  double T;     /* reduced temperature */
-  double tau;   /* relaxation time, paper units */
-  double kappa; /* surface-tension parameter, paper units */
-  double N, Q;  /* stencil parameters; M = (1-2N)/4, R = (1-Q)/2 */
-  double U;     /* wall speed (lattice units): lower wall -U, upper +U */
-} lbo_params;
 
 /* ---------------------------------------------------------------------- */
 /* Pointwise pieces, exported so tests can pin each one on its own.        */

@@ -1,7 +1,7 @@
 """Build the HIP library liblbvdw.so (gfx950) in-tree.
 
-Compiles the HIP sources of csrc/ (lattice step, C ABI, batch, surrogate)
-with hipcc for gfx950 only.
+Compiles the HIP sources of csrc/ (lattice step, C ABI, batch, the D2Q17
+variant, surrogate) with hipcc for gfx950 only.
 Packed FP32 instructions are disabled for device code. Multiply-adds fuse only
 within one source expression (-ffp-contract=on), so the arithmetic of a node
 does not depend on how the compiler lays out a kernel instance: every launch
@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbvdw.so")
-SOURCES = ["lb_device.hip", "lb_api.hip", "lb_batch.hip", "sg_device.hip", "sg_api.hip"]
+SOURCES = ["lb_device.hip", "lb_api.hip", "lb_batch.hip", "d17_device.hip", "d17_api.hip",
+           "sg_device.hip", "sg_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",

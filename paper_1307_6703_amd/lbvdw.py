@@ -80,6 +80,20 @@ SIGNATURES = {
     "lb_batch_set_equilibrium_device": (ctypes.c_int, [_VP, _VP, _I32P]),
     "lb_batch_shift_equilibrium_device": (ctypes.c_int, [_VP, _VP, _VP, _I32P]),
     "lb_batch_step_subset": (ctypes.c_int, [_VP, ctypes.c_int64, _I32P]),
+    # include/lbd2q17.h
+    "lb17_lattice": (ctypes.c_int, [_I32P, _I32P, _DP, _DP]),
+    "lb17_workspace_bytes": (ctypes.c_int, [_PP, ctypes.POINTER(ctypes.c_size_t)]),
+    "lb17_create": (ctypes.c_int, [_PP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    "lb17_init_lattice": (ctypes.c_int, [_VP, _DP, _DP, _DP]),
+    "lb17_step_n": (ctypes.c_int, [_VP, ctypes.c_int64]),
+    "lb17_get_moments": (ctypes.c_int, [_VP, _DP, _DP, _DP]),
+    "lb17_reduce": (ctypes.c_int, [_VP, _DP]),
+    "lb17_get_populations": (ctypes.c_int, [_VP, _DP]),
+    "lb17_set_populations": (ctypes.c_int, [_VP, _DP, ctypes.c_int64]),
+    "lb17_set_launch": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
+    "lb17_get_launch": (ctypes.c_int, [_VP, _I32P, _I32P, _I32P]),
+    "lb17_get_step": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64)]),
+    "lb17_destroy": (ctypes.c_int, [_VP]),
     # include/lbsurrogate.h
     "lbs_param_count": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64)]),
     "lbs_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -315,6 +329,98 @@ class Lattice:
     def close(self):
         if getattr(self, "_h", None) is not None and _lib is not None:
             _lib.lb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lattice17():
+    """The D2Q17 velocity set: (cx, cy, w, s) as lb17_lattice gives them."""
+    load_library()
+    cx, cy = (ctypes.c_int32 * 17)(), (ctypes.c_int32 * 17)()
+    w = np.empty(17)
+    s = ctypes.c_double()
+    _check(_lib.lb17_lattice(cx, cy, _dptr(w), ctypes.byref(s)))
+    return np.array(cx[:]), np.array(cy[:]), w, s.value
+
+
+class Lattice17:
+    """One periodic D2Q17 lattice on the current GPU (include/lbd2q17.h):
+    workspace tensor + lb17_handle. Parameters as for Lattice; y_periodic is
+    implied, U must be 0, fp32 is False/True."""
+
+    def __init__(self, Lx, Ly, *, T=0.95, tau=1.0, kappa=0.3, N=0.3, Q=2.0, fext=None,
+                 fp32=False, check_every=0, drift_correct=False, device="cuda", stream=None):
+        import torch
+        lib = load_library()
+        self.Lx, self.Ly = int(Lx), int(Ly)
+        self.fp32 = bool(fp32)
+        self._p, self._fext = make_params(Lx, Ly, T, tau, kappa, N, Q, 0.0, fext, True,
+                                          int(self.fp32), check_every, drift_correct, False)
+        nbytes = ctypes.c_size_t()
+        _check(lib.lb17_workspace_bytes(ctypes.byref(self._p), ctypes.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        h = ctypes.c_void_p()
+        _check(lib.lb17_create(ctypes.byref(self._p), ctypes.c_void_p(base + off), nbytes.value,
+                               _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def shape(self):
+        return (self.Ly, self.Lx)
+
+    def init(self, n0, ux0=None, uy0=None):
+        a = [_host(v, self.shape) for v in (n0, ux0, uy0)]
+        _check(_lib.lb17_init_lattice(self._h, _dptr(a[0]), _dptr(a[1]), _dptr(a[2])))
+        return self
+
+    def step(self, nsteps: int = 1):
+        _check(_lib.lb17_step_n(self._h, int(nsteps)))
+        return self
+
+    def moments(self):
+        n, ux, uy = (np.empty(self.shape) for _ in range(3))
+        _check(_lib.lb17_get_moments(self._h, _dptr(n), _dptr(ux), _dptr(uy)))
+        return n, ux, uy
+
+    def reduce(self):
+        out = np.empty(6)
+        _check(_lib.lb17_reduce(self._h, _dptr(out)))
+        return dict(mass=out[0], jx=out[1], jy=out[2], nmin=out[3], nmax=out[4], nonfinite=out[5])
+
+    def populations(self):
+        f = np.empty((17,) + self.shape)
+        _check(_lib.lb17_get_populations(self._h, _dptr(f)))
+        return f
+
+    def set_populations(self, f, step: int = 0):
+        f = _host(f, (17,) + self.shape)
+        _check(_lib.lb17_set_populations(self._h, _dptr(f), int(step)))
+        return self
+
+    @property
+    def step_count(self) -> int:
+        v = ctypes.c_int64()
+        _check(_lib.lb17_get_step(self._h, ctypes.byref(v)))
+        return v.value
+
+    def set_launch(self, threads: int = 0, rows: int = 0):
+        _check(_lib.lb17_set_launch(self._h, int(threads), int(rows)))
+
+    def get_launch(self):
+        t, r, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.lb17_get_launch(self._h, ctypes.byref(t), ctypes.byref(r), ctypes.byref(b)))
+        return t.value, r.value, b.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.lb17_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -4,19 +4,20 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1307_6703_amd import lbvdw
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("lbvdw.h", "lbsurrogate.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("lbvdw.h", "lbd2q17.h", "lbsurrogate.h")]
 
 
 def _declared():
     names = set()
     for h in HEADERS:
         src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
-        names |= set(re.findall(r"\b(?:lb_status|const char\*)\s+(lbs?_\w+)\s*\(", src))
+        names |= set(re.findall(r"\b(?:lb_status|const char\*)\s+(lb(?:s|17)?_\w+)\s*\(", src))
     return sorted(names)
 
 
@@ -34,7 +35,9 @@ def test_header_declares_the_documented_calls():
                  "lb_batch_create", "lb_batch_init", "lb_batch_step_n", "lb_batch_get_moments",
                  "lb_batch_status", "lb_destroy", "lb_batch_destroy", "lb_last_error",
                  "lb_batch_step_subset", "lb_batch_set_equilibrium_device", "lbs_create",
-                 "lbs_forward", "lbs_train_step", "lbs_conv", "lbs_wgrad"):
+                 "lbs_forward", "lbs_train_step", "lbs_conv", "lbs_wgrad", "lb17_create",
+                 "lb17_init_lattice", "lb17_step_n", "lb17_get_moments", "lb17_reduce",
+                 "lb17_get_populations", "lb17_set_populations", "lb17_destroy"):
         assert must in names
 
 
@@ -137,3 +140,55 @@ def test_surrogate_sizes_and_validation(lib):
     st = lib.lbs_wgrad(16, 48, 16, 48, None, None, 1, 4, 4, 1.0, None, 1, None, None, None)
     assert st == lbvdw.LB_EINVAL
     assert lib.lbs_create(1, 4, 4, 0, None, 0, None, None) == lbvdw.LB_EINVAL
+
+
+def _bytes17(lib, **kw):
+    kw.setdefault("y_periodic", True)
+    p, fx = lbvdw.make_params(**kw)
+    n = ctypes.c_size_t()
+    st = lib.lb17_workspace_bytes(ctypes.byref(p), ctypes.byref(n))
+    return st, n.value, lib.lb_last_error().decode()
+
+
+def test_d2q17_workspace_and_lattice(lib):
+    st32, n32, _ = _bytes17(lib, Lx=512, Ly=256, fp32=True)
+    st64, n64, _ = _bytes17(lib, Lx=512, Ly=256, fp32=False)
+    assert st32 == 0 and st64 == 0
+    nn = 512 * 256
+    # two buffers of 17 planes, plus three FP64 moment planes
+    assert n32 >= 2 * 17 * nn * 4 + 3 * nn * 8
+    assert n64 - n32 == pytest.approx(2 * 17 * nn * 4, rel=0.01)
+    # the library's velocity set and weights are the oracle's
+    from oracle import d2q17 as o17
+    cx, cy, w, s = lbvdw.lattice17()
+    ocx, ocy, ow, os_ = o17.lattice()
+    assert (cx == ocx).all() and (cy == ocy).all()
+    assert np.abs(w - ow).max() < 1e-15 and abs(s - os_) < 1e-15
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(Lx=16, Ly=16, y_periodic=False), "periodic"),
+    (dict(Lx=16, Ly=16, U=0.01), "U must be 0"),
+    (dict(Lx=16, Ly=16, regularized=True), "BGK"),
+    (dict(Lx=16, Ly=16, fp32="sr"), "fp32"),
+    (dict(Lx=16, Ly=3), "Ly"),
+    (dict(Lx=16, Ly=16, tau=0.25), "tau"),
+    (dict(Lx=8192, Ly=4096, fp32=True), "2 GiB"),
+    (dict(Lx=4, Ly=16, fext=[0.0, float("nan"), 0.0, 0.0]), "fext"),
+])
+def test_d2q17_invalid_parameters_are_rejected(lib, kw, needle):
+    st, _, msg = _bytes17(lib, **kw)
+    assert st == lbvdw.LB_EINVAL
+    assert needle in msg
+
+
+def test_d2q17_create_checks_the_workspace_first(lib):
+    p, _ = lbvdw.make_params(Lx=32, Ly=16, y_periodic=True)
+    h = ctypes.c_void_p()
+    st = lib.lb17_create(ctypes.byref(p), ctypes.c_void_p(1 << 20), 1024, None, ctypes.byref(h))
+    assert st == lbvdw.LB_ENOMEM and "too small" in lib.lb_last_error().decode()
+    st = lib.lb17_create(ctypes.byref(p), ctypes.c_void_p((1 << 20) + 8), 1 << 30, None,
+                         ctypes.byref(h))
+    assert st == lbvdw.LB_EINVAL and "aligned" in lib.lb_last_error().decode()
+    assert lib.lb17_step_n(None, 1) == lbvdw.LB_EINVAL
+    assert lib.lb17_destroy(None) == lbvdw.LB_OK

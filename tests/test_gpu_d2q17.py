@@ -1,0 +1,258 @@
+"""Parity of the D2Q17 HIP path (include/lbd2q17.h, through the C ABI) with
+the FP64 D2Q17 oracle (the third-order model named after Eq.(nav)).
+
+FP64 mode: densities, velocities and populations within 1e-10 (absolute).
+FP32 storage: within 1e-4 relative to the density. Inputs are seeded and
+identical on both sides (lbsynth): a quench at T = 0.9 with the periodic
+potential. Each case prints its name first, so a failing GPU run names the
+case that was running."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import lbsynth as ls
+from oracle import d2q17 as o17
+from oracle.lb_oracle import Params
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32 = 1e-4
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _pair(Lx, Ly, *, T=0.9, tau=1.0, kappa=0.3, V0=0.01, k=2, fp32=False, seed=1307,
+          launch=None, n0=None, ux0=None, uy0=None, oracle=True, **extra):
+    from paper_1307_6703_amd import Lattice17
+    N, Q = ls.table1_nq(T)
+    fext = ls.potential_force(Lx, V0, k)
+    if n0 is None:
+        n0 = ls.noisy_density(Lx, Ly, seed)
+    g = Lattice17(Lx, Ly, T=T, tau=tau, kappa=kappa, N=N, Q=Q, fext=fext, fp32=fp32, **extra)
+    if launch:
+        g.set_launch(*launch)
+    g.init(n0, ux0, uy0)
+    o = None
+    if oracle:
+        o = o17.Oracle17(Params(Lx, Ly, T=T, tau=tau, kappa=kappa, N=N, Q=Q, y_periodic=True),
+                         n0, ux0, uy0, fext=fext)
+    return g, o
+
+
+def _cmp(g, o):
+    n, ux, uy = g.moments()
+    return (np.abs(n - o.n).max(), np.abs(ux - o.ux).max(), np.abs(uy - o.uy).max(),
+            (np.abs(n - o.n) / o.n).max())
+
+
+# (Lx, Ly, threads, rows, V0): several strips and chunks with ragged tails,
+# one strip narrower than the workgroup, few- and one-column lattices. The
+# potential's force table scales as 1/Lx: on one column it is a uniform push
+# that accelerates the fluid without bound, so that case runs without it.
+SHAPES = [(300, 70, 64, 16, 0.01), (131, 37, 128, 8, 0.01), (517, 130, 256, 24, 0.01),
+          (64, 64, 256, 64, 0.01), (5, 9, 64, 4, 0.01), (1, 16, 64, 16, 0.0)]
+
+
+@pytest.mark.parametrize("Lx,Ly,threads,rows,V0", SHAPES)
+def test_fp64_parity_ragged_shapes(torch_cuda, Lx, Ly, threads, rows, V0):
+    _say("d2q17 fp64", Lx, Ly, threads, rows, V0)
+    g, o = _pair(Lx, Ly, V0=V0, launch=(threads, rows))
+    f0 = g.populations()
+    assert np.abs(f0 - o.S).max() <= 1e-15
+    done = 0
+    for upto in (1, 10, 100):
+        g.step(upto - done)
+        o.run(upto - done, threads=8)
+        done = upto
+        dn, dux, duy, _ = _cmp(g, o)
+        _say(f"step {upto}: |dn| {dn:.2e} |dux| {dux:.2e} |duy| {duy:.2e}")
+        assert dn <= TOL64 and dux <= TOL64 and duy <= TOL64
+    assert np.abs(g.populations() - o.S).max() <= TOL64
+
+
+def test_fp64_parity_long_quench(torch_cuda):
+    # 1000 steps of a quench with the potential: the phases separate
+    _say("d2q17 fp64 long 128x64")
+    g, o = _pair(128, 64, V0=0.05, k=4)
+    m0 = g.reduce()["mass"]
+    done = 0
+    for upto in (200, 1000):
+        g.step(upto - done)
+        o.run(upto - done, threads=8)
+        done = upto
+        dn, dux, duy, _ = _cmp(g, o)
+        _say(f"step {upto}: |dn| {dn:.2e} |dux| {dux:.2e} |duy| {duy:.2e}")
+        assert dn <= TOL64 and dux <= TOL64 and duy <= TOL64
+    assert o.n.max() - o.n.min() > 0.3
+    r = g.reduce()
+    assert abs(r["mass"] - m0) / m0 <= 1e-13
+    assert abs(r["mass"] - o.mass()) / m0 <= 1e-13
+    jx, jy = o.momentum()
+    assert abs(r["jx"] - jx) <= 1e-10 and abs(r["jy"] - jy) <= 1e-10
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_launch_shapes_give_the_same_bits(torch_cuda, fp32):
+    _say("d2q17 launch shapes", "fp32" if fp32 else "fp64")
+    ref = None
+    for launch in ((64, 8), (128, 40), (256, 200), (256, 16)):
+        g, _ = _pair(300, 200, fp32=fp32, launch=launch, oracle=False)
+        g.step(12)
+        f = g.populations()
+        if ref is None:
+            ref = f
+        else:
+            assert np.array_equal(f, ref), launch
+
+
+@pytest.mark.parametrize("Lx,Ly,threads,rows", [(300, 70, 64, 16), (517, 130, 256, 24)])
+def test_fp32_parity_quench(torch_cuda, Lx, Ly, threads, rows):
+    # 100 steps into the quench: the spinodal stage amplifies any difference
+    # (a one-ulp FP32 change of the initial density grows to 2e-6 by step
+    # 100 and 3e-4 by step 300 in the FP64 oracle), so the 1e-4 gate applies
+    # before that amplification
+    _say("d2q17 fp32 quench", Lx, Ly, threads, rows)
+    g, o = _pair(Lx, Ly, fp32=True, launch=(threads, rows))
+    g.step(100)
+    o.run(100, threads=8)
+    dn, dux, duy, rel = _cmp(g, o)
+    _say(f"fp32 step 100: rel dn {rel:.2e} |dux| {dux:.2e} |duy| {duy:.2e}")
+    assert rel <= TOL32 and dux <= TOL32 and duy <= TOL32
+
+
+def test_fp32_parity_relaxing_droplet(torch_cuda):
+    # a droplet relaxing for 2000 steps (no amplification: a one-ulp change
+    # of the initial density stays at 1e-8)
+    from oracle import closed_forms as cf
+    _say("d2q17 fp32 droplet 128x128")
+    T = 0.95
+    nl, nv, _ = cf.maxwell(T)
+    n0 = ls.droplet(128, 128, 30, nl, nv, width=2.0)
+    g, o = _pair(128, 128, T=T, V0=0.0, fp32=True, n0=n0, check_every=100, drift_correct=True)
+    for upto in (500, 2000):
+        g.step(upto - o.steps)
+        o.run(upto - o.steps, threads=8)
+        dn, dux, duy, rel = _cmp(g, o)
+        _say(f"fp32 droplet step {upto}: rel dn {rel:.2e} |dux| {dux:.2e} |duy| {duy:.2e}")
+        assert rel <= TOL32 and dux <= TOL32 and duy <= TOL32
+
+
+def test_fp32_drift_correction_restores_the_mass(torch_cuda):
+    _say("d2q17 fp32 drift correction")
+    runs = {}
+    for drift in (False, True):
+        g, _ = _pair(256, 128, fp32=True, oracle=False, check_every=100, drift_correct=drift)
+        m0 = g.reduce()["mass"]
+        g.step(3000)
+        runs[drift] = abs(g.reduce()["mass"] / m0 - 1)
+    _say("mass drift without / with correction", runs[False], runs[True])
+    assert runs[True] <= 1e-12
+    assert runs[True] < runs[False]
+
+
+def test_restart_from_oracle_populations(torch_cuda):
+    # set_populations takes a state mid-run; the next steps agree with the
+    # oracle's, and the state reads back unchanged
+    _say("d2q17 restart")
+    g, o = _pair(96, 40)
+    o.run(50, threads=8)
+    g.set_populations(o.S, step=50)
+    assert g.step_count == 50
+    assert np.abs(g.populations() - o.S).max() <= 1e-15
+    g.step(30)
+    o.run(30, threads=8)
+    dn, dux, duy, _ = _cmp(g, o)
+    assert dn <= TOL64 and dux <= TOL64 and duy <= TOL64
+    assert g.step_count == 80
+
+
+def test_bad_state_is_reported_not_stepped(torch_cuda):
+    # a state with a node above the excluded-volume pole fails the first check
+    from paper_1307_6703_amd import LBError
+    _say("d2q17 unstable state")
+    g, o = _pair(32, 16, oracle=True, check_every=1)
+    f = o.S.copy()
+    f[0, 5, 7] += 3.0
+    g.set_populations(f)
+    g.step(1)
+    with pytest.raises(LBError) as e:
+        g.moments()
+    assert "LB_EUNSTABLE" in str(e.value)
+    with pytest.raises(LBError) as e:
+        g.step(1)
+    assert "LB_ESTATE" in str(e.value)
+
+
+def _shear_rate(Lx, U, tau=0.6, T=0.95, steps=400, amp=1e-5):
+    x = np.arange(Lx)
+    Ly = 4
+    n0 = np.full((Ly, Lx), 0.3)
+    ux0 = np.full((Ly, Lx), U)
+    uy0 = np.tile(amp * np.sin(2 * np.pi * x / Lx), (Ly, 1))
+    g, _ = _pair(Lx, Ly, T=T, tau=tau, kappa=0.0, V0=0.0, n0=n0, ux0=ux0, uy0=uy0,
+                 oracle=False)
+
+    def mode():
+        g.step(1)
+        return abs((g.moments()[2].mean(0) * np.exp(-2j * np.pi * x / Lx)).sum())
+
+    g.step(19)
+    a0 = mode()
+    g.step(steps - 1)
+    return -math.log(mode() / a0) / steps
+
+
+def test_viscosity_is_galilean_invariant(torch_cuda):
+    # the HIP path keeps the property the third-order model exists for: the
+    # shear wave's decay does not depend on a uniform flow along its wave vector
+    _say("d2q17 galilean invariance")
+    base = _shear_rate(64, 0.0)
+    for U in (0.05, 0.1):
+        assert abs(_shear_rate(64, U) / base - 1) < 1e-4
+
+
+def test_full_size_windows_against_the_oracle(torch_cuda):
+    """8192 x 2048 FP32 at the default launch, 10 steps; the oracle runs
+    periodic windows of 120 x 120 from the same initial fields, which are
+    exact farther than 5 nodes per step from their edges (pinned on the CPU);
+    three windows, one across the periodic corner."""
+    _say("d2q17 full size 8192x2048 fp32")
+    Lx, Ly, S, W = 8192, 2048, 10, 120
+    T, V0, k = 0.9, 0.01, 32
+    N, Q = ls.table1_nq(T)
+    n0 = ls.noisy_density(Lx, Ly, 1307)
+    fext = ls.potential_force(Lx, V0, k)
+    g, _ = _pair(Lx, Ly, T=T, V0=V0, k=k, fp32=True, n0=n0, oracle=False)
+    _say("default launch", g.get_launch())
+    m0 = g.reduce()["mass"]
+    g.step(S)
+    n, ux, uy = g.moments()
+    assert abs(g.reduce()["mass"] / m0 - 1) < 1e-6
+    m = 5 * S
+    for x0, y0 in ((1000, 500), (4000, 1900), (8192 - 60, 2048 - 60)):
+        xs = np.arange(x0, x0 + W) % Lx
+        ys = np.arange(y0, y0 + W) % Ly
+        o = o17.Oracle17(Params(W, W, T=T, tau=1.0, kappa=0.3, N=N, Q=Q, y_periodic=True),
+                         np.ascontiguousarray(n0[np.ix_(ys, xs)]), fext=fext[xs])
+        o.run(S, threads=8)
+        inner = (slice(m, W - m), slice(m, W - m))
+        gn = n[np.ix_(ys, xs)][inner]
+        rel = (np.abs(gn - o.n[inner]) / o.n[inner]).max()
+        du = max(np.abs(ux[np.ix_(ys, xs)][inner] - o.ux[inner]).max(),
+                 np.abs(uy[np.ix_(ys, xs)][inner] - o.uy[inner]).max())
+        _say(f"window ({x0},{y0}): rel dn {rel:.2e} |du| {du:.2e}")
+        assert rel <= TOL32 and du <= TOL32

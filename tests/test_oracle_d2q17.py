@@ -193,3 +193,31 @@ def test_rejects_walls_and_regularised_collision():
         o17.Oracle17(Params(8, 8, y_periodic=False), np.ones((8, 8)))
     with pytest.raises(ValueError):
         o17.Oracle17(Params(8, 8, y_periodic=True, regularized=True), np.ones((8, 8)))
+
+
+def test_window_runs_are_exact_inside_the_dependency_cone():
+    """A node's populations after a step depend on the stored populations at
+    most 5 nodes away (pull reach 3, force stencils 2): a periodic window run
+    from the same initial fields equals the full run bitwise on nodes farther
+    than 5 S from the window's edges after S steps. (Used by the full-size GPU
+    test to check 8192 x 2048.)"""
+    w, p = _quench(L=(96, 80))
+    n0, fext = w.n0(), w.fext()
+    x0, y0, wx, wy = 30, 20, 50, 46
+    pw = Params(wx, wy, T=p.T, tau=p.tau, kappa=p.kappa, N=p.N, Q=p.Q, y_periodic=True)
+    sub = (slice(None), slice(y0, y0 + wy), slice(x0, x0 + wx))
+    for S in (1, 4):
+        full = o17.Oracle17(p, n0, fext=fext)
+        full.run(S)
+        win = o17.Oracle17(pw, np.ascontiguousarray(n0[y0:y0 + wy, x0:x0 + wx]),
+                           fext=fext[x0:x0 + wx])
+        win.run(S)
+        m = 5 * S
+        inner = (slice(None), slice(m, wy - m), slice(m, wx - m))
+        assert np.array_equal(win.S[inner], full.S[sub][inner])
+        if S == 1:
+            # one node closer to the edge is already different: the cone is
+            # tight (after more steps the difference at its rim falls below
+            # rounding)
+            edge = (slice(None), slice(m - 1, wy - m + 1), slice(m - 1, wx - m + 1))
+            assert not np.array_equal(win.S[edge], full.S[sub][edge])

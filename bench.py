@@ -11,8 +11,9 @@ the checks.
 Order of the measurements: the step kernel alone (checks off) for the
 roofline, then, queued behind it on the same lattice with no idle gap, the
 --warmup and --steps of the headline with the checks; then the cost of a
-check, the other precisions on the same lattice, the batched sweep, the
-learned surrogate and the CPU oracle.
+check, the other precisions on the same lattice, the D2Q17 variant on its
+periodic workload of the same size, the batched sweep, the learned surrogate
+and the CPU oracle.
 
 The default launch runs two steps per launch (the two-step kernel keeps the
 first step's populations on chip). The roofline counts 72 algorithmic bytes
@@ -41,6 +42,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_UPDATE_FP32 = 72     # 9 populations read + 9 written, 4 B each
 BYTES_PER_UPDATE_FP64 = 144
+BYTES_PER_UPDATE_D2Q17_FP32 = 136   # 17 populations read + 17 written, 4 B each
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1307_6703_amd", "csrc", "lb_device.hip")
 TUNED = os.path.join(ROOT, "paper_1307_6703_amd", "tuned_launch.json")
@@ -229,6 +231,56 @@ def mode_bench(w, n0_dev, fext, prec: int, steps: int, check_every: int):
             "nmin": red["nmin"], "nmax": red["nmax"]}
 
 
+def d2q17_bench(steps: int, check_every: int):
+    """The D2Q17 variant (the third-order model named after Eq.(nav)) on its
+    workload, 8192 x 2048 periodic, FP32 storage, in its default launch:
+    `steps` timed steps with the FP64 checks and drift correction after 20
+    warm-up steps, then the same number without checks for the step kernel's
+    roofline at 136 algorithmic bytes per node update."""
+    import torch
+    import lbsynth as ls
+    from paper_1307_6703_amd import Lattice17
+    w = ls.D2Q17_WORKLOAD
+    lat = Lattice17(w.Lx, w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, fext=w.fext(),
+                    fp32=True, check_every=check_every, drift_correct=True)
+    lat.init(w.n0())
+    threads, rows, blocks = lat.get_launch()
+    m0 = lat.reduce()["mass"]
+    lat.step(20)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    lat.step(steps)
+    ev[1].record()
+    torch.cuda.synchronize()
+    red = lat.reduce()
+    lat.close()
+    # the kernel alone: a lattice without checks, queued steps
+    k = Lattice17(w.Lx, w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, fext=w.fext(),
+                  fp32=True)
+    k.init(w.n0())
+    k.step(20)
+    ev[2].record()
+    k.step(steps)
+    ev[3].record()
+    torch.cuda.synchronize()
+    k.close()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    k_ms = ev[2].elapsed_time(ev[3]) / steps
+    bpu = BYTES_PER_UPDATE_D2Q17_FP32
+    achieved = bpu * w.nodes / (k_ms * 1e-3) / 1e9
+    assert red["nonfinite"] == 0 and 0 < red["nmin"] and red["nmax"] < 3, red
+    return {"workload": w.name, "Lx": w.Lx, "Ly": w.Ly, "T": w.T, "V0": w.V0, "stripes": w.k,
+            "MLUPS": round(w.nodes / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 5),
+            "steps": steps, "checks": f"fp64 every {check_every} steps + drift correction",
+            "launch": {"threads": threads, "rows": rows, "workgroups": blocks,
+                       "steps_per_launch": 1},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "kernel": "step17_kernel<float, float, %d>" % threads,
+                         "us_per_launch": round(k_ms * 1e3, 2), "bytes_per_update": bpu},
+            "mass_drift": abs(red["mass"] - m0) / m0, "nmin": red["nmin"], "nmax": red["nmax"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,6 +312,8 @@ def main():
                     help="Adam steps of the surrogate's training; the learning-rate schedule "
                          "runs over them unless the time limit ends it first (then the result "
                          "depends on the device's speed)")
+    ap.add_argument("--d2q17-steps", type=int, default=400,
+                    help="timed steps of the D2Q17 variant on its workload (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (for scaling HBM counters)")
     args = ap.parse_args()
@@ -450,6 +504,11 @@ def main():
             print(f"[bench] {name}: {out['modes'][name]['MLUPS']} MLUPS, step kernel "
                   f"{out['modes'][name]['roofline']['us_per_launch']} us", file=sys.stderr, flush=True)
             torch.cuda.empty_cache()
+    if args.d2q17_steps > 0:
+        out["d2q17"] = d2q17_bench(args.d2q17_steps, args.check_every)
+        print(f"[bench] d2q17: {out['d2q17']['MLUPS']} MLUPS, step kernel "
+              f"{out['d2q17']['roofline']['us_per_launch']} us", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
     if args.batched_steps > 0:
         bl = tuple(int(v) for v in args.batched_launch.split(",")) if args.batched_launch else None
         out["batched"] = batched_bench(args.batched_steps, launch=bl)

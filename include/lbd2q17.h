@@ -107,8 +107,8 @@ lb_status lb17_get_populations(lb17_handle* h, double* f);
  * counter; resets the stability flag and the reference mass. */
 lb_status lb17_set_populations(lb17_handle* h, const double* f, int64_t step);
 
-/* Launch shape of the step kernel: threads per workgroup (64, 128 or 256;
- * strips of threads - 4 columns) and rows per workgroup (>= 1); 0 keeps the
+/* Launch shape of the step kernel: threads per workgroup (64, 128, 256 or
+ * 512; strips of threads - 4 columns) and rows per workgroup (>= 1); 0 keeps the
  * default. blocks: workgroups per step. */
 lb_status lb17_set_launch(lb17_handle* h, int32_t threads, int32_t rows);
 lb_status lb17_get_launch(lb17_handle* h, int32_t* threads, int32_t* rows, int32_t* blocks);

@@ -134,6 +134,13 @@ ROOFLINE = Workload("lb-fp32-8192x2048-walls", 8192, 2048, T=0.90, V0=0.1 * V0_S
                     note="V0 0.1 -> 0.01: as given the scheme diverges within ~300 steps")
 
 
+# The D2Q17 variant's workload: the headline lattice's size, temperature,
+# potential and noise, periodic in y (the paper's wall rule is D2Q9's).
+D2Q17_WORKLOAD = Workload("lb17-fp32-8192x2048-periodic", 8192, 2048, T=0.90,
+                          V0=0.1 * V0_STABLE_SCALE, k=32, U=0.0, y_periodic=True, steps=400,
+                          seed=1307, fp32=True, note="periodic in y: no D2Q17 wall rule")
+
+
 def batch_draws(count: int = 96, seed: int = 1307) -> List[Workload]:
     """Instances of the batched sweep. Draw order per instance: Lx, Ly, T, V0,
     k, U, noise seed."""

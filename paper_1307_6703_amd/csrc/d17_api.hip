@@ -95,20 +95,23 @@ Layout17 layout17(const lb_params* p) {
 
 int64_t nodes(const lb17_handle* h) { return (int64_t)h->p.Lx * h->p.Ly; }
 
-// Default launch: FP32 256-thread strips, FP64 128 (register budget); rows
-// so that the grid holds about 2048 workgroups, in multiples of 8, at least
-// 16 (each chunk re-reads 4 rows).
+// Default launch, from measurements on 8192 x 2048 (FP32) and 8192 x 1024
+// (FP64): wide strips where the lattice is wide (512 threads for FP32, 256
+// for FP64, whose registers allow fewer waves), narrower ones for narrow
+// lattices; rows so that the grid holds about 4096 (FP32) or 2048 (FP64)
+// workgroups, in multiples of 8, at least 8. Neighbouring chunks share the
+// rows they both read through the cache (alternating march directions).
 void launch_shape(const lb17_handle* h, int* threads, int* rows) {
-  const int t = h->threads ? h->threads : (h->fp32 ? 256 : 128);
+  const int Lx = h->p.Lx;
+  int t = h->threads;
+  if (!t) t = Lx >= 2048 ? (h->fp32 ? 512 : 256) : Lx >= 256 ? 256 : Lx >= 96 ? 128 : 64;
   int r = h->rows;
   if (!r) {
-    const int strips = (h->p.Lx + t - 5) / (t - 4);
-    const int chunks = std::max(1, 2048 / strips);
+    const int strips = (Lx + t - 5) / (t - 4);
+    const int chunks = std::max(1, (h->fp32 ? 4096 : 2048) / strips);
     r = (h->p.Ly + chunks - 1) / chunks;
-    r = std::max(16, (r + 7) / 8 * 8);
+    r = std::max(8, r / 8 * 8);
   }
-  // at most 65535 chunks (the grid's y dimension)
-  r = std::max(r, (h->p.Ly + 65534) / 65535);
   *threads = t;
   *rows = std::min(r, h->p.Ly);
 }
@@ -359,8 +362,8 @@ lb_status lb17_set_populations(lb17_handle* h, const double* f, int64_t step) {
 
 lb_status lb17_set_launch(lb17_handle* h, int32_t threads, int32_t rows) {
   if (!h) return fail(LB_EINVAL, "handle is NULL");
-  if (threads != 0 && threads != 64 && threads != 128 && threads != 256)
-    return fail(LB_EINVAL, "threads must be 0, 64, 128 or 256 (got %d)", threads);
+  if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512)
+    return fail(LB_EINVAL, "threads must be 0, 64, 128, 256 or 512 (got %d)", threads);
   if (rows < 0) return fail(LB_EINVAL, "rows must be >= 0");
   h->threads = threads;
   h->rows = rows;

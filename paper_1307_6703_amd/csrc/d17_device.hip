@@ -29,13 +29,16 @@
 // as deviations g_i = f_i - w^_i nbar (nbar = 0 in FP64 mode).
 //
 // Kernel design. A workgroup of NT threads owns a strip of NT - 4 columns and
-// a chunk of rows; thread t works on column x0 - 2 + t and marches along y.
-// Each iteration takes one row a through three stages:
-//   A (row a):   the 17 pulled values S_i(x - c_i) (loaded one iteration
-//                ahead into a register ring), density deviation and raw
-//                momentum;
-//   B (row a-1): Laplacian of n and the pressure term p^i - p^w;
-//   C (row a-2): force from the gradients of both, u*, collision, store.
+// a chunk of rows; thread t works on column x0 - 2 + t and marches along y
+// (upwards in even chunks, downwards in odd ones, so that neighbouring chunks
+// read the rows they share at about the same time; the XCD-aware tile order
+// puts them on the same XCD). Each iteration takes one row a through three
+// stages (d = the march direction):
+//   A (row a):     the 17 pulled values S_i(x - c_i) (loaded one iteration
+//                  ahead into a register ring), density deviation and raw
+//                  momentum;
+//   B (row a-d):   Laplacian of n and the pressure term p^i - p^w;
+//   C (row a-2d):  force from the gradients of both, u*, collision, store.
 // The density deviations and the B results live in three-row LDS rings; the
 // pulled values wait two rows in registers. Two barriers per row. The pull
 // reaches three rows and columns: every load comes straight from the
@@ -126,15 +129,16 @@ __device__ __forceinline__ A rcp(A x) { return (A)1 / x; }
 template <>
 __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Per-lattice constants in the arithmetic precision.
+// Per-lattice constants in the arithmetic precision, converted on the host
+// and passed as a kernel argument, so they stay in scalar registers.
 template <typename A>
 struct K17 {
   A nbar, T, ps, keep, pre, om, kap, N, M, Q, Rw, Q4R, h1, h2, h3, half;
-  A w[5], owr[5], a1[5];
+  A w[5], wr[5], owr[5], a1[5];
 };
 
 template <typename A>
-__device__ __forceinline__ K17<A> make_k17(const Desc17& d) {
+static K17<A> make_k17(const Desc17& d) {
   K17<A> k;
   k.nbar = (A)d.nbar;
   k.T = (A)d.T;
@@ -155,6 +159,7 @@ __device__ __forceinline__ K17<A> make_k17(const Desc17& d) {
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
     k.w[j] = (A)d.w[j];
+    k.wr[j] = (A)d.wr[j];
     k.owr[j] = (A)d.owr[j];
     k.a1[j] = (A)d.a1[j];
   }
@@ -223,10 +228,11 @@ __device__ __forceinline__ void collide17(A (&g)[17], const K17<A>& k, A n, A dn
 // (K + 2) & 3, and row a + 1's are loaded into slot (K + 1) & 3.
 template <typename S, typename A, int NT, int K>
 __device__ __forceinline__ void iter17(
-    int a, int q, const Desc17& d, const K17<A>& k, A (&g)[4][17], A (&mx)[4], A (&my)[4],
-    A (&nR)[3][NT], A (&PR)[3][NT], A (&LR)[3][NT], __amdgpu_buffer_rsrc_t src,
-    __amdgpu_buffer_rsrc_t dst, uint32_t rb, uint32_t pb, const int (&vcol)[7], int voff_own,
-    bool own, int y0, int ae, A shift, A fx, int flags, double* mom, int xs) {
+    int it, int nit, int dir, int a, int q, const Desc17& d, const K17<A>& k, A (&g)[4][17],
+    A (&mx)[4], A (&my)[4], A (&nR)[3][NT], A (&PR)[3][NT], A (&LR)[3][NT],
+    __amdgpu_buffer_rsrc_t src, __amdgpu_buffer_rsrc_t dst, uint32_t rb, uint32_t pb,
+    const int (&vcol)[7], int voff_own, bool own, A shift, A fx, int flags, double* mom,
+    int xs) {
   const int t = threadIdx.x;
   const int Ly = d.Ly;
   // A: row a
@@ -234,7 +240,7 @@ __device__ __forceinline__ void iter17(
     A (&v)[17] = g[K];
     if (flags & kApplyShift) {
 #pragma unroll
-      for (int i = 0; i < 17; ++i) v[i] += (A)d.wr[shell17(i)] * shift;
+      for (int i = 0; i < 17; ++i) v[i] += k.wr[shell17(i)] * shift;
     }
     A s0 = v[0], sx = (A)0, sy = (A)0;
 #pragma unroll
@@ -247,38 +253,43 @@ __device__ __forceinline__ void iter17(
     mx[K] = sx;
     my[K] = sy;
   }
-  if (a + 1 <= ae) {
-    int ra = a + 1;
+  if (it + 1 < nit) {
+    int ra = a + dir;
     ra = ra < 0 ? ra + Ly : (ra >= Ly ? ra - Ly : ra);
     pull17<S, A>(g[(K + 1) & 3], src, ra, Ly, rb, pb, vcol);
   }
-  const int q1 = q == 0 ? 2 : q - 1;  // row a - 1
-  const int q2 = q == 2 ? 0 : q + 1;  // row a - 2 (and a + 1)
+  const int q1 = q == 0 ? 2 : q - 1;  // row a - dir
+  const int q2 = q == 2 ? 0 : q + 1;  // row a - 2 dir (and a + dir)
   __syncthreads();
-  // B: row a - 1
-  if (a >= y0 && t >= 1 && t <= NT - 2) {
+  // B: row a - dir
+  if (it >= 2 && t >= 1 && t <= NT - 2) {
     const A c = nR[q1][t];
-    const A L = k.Q * (nR[q1][t + 1] + nR[q1][t - 1] + nR[q][t] + nR[q2][t]) +
-                k.Rw * (nR[q][t + 1] + nR[q][t - 1] + nR[q2][t + 1] + nR[q2][t - 1]) -
+    // grouped by rows, so a march in the other direction rounds the same
+    const A L = k.Q * ((nR[q1][t + 1] + nR[q1][t - 1]) + (nR[q][t] + nR[q2][t])) +
+                k.Rw * ((nR[q][t + 1] + nR[q][t - 1]) + (nR[q2][t + 1] + nR[q2][t - 1])) -
                 k.Q4R * c;
     const A n = k.nbar + c;
     LR[q1][t] = L;
     PR[q1][t] = n * n * ((A)1.125 - k.T * rcp((A)3 - n)) * k.ps;
   }
   __syncthreads();
-  // C: row r = a - 2; LP rows r - 1, r, r + 1 are in slots q, q2, q1
-  if (a >= y0 + 2 && t >= 2 && t <= NT - 3) {
-    const int r = a - 2;
+  // C: row r = a - 2 dir; B's rows r - dir, r, r + dir are in slots q, q2, q1
+  // (the y differences are taken along the march and carry its sign; every
+  // sum over the two neighbour rows is grouped by row, so both march
+  // directions round the same)
+  if (it >= 4 && t >= 2 && t <= NT - 3) {
+    const int r = a - 2 * dir;
     const A dn = nR[q2][t];
     const A n = k.nbar + dn;
+    const A sy = (A)dir;
     const A gPx = k.N * (PR[q2][t + 1] - PR[q2][t - 1]) +
-                  k.M * (PR[q1][t + 1] - PR[q1][t - 1] + PR[q][t + 1] - PR[q][t - 1]);
-    const A gPy = k.N * (PR[q1][t] - PR[q][t]) +
-                  k.M * (PR[q1][t + 1] - PR[q][t + 1] + PR[q1][t - 1] - PR[q][t - 1]);
+                  k.M * ((PR[q1][t + 1] - PR[q1][t - 1]) + (PR[q][t + 1] - PR[q][t - 1]));
+    const A gPy = sy * (k.N * (PR[q1][t] - PR[q][t]) +
+                        k.M * ((PR[q1][t + 1] - PR[q][t + 1]) + (PR[q1][t - 1] - PR[q][t - 1])));
     const A gLx = k.N * (LR[q2][t + 1] - LR[q2][t - 1]) +
-                  k.M * (LR[q1][t + 1] - LR[q1][t - 1] + LR[q][t + 1] - LR[q][t - 1]);
-    const A gLy = k.N * (LR[q1][t] - LR[q][t]) +
-                  k.M * (LR[q1][t + 1] - LR[q][t + 1] + LR[q1][t - 1] - LR[q][t - 1]);
+                  k.M * ((LR[q1][t + 1] - LR[q1][t - 1]) + (LR[q][t + 1] - LR[q][t - 1]));
+    const A gLy = sy * (k.N * (LR[q1][t] - LR[q][t]) +
+                        k.M * ((LR[q1][t + 1] - LR[q][t + 1]) + (LR[q1][t - 1] - LR[q][t - 1])));
     const A Fx = gPx + k.kap * n * gLx + fx;
     const A Fy = gPy + k.kap * n * gLy;
     constexpr int KC = (K + 2) & 3;
@@ -301,16 +312,28 @@ __device__ __forceinline__ void iter17(
 }
 
 template <typename S, typename A, int NT>
-__global__ __launch_bounds__(NT) void step17_kernel(Desc17 d, int parity, int rows, int flags,
-                                                    double* mom) {
+__global__ __launch_bounds__(NT) void step17_kernel(Desc17 d, K17<A> k, int parity, int rows,
+                                                    int chunks, int flags, double* mom) {
   __shared__ A nR[3][NT];
   __shared__ A PR[3][NT];
   __shared__ A LR[3][NT];
   const int t = threadIdx.x;
   const int Lx = d.Lx, Ly = d.Ly;
-  const int x0 = blockIdx.x * (NT - 4);
-  const int y0 = blockIdx.y * rows;
+  // Workgroups are dealt round-robin over the 8 XCDs; each XCD takes a
+  // contiguous run of tiles in row-of-chunks order (all strips of a chunk row,
+  // then the next chunk row), so neighbouring strips, which share the cache
+  // lines at their edges, run together on one XCD; odd chunks march
+  // downwards, so the rows two neighbouring chunks both read are read at
+  // about the same time.
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int qb = nb >> 3, rm = nb & 7, xcd = b & 7;
+  const int tile = xcd * qb + (xcd < rm ? xcd : rm) + (b >> 3);
+  const int strips = nb / chunks;
+  const int chunk = tile / strips, strip = tile - chunk * strips;
+  const int x0 = strip * (NT - 4);
+  const int y0 = chunk * rows;
   const int y1 = min(y0 + rows, Ly);
+  const int dir = (chunk & 1) ? -1 : 1;
   const int xu = x0 - 2 + t;  // unwrapped column
   int xs = xu % Lx;
   if (xs < 0) xs += Lx;
@@ -326,33 +349,35 @@ __global__ __launch_bounds__(NT) void step17_kernel(Desc17 d, int parity, int ro
   const int nbytes = (int)(rb * (uint32_t)Ly);
   const __amdgpu_buffer_rsrc_t src = rsrc(d.S[parity], nbytes);
   const __amdgpu_buffer_rsrc_t dst = rsrc(d.S[parity ^ 1], nbytes);
-  const K17<A> k = make_k17<A>(d);
   const A fx = (A)d.fext[xs];
   const A shift = (flags & kApplyShift) ? (A)*d.shift : (A)0;
 
   A g[4][17];
   A mx[4], my[4];
-  const int ab = y0 - 2, ae = y1 + 1;
+  // rows y0 - 2 .. y1 + 1 in the march direction
+  const int nit = y1 - y0 + 4;
+  const int ab = dir > 0 ? y0 - 2 : y1 + 1;
   {
-    int ra = ab < 0 ? ab + Ly : ab;
+    const int ra = ab < 0 ? ab + Ly : (ab >= Ly ? ab - Ly : ab);
     pull17<S, A>(g[0], src, ra, Ly, rb, pb, vcol);
   }
-  int q = 0;  // LDS ring slot of row a: (a - ab) mod 3
-  for (int a = ab; a <= ae; a += 4) {
-    iter17<S, A, NT, 0>(a, q, d, k, g, mx, my, nR, PR, LR, src, dst, rb, pb, vcol, vcol[3], own,
-                        y0, ae, shift, fx, flags, mom, xs);
+  int q = 0;  // LDS ring slot of row a: it mod 3
+  for (int it = 0; it < nit; it += 4) {
+    const int a = ab + dir * it;
+    iter17<S, A, NT, 0>(it, nit, dir, a, q, d, k, g, mx, my, nR, PR, LR, src, dst, rb, pb, vcol,
+                        vcol[3], own, shift, fx, flags, mom, xs);
     q = q == 2 ? 0 : q + 1;
-    if (a + 1 > ae) break;
-    iter17<S, A, NT, 1>(a + 1, q, d, k, g, mx, my, nR, PR, LR, src, dst, rb, pb, vcol, vcol[3],
-                        own, y0, ae, shift, fx, flags, mom, xs);
+    if (it + 1 >= nit) break;
+    iter17<S, A, NT, 1>(it + 1, nit, dir, a + dir, q, d, k, g, mx, my, nR, PR, LR, src, dst, rb,
+                        pb, vcol, vcol[3], own, shift, fx, flags, mom, xs);
     q = q == 2 ? 0 : q + 1;
-    if (a + 2 > ae) break;
-    iter17<S, A, NT, 2>(a + 2, q, d, k, g, mx, my, nR, PR, LR, src, dst, rb, pb, vcol, vcol[3],
-                        own, y0, ae, shift, fx, flags, mom, xs);
+    if (it + 2 >= nit) break;
+    iter17<S, A, NT, 2>(it + 2, nit, dir, a + 2 * dir, q, d, k, g, mx, my, nR, PR, LR, src, dst,
+                        rb, pb, vcol, vcol[3], own, shift, fx, flags, mom, xs);
     q = q == 2 ? 0 : q + 1;
-    if (a + 3 > ae) break;
-    iter17<S, A, NT, 3>(a + 3, q, d, k, g, mx, my, nR, PR, LR, src, dst, rb, pb, vcol, vcol[3],
-                        own, y0, ae, shift, fx, flags, mom, xs);
+    if (it + 3 >= nit) break;
+    iter17<S, A, NT, 3>(it + 3, nit, dir, a + 3 * dir, q, d, k, g, mx, my, nR, PR, LR, src, dst,
+                        rb, pb, vcol, vcol[3], own, shift, fx, flags, mom, xs);
     q = q == 2 ? 0 : q + 1;
   }
 }
@@ -360,17 +385,23 @@ __global__ __launch_bounds__(NT) void step17_kernel(Desc17 d, int parity, int ro
 template <typename S, typename A>
 static hipError_t launch_t(int threads, int rows, const Desc17& d, int parity, int flags,
                            double* mom, hipStream_t st) {
-  const dim3 grid((d.Lx + threads - 5) / (threads - 4), (d.Ly + rows - 1) / rows);
-  if (grid.y > 65535u) return hipErrorInvalidValue;
+  const int64_t strips = (d.Lx + threads - 5) / (threads - 4);
+  const int64_t chunks = (d.Ly + rows - 1) / rows;
+  if (strips * chunks > INT32_MAX) return hipErrorInvalidValue;
+  const int grid = (int)(strips * chunks);
+  const K17<A> k = make_k17<A>(d);
   switch (threads) {
     case 64:
-      step17_kernel<S, A, 64><<<grid, 64, 0, st>>>(d, parity, rows, flags, mom);
+      step17_kernel<S, A, 64><<<grid, 64, 0, st>>>(d, k, parity, rows, (int)chunks, flags, mom);
       break;
     case 128:
-      step17_kernel<S, A, 128><<<grid, 128, 0, st>>>(d, parity, rows, flags, mom);
+      step17_kernel<S, A, 128><<<grid, 128, 0, st>>>(d, k, parity, rows, (int)chunks, flags, mom);
       break;
     case 256:
-      step17_kernel<S, A, 256><<<grid, 256, 0, st>>>(d, parity, rows, flags, mom);
+      step17_kernel<S, A, 256><<<grid, 256, 0, st>>>(d, k, parity, rows, (int)chunks, flags, mom);
+      break;
+    case 512:
+      step17_kernel<S, A, 512><<<grid, 512, 0, st>>>(d, k, parity, rows, (int)chunks, flags, mom);
       break;
     default:
       return hipErrorInvalidValue;

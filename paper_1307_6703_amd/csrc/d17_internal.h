@@ -41,8 +41,9 @@ void lattice17(int cx[17], int cy[17], double w[17], double* s);
 double rest_weight17(int i, double T);
 
 // One time step over the whole lattice: strips of threads - 4 columns,
-// chunks of `rows` rows; reads S[parity], writes S[parity ^ 1]; with
-// kWriteMoments also n, ux, uy (FP64 planes) into mom. threads: 64, 128 or 256.
+// chunks of `rows` rows (one workgroup each, in XCD-aware order); reads S[parity], writes S[parity ^ 1]; with
+// kWriteMoments also n, ux, uy (FP64 planes) into mom. threads: 64, 128, 256
+// or 512.
 hipError_t launch_step17(bool fp32, int threads, int rows, const Desc17& d, int parity, int flags,
                          double* mom, hipStream_t st);
 hipError_t launch_init17(bool fp32, const Desc17& d, int parity, const double* n0,

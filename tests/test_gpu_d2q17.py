@@ -109,7 +109,7 @@ def test_fp64_parity_long_quench(torch_cuda):
 def test_launch_shapes_give_the_same_bits(torch_cuda, fp32):
     _say("d2q17 launch shapes", "fp32" if fp32 else "fp64")
     ref = None
-    for launch in ((64, 8), (128, 40), (256, 200), (256, 16)):
+    for launch in ((64, 8), (128, 40), (256, 200), (256, 16), (512, 8)):
         g, _ = _pair(300, 200, fp32=fp32, launch=launch, oracle=False)
         g.step(12)
         f = g.populations()

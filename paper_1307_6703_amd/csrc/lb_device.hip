@@ -801,6 +801,17 @@ hipError_t launch_step2(int threads, const Desc* d_descs, const Tile* d_tiles, i
 // everything the two-step kernel compiles from.
 // ---------------------------------------------------------------------------
 
+// Population stores of the one-step kernel: FP64 values with the
+// non-temporal bit, so the written planes do not displace rows that
+// neighbouring chunks still read; FP32 values as they are.
+__device__ __forceinline__ void pop_st(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  buf_st(v, r, voff, soff);
+}
+__device__ __forceinline__ void pop_st(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, 2);
+}
+
 // Counter-based random numbers for the stochastic rounding: the pcg4d hash of
 // Jarzynski and Olano ("Hash Functions for GPU Rendering", JCGT 9(3), 2020),
 // applied to (column, row, step, 0), so every node, step and population gets
@@ -1139,7 +1150,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? LB_WAVES_PER_SIMD : 1) void st
             buf_st(round_stochastic(g[i], q[i]), so, vst, (int)((uint32_t)i * pbytes + roff));
         } else {
 #pragma unroll
-          for (int i = 0; i < 9; ++i) buf_st(g[i], so, vst, (int)((uint32_t)i * pbytes + roff));
+          for (int i = 0; i < 9; ++i) pop_st(g[i], so, vst, (int)((uint32_t)i * pbytes + roff));
         }
         if (MOM) {
           const int momb = (int)(3 * nn * 8);

@@ -36,9 +36,9 @@ def torch_cuda():
 
 
 def _pair(Lx, Ly, *, T=0.9, tau=1.0, kappa=0.3, V0=0.01, k=2, fp32=False, seed=1307,
-          launch=None, n0=None, ux0=None, uy0=None, oracle=True, **extra):
+          launch=None, n0=None, ux0=None, uy0=None, oracle=True, NQ=None, **extra):
     from paper_1307_6703_amd import Lattice17
-    N, Q = ls.table1_nq(T)
+    N, Q = NQ if NQ else ls.table1_nq(T)
     fext = ls.potential_force(Lx, V0, k)
     if n0 is None:
         n0 = ls.noisy_density(Lx, Ly, seed)
@@ -82,6 +82,21 @@ def test_fp64_parity_ragged_shapes(torch_cuda, Lx, Ly, threads, rows, V0):
         _say(f"step {upto}: |dn| {dn:.2e} |dux| {dux:.2e} |duy| {duy:.2e}")
         assert dn <= TOL64 and dux <= TOL64 and duy <= TOL64
     assert np.abs(g.populations() - o.S).max() <= TOL64
+
+
+@pytest.mark.parametrize("T,tau,kappa", [(1.2, 0.7, 0.5), (0.95, 2.0, 0.1)])
+def test_fp64_parity_other_parameters(torch_cuda, T, tau, kappa):
+    # above the critical temperature (every rest weight positive) and at a
+    # long relaxation time with a weak square-gradient term, on a ragged
+    # lattice in 128-thread strips; stencil (N, Q) = (0.3, 2.0)
+    _say("d2q17 fp64 params", T, tau, kappa)
+    g, o = _pair(203, 77, T=T, tau=tau, kappa=kappa, V0=0.02, k=3, launch=(128, 24),
+                 NQ=(0.3, 2.0))
+    g.step(200)
+    o.run(200, threads=8)
+    dn, dux, duy, _ = _cmp(g, o)
+    _say(f"step 200: |dn| {dn:.2e} |dux| {dux:.2e} |duy| {duy:.2e}")
+    assert dn <= TOL64 and dux <= TOL64 and duy <= TOL64
 
 
 def test_fp64_parity_long_quench(torch_cuda):
@@ -256,3 +271,32 @@ def test_full_size_windows_against_the_oracle(torch_cuda):
                  np.abs(uy[np.ix_(ys, xs)][inner] - o.uy[inner]).max())
         _say(f"window ({x0},{y0}): rel dn {rel:.2e} |du| {du:.2e}")
         assert rel <= TOL32 and du <= TOL32
+
+
+def test_full_size_fp64_windows_against_the_oracle(torch_cuda):
+    """8192 x 1024 FP64 (the largest FP64 lattice the 2 GiB buffer rule
+    allows at this width) at the default launch, 8 steps; periodic 100 x 100
+    oracle windows, exact farther than 5 nodes per step from their edges."""
+    _say("d2q17 full size 8192x1024 fp64")
+    Lx, Ly, S, W = 8192, 1024, 8, 100
+    T, V0, k = 0.9, 0.01, 32
+    N, Q = ls.table1_nq(T)
+    n0 = ls.noisy_density(Lx, Ly, 99)
+    fext = ls.potential_force(Lx, V0, k)
+    g, _ = _pair(Lx, Ly, T=T, V0=V0, k=k, fp32=False, n0=n0, oracle=False)
+    _say("default launch", g.get_launch())
+    g.step(S)
+    n, ux, uy = g.moments()
+    m = 5 * S
+    for x0, y0 in ((2500, 300), (8192 - 50, 1024 - 50)):
+        xs = np.arange(x0, x0 + W) % Lx
+        ys = np.arange(y0, y0 + W) % Ly
+        o = o17.Oracle17(Params(W, W, T=T, tau=1.0, kappa=0.3, N=N, Q=Q, y_periodic=True),
+                         np.ascontiguousarray(n0[np.ix_(ys, xs)]), fext=fext[xs])
+        o.run(S, threads=8)
+        inner = (slice(m, W - m), slice(m, W - m))
+        dn = np.abs(n[np.ix_(ys, xs)][inner] - o.n[inner]).max()
+        du = max(np.abs(ux[np.ix_(ys, xs)][inner] - o.ux[inner]).max(),
+                 np.abs(uy[np.ix_(ys, xs)][inner] - o.uy[inner]).max())
+        _say(f"window ({x0},{y0}): |dn| {dn:.2e} |du| {du:.2e}")
+        assert dn <= TOL64 and du <= TOL64

@@ -264,8 +264,21 @@ def d2q17_bench(steps: int, check_every: int):
     ev[3].record()
     torch.cuda.synchronize()
     k.close()
+    # FP32 storage with FP64 arithmetic and stochastic rounding, kernel alone
+    sr = Lattice17(w.Lx, w.Ly, T=w.T, tau=w.tau, kappa=w.kappa, N=w.N, Q=w.Q, fext=w.fext(),
+                   fp32="sr")
+    sr.init(w.n0())
+    sr_launch = sr.get_launch()
+    sr.step(20)
+    e4, e5 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e4.record()
+    sr.step(steps)
+    e5.record()
+    torch.cuda.synchronize()
+    sr.close()
     ms = ev[0].elapsed_time(ev[1]) / steps
     k_ms = ev[2].elapsed_time(ev[3]) / steps
+    sr_ms = e4.elapsed_time(e5) / steps
     bpu = BYTES_PER_UPDATE_D2Q17_FP32
     achieved = bpu * w.nodes / (k_ms * 1e-3) / 1e9
     assert red["nonfinite"] == 0 and 0 < red["nmin"] and red["nmax"] < 3, red
@@ -278,7 +291,13 @@ def d2q17_bench(steps: int, check_every: int):
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                          "kernel": "step17_kernel<float, float, %d>" % threads,
                          "us_per_launch": round(k_ms * 1e3, 2), "bytes_per_update": bpu},
-            "mass_drift": abs(red["mass"] - m0) / m0, "nmin": red["nmin"], "nmax": red["nmax"]}
+            "mass_drift": abs(red["mass"] - m0) / m0, "nmin": red["nmin"], "nmax": red["nmax"],
+            "fp32_storage_fp64_arithmetic_sr": {
+                "MLUPS_kernel": round(w.nodes / (sr_ms * 1e-3) / 1e6, 1),
+                "us_per_launch": round(sr_ms * 1e3, 2),
+                "achieved_gbs": round(bpu * w.nodes / (sr_ms * 1e-3) / 1e9, 1),
+                "launch": {"threads": sr_launch[0], "rows": sr_launch[1],
+                           "workgroups": sr_launch[2]}}}
 
 
 def main():

@@ -43,10 +43,15 @@
  *
  * Precision: lb_params.fp32 = 0 stores and computes in FP64; fp32 = 1 stores
  * g_i = f_i - w^_i nbar in FP32 (w^_i the rest-state weights at T, nbar the
- * mean density) and computes in FP32. Mass and momentum checks are FP64.
+ * mean density) and computes in FP32; fp32 = 2 stores the same FP32
+ * deviations but computes in FP64 and rounds each stored value
+ * stochastically (as in lbvdw.h: the draws come from a counter-based hash of
+ * column, row and step, so runs are deterministic and independent of the
+ * launch shape, and a restart with lb17_set_populations continues with the
+ * draws of its step). Mass and momentum checks are FP64.
  *
  * Parameters: lb_params of lbvdw.h with y_periodic = 1, U = 0, collision = 0,
- * fp32 in {0, 1}, Ly >= 4, 17 Lx Ly (4 or 8) bytes < 2 GiB, sqrt(s) tau > 1/2,
+ * fp32 in {0, 1, 2}, Ly >= 4, 17 Lx Ly (4 or 8) bytes < 2 GiB, sqrt(s) tau > 1/2,
  * the other fields as documented there (check_every and drift_correct
  * included).
  *

@@ -21,7 +21,8 @@ struct lb17_handle {
   lb_params p;
   hipStream_t st;
   Desc17 d;
-  bool fp32;
+  bool fp32;        // FP32 storage (fp32 = 1 or 2)
+  int prec;         // lb_params.fp32
   double* fext;     // device, Lx values (F_ext,x / s)
   double* part;     // device, reduce partials
   Reduce17* red;    // device
@@ -51,7 +52,7 @@ lb_status validate17(const lb_params* p) {
     return fail(LB_EINVAL, "D2Q17 lattices are periodic in y (the wall rule is D2Q9's)");
   if (p->U != 0.0) return fail(LB_EINVAL, "D2Q17 lattices have no walls: U must be 0");
   if (p->collision != 0) return fail(LB_EINVAL, "D2Q17 lattices collide with BGK only");
-  if (p->fp32 != 0 && p->fp32 != 1) return fail(LB_EINVAL, "fp32 must be 0 or 1 (got %d)", p->fp32);
+  if (p->fp32 < 0 || p->fp32 > 2) return fail(LB_EINVAL, "fp32 must be 0, 1 or 2 (got %d)", p->fp32);
   if ((int64_t)p->Lx * p->Ly * 17 * (p->fp32 ? 4 : 8) >= ((int64_t)1 << 31))
     return fail(LB_EINVAL, "17*Lx*Ly*(4|8) bytes must be < 2 GiB");
   if (!(p->T > 0.0 && p->T <= 1.5)) return fail(LB_EINVAL, "T must be in (0, 1.5] (got %g)", p->T);
@@ -96,19 +97,21 @@ Layout17 layout17(const lb_params* p) {
 int64_t nodes(const lb17_handle* h) { return (int64_t)h->p.Lx * h->p.Ly; }
 
 // Default launch, from measurements on 8192 x 2048 (FP32) and 8192 x 1024
-// (FP64): wide strips where the lattice is wide (512 threads for FP32, 256
-// for FP64, whose registers allow fewer waves), narrower ones for narrow
-// lattices; rows so that the grid holds about 4096 (FP32) or 2048 (FP64)
-// workgroups, in multiples of 8, at least 8. Neighbouring chunks share the
-// rows they both read through the cache (alternating march directions).
+// (FP64): wide strips where the lattice is wide (512 threads for FP32
+// arithmetic, 256 for FP64 arithmetic, whose registers allow fewer waves),
+// narrower ones for narrow lattices; rows so that the grid holds about 4096
+// (FP32) or 2048 (FP64 arithmetic) workgroups, in multiples of 8, at least 8.
+// Neighbouring chunks share the rows they both read through the cache
+// (alternating march directions).
 void launch_shape(const lb17_handle* h, int* threads, int* rows) {
   const int Lx = h->p.Lx;
+  const bool a32 = h->prec == 1;  // FP32 arithmetic
   int t = h->threads;
-  if (!t) t = Lx >= 2048 ? (h->fp32 ? 512 : 256) : Lx >= 256 ? 256 : Lx >= 96 ? 128 : 64;
+  if (!t) t = Lx >= 2048 ? (a32 ? 512 : 256) : Lx >= 256 ? 256 : Lx >= 96 ? 128 : 64;
   int r = h->rows;
   if (!r) {
     const int strips = (Lx + t - 5) / (t - 4);
-    const int chunks = std::max(1, (h->fp32 ? 4096 : 2048) / strips);
+    const int chunks = std::max(1, (a32 ? 4096 : 2048) / strips);
     r = (h->p.Ly + chunks - 1) / chunks;
     r = std::max(8, r / 8 * 8);
   }
@@ -218,7 +221,8 @@ lb_status lb17_create(const lb_params* p, void* dev_ws, size_t ws_bytes, void* h
   h->p = *p;
   h->p.fext_x = nullptr;
   h->st = (hipStream_t)hip_stream;
-  h->fp32 = p->fp32 == 1;
+  h->fp32 = p->fp32 != 0;
+  h->prec = p->fp32;
   char* ws = (char*)dev_ws;
   h->red = (Reduce17*)(ws + L.red);
   h->fext = (double*)(ws + L.fext);
@@ -277,7 +281,8 @@ lb_status lb17_step_n(lb17_handle* h, int64_t nsteps) {
   for (int64_t k = 0; k < nsteps; ++k) {
     int flags = (k == nsteps - 1) ? d17k::kWriteMoments : 0;
     if (h->pending_shift) flags |= d17k::kApplyShift;
-    HIPCHK(d17k::launch_step17(h->fp32, threads, rows, h->d, h->parity, flags, h->mom, h->st));
+    HIPCHK(d17k::launch_step17(h->prec, threads, rows, h->d, h->parity, flags, h->mom,
+                               (uint32_t)h->step, h->st));
     h->parity ^= 1;
     h->pending_shift = false;
     h->step += 1;

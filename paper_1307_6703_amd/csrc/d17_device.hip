@@ -50,6 +50,7 @@
 #include <cstdint>
 
 #include "d17_internal.h"
+#include "lb_rng.h"
 
 namespace d17k {
 
@@ -229,13 +230,13 @@ __device__ __forceinline__ void collide17(A (&g)[17], const K17<A>& k, A n, A dn
 // One row iteration of the march (stages A, B, C of the file header). K: the
 // register slot holding row a's pulled values; row a - 2's are in slot
 // (K + 2) & 3, and row a + 1's are loaded into slot (K + 1) & 3.
-template <typename S, typename A, int NT, int K>
+template <typename S, typename A, int NT, int K, bool SR>
 __device__ __forceinline__ void iter17(
     int it, int nit, int dir, int a, int q, const Desc17& d, const K17<A>& k, A (&g)[4][17],
     A (&mx)[4], A (&my)[4], A (&nR)[3][NT], A (&PR)[3][NT], A (&LR)[3][NT],
     __amdgpu_buffer_rsrc_t src, __amdgpu_buffer_rsrc_t dst, uint32_t rb, uint32_t pb,
     const int (&vcol)[7], int voff_own, bool own, A shift, A fx, int flags, double* mom,
-    int xs) {
+    int xs, uint32_t rstep) {
   const int t = threadIdx.x;
   const int Ly = d.Ly;
   // A: row a
@@ -301,8 +302,19 @@ __device__ __forceinline__ void iter17(
     collide17<A>(g[KC], k, n, dn, jx, jy, rn, Fx, Fy);
     if (own) {
       const uint32_t ro = (uint32_t)r * rb;
+      if constexpr (SR) {
+        // 17 draws of 14 bits from two hashes of (column, row, step, 0 | 1)
+        uint32_t q[18];
+        lbrng::draws14(lbrng::pcg4d(lbrng::U4{(uint32_t)xs, (uint32_t)r, rstep, 0u}), q);
+        lbrng::draws14(lbrng::pcg4d(lbrng::U4{(uint32_t)xs, (uint32_t)r, rstep, 1u}), q + 9);
 #pragma unroll
-      for (int i = 0; i < 17; ++i) st((S)g[KC][i], dst, voff_own, (int)(ro + (uint32_t)i * pb));
+        for (int i = 0; i < 17; ++i)
+          st(lbrng::round_stochastic((double)g[KC][i], q[i]), dst, voff_own,
+             (int)(ro + (uint32_t)i * pb));
+      } else {
+#pragma unroll
+        for (int i = 0; i < 17; ++i) st((S)g[KC][i], dst, voff_own, (int)(ro + (uint32_t)i * pb));
+      }
       if (flags & kWriteMoments) {
         const int64_t o = (int64_t)r * d.Lx + xs;
         const int64_t nn = (int64_t)d.Lx * Ly;
@@ -314,9 +326,10 @@ __device__ __forceinline__ void iter17(
   }
 }
 
-template <typename S, typename A, int NT>
+template <typename S, typename A, int NT, bool SR>
 __global__ __launch_bounds__(NT) void step17_kernel(Desc17 d, K17<A> k, int parity, int rows,
-                                                    int chunks, int flags, double* mom) {
+                                                    int chunks, int flags, double* mom,
+                                                    uint32_t rstep) {
   __shared__ A nR[3][NT];
   __shared__ A PR[3][NT];
   __shared__ A LR[3][NT];
@@ -367,27 +380,27 @@ __global__ __launch_bounds__(NT) void step17_kernel(Desc17 d, K17<A> k, int pari
   int q = 0;  // LDS ring slot of row a: it mod 3
   for (int it = 0; it < nit; it += 4) {
     const int a = ab + dir * it;
-    iter17<S, A, NT, 0>(it, nit, dir, a, q, d, k, g, mx, my, nR, PR, LR, src, dst, rb, pb, vcol,
-                        vcol[3], own, shift, fx, flags, mom, xs);
+    iter17<S, A, NT, 0, SR>(it, nit, dir, a, q, d, k, g, mx, my, nR, PR, LR, src, dst, rb, pb, vcol,
+                        vcol[3], own, shift, fx, flags, mom, xs, rstep);
     q = q == 2 ? 0 : q + 1;
     if (it + 1 >= nit) break;
-    iter17<S, A, NT, 1>(it + 1, nit, dir, a + dir, q, d, k, g, mx, my, nR, PR, LR, src, dst, rb,
-                        pb, vcol, vcol[3], own, shift, fx, flags, mom, xs);
+    iter17<S, A, NT, 1, SR>(it + 1, nit, dir, a + dir, q, d, k, g, mx, my, nR, PR, LR, src, dst, rb,
+                        pb, vcol, vcol[3], own, shift, fx, flags, mom, xs, rstep);
     q = q == 2 ? 0 : q + 1;
     if (it + 2 >= nit) break;
-    iter17<S, A, NT, 2>(it + 2, nit, dir, a + 2 * dir, q, d, k, g, mx, my, nR, PR, LR, src, dst,
-                        rb, pb, vcol, vcol[3], own, shift, fx, flags, mom, xs);
+    iter17<S, A, NT, 2, SR>(it + 2, nit, dir, a + 2 * dir, q, d, k, g, mx, my, nR, PR, LR, src, dst,
+                        rb, pb, vcol, vcol[3], own, shift, fx, flags, mom, xs, rstep);
     q = q == 2 ? 0 : q + 1;
     if (it + 3 >= nit) break;
-    iter17<S, A, NT, 3>(it + 3, nit, dir, a + 3 * dir, q, d, k, g, mx, my, nR, PR, LR, src, dst,
-                        rb, pb, vcol, vcol[3], own, shift, fx, flags, mom, xs);
+    iter17<S, A, NT, 3, SR>(it + 3, nit, dir, a + 3 * dir, q, d, k, g, mx, my, nR, PR, LR, src, dst,
+                        rb, pb, vcol, vcol[3], own, shift, fx, flags, mom, xs, rstep);
     q = q == 2 ? 0 : q + 1;
   }
 }
 
-template <typename S, typename A>
+template <typename S, typename A, bool SR>
 static hipError_t launch_t(int threads, int rows, const Desc17& d, int parity, int flags,
-                           double* mom, hipStream_t st) {
+                           double* mom, uint32_t rstep, hipStream_t st) {
   const int64_t strips = (d.Lx + threads - 5) / (threads - 4);
   const int64_t chunks = (d.Ly + rows - 1) / rows;
   if (strips * chunks > INT32_MAX) return hipErrorInvalidValue;
@@ -395,16 +408,20 @@ static hipError_t launch_t(int threads, int rows, const Desc17& d, int parity, i
   const K17<A> k = make_k17<A>(d);
   switch (threads) {
     case 64:
-      step17_kernel<S, A, 64><<<grid, 64, 0, st>>>(d, k, parity, rows, (int)chunks, flags, mom);
+      step17_kernel<S, A, 64, SR>
+          <<<grid, 64, 0, st>>>(d, k, parity, rows, (int)chunks, flags, mom, rstep);
       break;
     case 128:
-      step17_kernel<S, A, 128><<<grid, 128, 0, st>>>(d, k, parity, rows, (int)chunks, flags, mom);
+      step17_kernel<S, A, 128, SR>
+          <<<grid, 128, 0, st>>>(d, k, parity, rows, (int)chunks, flags, mom, rstep);
       break;
     case 256:
-      step17_kernel<S, A, 256><<<grid, 256, 0, st>>>(d, k, parity, rows, (int)chunks, flags, mom);
+      step17_kernel<S, A, 256, SR>
+          <<<grid, 256, 0, st>>>(d, k, parity, rows, (int)chunks, flags, mom, rstep);
       break;
     case 512:
-      step17_kernel<S, A, 512><<<grid, 512, 0, st>>>(d, k, parity, rows, (int)chunks, flags, mom);
+      step17_kernel<S, A, 512, SR>
+          <<<grid, 512, 0, st>>>(d, k, parity, rows, (int)chunks, flags, mom, rstep);
       break;
     default:
       return hipErrorInvalidValue;
@@ -412,11 +429,19 @@ static hipError_t launch_t(int threads, int rows, const Desc17& d, int parity, i
   return hipGetLastError();
 }
 
-hipError_t launch_step17(bool fp32, int threads, int rows, const Desc17& d, int parity, int flags,
-                         double* mom, hipStream_t st) {
+hipError_t launch_step17(int prec, int threads, int rows, const Desc17& d, int parity, int flags,
+                         double* mom, uint32_t rstep, hipStream_t st) {
   if (rows < 1) return hipErrorInvalidValue;
-  return fp32 ? launch_t<float, float>(threads, rows, d, parity, flags, mom, st)
-              : launch_t<double, double>(threads, rows, d, parity, flags, mom, st);
+  switch (prec) {
+    case 0:
+      return launch_t<double, double, false>(threads, rows, d, parity, flags, mom, rstep, st);
+    case 1:
+      return launch_t<float, float, false>(threads, rows, d, parity, flags, mom, rstep, st);
+    case 2:
+      return launch_t<float, double, true>(threads, rows, d, parity, flags, mom, rstep, st);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 // ---- initial state, checks, population transfer ---------------------------

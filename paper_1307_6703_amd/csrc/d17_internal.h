@@ -41,11 +41,13 @@ void lattice17(int cx[17], int cy[17], double w[17], double* s);
 double rest_weight17(int i, double T);
 
 // One time step over the whole lattice: strips of threads - 4 columns,
-// chunks of `rows` rows (one workgroup each, in XCD-aware order); reads S[parity], writes S[parity ^ 1]; with
-// kWriteMoments also n, ux, uy (FP64 planes) into mom. threads: 64, 128, 256
-// or 512.
-hipError_t launch_step17(bool fp32, int threads, int rows, const Desc17& d, int parity, int flags,
-                         double* mom, hipStream_t st);
+// chunks of `rows` rows (one workgroup each, in XCD-aware order); reads
+// S[parity], writes S[parity ^ 1]; with kWriteMoments also n, ux, uy (FP64
+// planes) into mom. threads: 64, 128, 256 or 512. prec (lb_params.fp32): 0
+// FP64; 1 FP32 storage and arithmetic; 2 FP32 storage, FP64 arithmetic and
+// stochastic rounding of the stored values with the draws of step rstep.
+hipError_t launch_step17(int prec, int threads, int rows, const Desc17& d, int parity, int flags,
+                         double* mom, uint32_t rstep, hipStream_t st);
 hipError_t launch_init17(bool fp32, const Desc17& d, int parity, const double* n0,
                          const double* ux, const double* uy, hipStream_t st);
 int reduce17_blocks(int64_t nn);

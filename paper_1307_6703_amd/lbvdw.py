@@ -351,16 +351,17 @@ def lattice17():
 class Lattice17:
     """One periodic D2Q17 lattice on the current GPU (include/lbd2q17.h):
     workspace tensor + lb17_handle. Parameters as for Lattice; y_periodic is
-    implied, U must be 0, fp32 is False/True."""
+    implied, U must be 0; fp32 as for Lattice (False, True or "sr")."""
 
     def __init__(self, Lx, Ly, *, T=0.95, tau=1.0, kappa=0.3, N=0.3, Q=2.0, fext=None,
                  fp32=False, check_every=0, drift_correct=False, device="cuda", stream=None):
         import torch
         lib = load_library()
         self.Lx, self.Ly = int(Lx), int(Ly)
-        self.fp32 = bool(fp32)
+        self.precision = precision(fp32)
+        self.fp32 = self.precision != FP64  # FP32 storage
         self._p, self._fext = make_params(Lx, Ly, T, tau, kappa, N, Q, 0.0, fext, True,
-                                          int(self.fp32), check_every, drift_correct, False)
+                                          self.precision, check_every, drift_correct, False)
         nbytes = ctypes.c_size_t()
         _check(lib.lb17_workspace_bytes(ctypes.byref(self._p), ctypes.byref(nbytes)))
         self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)

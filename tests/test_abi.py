@@ -170,7 +170,6 @@ def test_d2q17_workspace_and_lattice(lib):
     (dict(Lx=16, Ly=16, y_periodic=False), "periodic"),
     (dict(Lx=16, Ly=16, U=0.01), "U must be 0"),
     (dict(Lx=16, Ly=16, regularized=True), "BGK"),
-    (dict(Lx=16, Ly=16, fp32="sr"), "fp32"),
     (dict(Lx=16, Ly=3), "Ly"),
     (dict(Lx=16, Ly=16, tau=0.25), "tau"),
     (dict(Lx=8192, Ly=4096, fp32=True), "2 GiB"),
@@ -180,6 +179,17 @@ def test_d2q17_invalid_parameters_are_rejected(lib, kw, needle):
     st, _, msg = _bytes17(lib, **kw)
     assert st == lbvdw.LB_EINVAL
     assert needle in msg
+
+
+def test_d2q17_precision_field(lib):
+    for v in (0, 1, 2):
+        st, n, _ = _bytes17(lib, Lx=64, Ly=32, fp32=v)
+        assert st == 0 and n > 0
+    p, _ = lbvdw.make_params(Lx=64, Ly=32, y_periodic=True)
+    p.fp32 = 3
+    n = ctypes.c_size_t()
+    assert lib.lb17_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == lbvdw.LB_EINVAL
+    assert "fp32" in lib.lb_last_error().decode()
 
 
 def test_d2q17_create_checks_the_workspace_first(lib):

@@ -187,6 +187,14 @@ def batched_bench(steps: int, seed: int = 1307, launch=None):
            "launch": {"threads": th, "rows": rw, "steps_per_launch": b.steps_per_launch()},
            "unstable_instances": sum(1 for v in status if v != 0),
            "draws_replaced_unstable": replaced,
+           # 72 algorithmic bytes per node update; the two population buffers
+           # (2 x 36 B per node) exceed the 256 MB Infinity Cache, so the batch
+           # streams from HBM rather than running cache-resident
+           "algorithmic_gbs": round(BYTES_PER_UPDATE_FP32 * b.nodes * steps / (ms * 1e-3) / 1e9, 1),
+           "algorithmic_frac_of_peak": round(BYTES_PER_UPDATE_FP32 * b.nodes * steps /
+                                             (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "population_buffers_mb": round(2 * 36 * b.nodes / 1e6, 1),
+           "cache_resident": 2 * 36 * b.nodes < 256e6,
            "workload": "96 draws: Lx in {128..1024}, Ly in {64,128,256}, T in [0.85,0.98], "
                        "V0 in [0,0.02], k in {2,4,8}, U in [0,0.08], FP32"}
     b.close()

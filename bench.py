@@ -297,7 +297,7 @@ def d2q17_bench(steps: int, check_every: int):
                        "steps_per_launch": 1},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "kernel": "step17_kernel<float, float, %d>" % threads,
+                         "kernel": "step17_kernel<float, float, %d, false>" % threads,
                          "us_per_launch": round(k_ms * 1e3, 2), "bytes_per_update": bpu},
             "mass_drift": abs(red["mass"] - m0) / m0, "nmin": red["nmin"], "nmax": red["nmax"],
             "fp32_storage_fp64_arithmetic_sr": {

@@ -118,6 +118,14 @@ lb_status lb17_set_populations(lb17_handle* h, const double* f, int64_t step);
 lb_status lb17_set_launch(lb17_handle* h, int32_t threads, int32_t rows);
 lb_status lb17_get_launch(lb17_handle* h, int32_t* threads, int32_t* rows, int32_t* blocks);
 
+/* Time nsteps steps of each candidate launch shape, pick the fastest and
+ * apply it; return it (ms_per_step may be NULL). The timed steps are real
+ * steps: the lattice advances by nsteps plus one warm-up step per candidate,
+ * with the periodic checks that fall in them. The launch shape never changes
+ * results. Synchronises. */
+lb_status lb17_autotune(lb17_handle* h, int32_t nsteps, int32_t* threads, int32_t* rows,
+                        double* ms_per_step);
+
 /* Steps taken since the last init / set_populations plus the restored count. */
 lb_status lb17_get_step(lb17_handle* h, int64_t* step);
 

@@ -186,6 +186,28 @@ void fill_desc(lb17_handle* h, char* ws, const Layout17& L) {
   d.h3 = s * s * s / 6.0;
 }
 
+// nsteps steps in the current launch shape; the last one writes the moments.
+lb_status step_impl17(lb17_handle* h, int64_t nsteps) {
+  int threads, rows;
+  launch_shape(h, &threads, &rows);
+  for (int64_t k = 0; k < nsteps; ++k) {
+    int flags = (k == nsteps - 1) ? d17k::kWriteMoments : 0;
+    if (h->pending_shift) flags |= d17k::kApplyShift;
+    HIPCHK(d17k::launch_step17(h->prec, threads, rows, h->d, h->parity, flags, h->mom,
+                               (uint32_t)h->step, h->st));
+    h->parity ^= 1;
+    h->pending_shift = false;
+    h->step += 1;
+    if (h->p.check_every > 0 && h->step % h->p.check_every == 0) {
+      lb_status r = enqueue_check(h, 0);
+      if (r != LB_OK) return r;
+      h->pending_shift = h->p.drift_correct && h->fp32;
+    }
+  }
+  if (nsteps > 0) h->moments_valid = true;
+  return LB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -276,24 +298,7 @@ lb_status lb17_step_n(lb17_handle* h, int64_t nsteps) {
   if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
   if (!h->has_state) return fail(LB_ESTATE, "lattice has no state");
   if (h->unstable) return fail(LB_ESTATE, "a stability check failed; restart the lattice");
-  int threads, rows;
-  launch_shape(h, &threads, &rows);
-  for (int64_t k = 0; k < nsteps; ++k) {
-    int flags = (k == nsteps - 1) ? d17k::kWriteMoments : 0;
-    if (h->pending_shift) flags |= d17k::kApplyShift;
-    HIPCHK(d17k::launch_step17(h->prec, threads, rows, h->d, h->parity, flags, h->mom,
-                               (uint32_t)h->step, h->st));
-    h->parity ^= 1;
-    h->pending_shift = false;
-    h->step += 1;
-    if (h->p.check_every > 0 && h->step % h->p.check_every == 0) {
-      lb_status r = enqueue_check(h, 0);
-      if (r != LB_OK) return r;
-      h->pending_shift = h->p.drift_correct && h->fp32;
-    }
-  }
-  if (nsteps > 0) h->moments_valid = true;
-  return LB_OK;
+  return step_impl17(h, nsteps);
 }
 
 lb_status lb17_get_moments(lb17_handle* h, double* n, double* ux, double* uy) {
@@ -382,6 +387,63 @@ lb_status lb17_get_launch(lb17_handle* h, int32_t* threads, int32_t* rows, int32
   if (threads) *threads = t;
   if (rows) *rows = r;
   if (blocks) *blocks = ((h->p.Lx + t - 5) / (t - 4)) * ((h->p.Ly + r - 1) / r);
+  return LB_OK;
+}
+
+lb_status lb17_autotune(lb17_handle* h, int32_t nsteps, int32_t* threads, int32_t* rows,
+                        double* ms_per_step) {
+  if (!h) return fail(LB_EINVAL, "handle is NULL");
+  if (nsteps < 1) return fail(LB_EINVAL, "nsteps must be >= 1");
+  if (!h->has_state) return fail(LB_ESTATE, "lattice has no state");
+  if (h->unstable) return fail(LB_ESTATE, "a stability check failed; restart the lattice");
+  // candidates: every strip width up to about twice the lattice width, and
+  // for each the default chunk height and a few fixed ones
+  std::vector<std::pair<int, int>> cand;
+  const int t0 = h->threads, r0 = h->rows;
+  for (int t : {64, 128, 256, 512}) {
+    if (t > 64 && h->p.Lx + 4 <= t / 2) continue;
+    h->threads = t;
+    h->rows = 0;
+    int dt, dr;
+    launch_shape(h, &dt, &dr);
+    std::vector<int> rs = {dr, 8, 16, 32, 64};
+    std::sort(rs.begin(), rs.end());
+    rs.erase(std::unique(rs.begin(), rs.end()), rs.end());
+    for (int rw : rs)
+      if (rw <= h->p.Ly) cand.push_back({t, rw});
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double best = 1e300;
+  int bt = t0, br = r0;
+  lb_status r = LB_OK;
+  for (const auto& c : cand) {
+    h->threads = c.first;
+    h->rows = c.second;
+    if ((r = step_impl17(h, 1)) != LB_OK) break;  // warm-up
+    if (hipEventRecord(e0, h->st) != hipSuccess) { r = fail(LB_EDEVICE, "event record failed"); break; }
+    if ((r = step_impl17(h, nsteps)) != LB_OK) break;
+    if (hipEventRecord(e1, h->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      r = fail(LB_EDEVICE, "event sync failed");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms / nsteps < best) {
+      best = ms / nsteps;
+      bt = c.first;
+      br = c.second;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->threads = bt;
+  h->rows = br;
+  if (r != LB_OK) return r;
+  if (threads) *threads = bt;
+  if (rows) *rows = br;
+  if (ms_per_step) *ms_per_step = best;
   return LB_OK;
 }
 

@@ -93,6 +93,7 @@ SIGNATURES = {
     "lb17_set_launch": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "lb17_get_launch": (ctypes.c_int, [_VP, _I32P, _I32P, _I32P]),
     "lb17_get_step": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64)]),
+    "lb17_autotune": (ctypes.c_int, [_VP, ctypes.c_int32, _I32P, _I32P, _DP]),
     "lb17_destroy": (ctypes.c_int, [_VP]),
     # include/lbsurrogate.h
     "lbs_param_count": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64)]),
@@ -418,6 +419,12 @@ class Lattice17:
         t, r, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(_lib.lb17_get_launch(self._h, ctypes.byref(t), ctypes.byref(r), ctypes.byref(b)))
         return t.value, r.value, b.value
+
+    def autotune(self, nsteps: int = 10):
+        t, r, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(_lib.lb17_autotune(self._h, int(nsteps), ctypes.byref(t), ctypes.byref(r),
+                                  ctypes.byref(ms)))
+        return t.value, r.value, ms.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

@@ -198,6 +198,17 @@ def test_stochastic_rounding_stays_with_fp64(torch_cuda, case):
     assert err["sr"] * 10 < err[1]
 
 
+def test_autotune_picks_a_shape_and_changes_no_bits(torch_cuda):
+    _say("d2q17 autotune")
+    g, _ = _pair(600, 200, fp32=True, oracle=False)
+    t, r, ms = g.autotune(nsteps=4)
+    assert t in (64, 128, 256, 512) and 1 <= r <= 200 and ms > 0
+    assert g.get_launch()[:2] == (t, r)
+    ref, _ = _pair(600, 200, fp32=True, oracle=False)
+    ref.step(g.step_count)
+    assert np.array_equal(g.populations(), ref.populations())
+
+
 def test_fp32_drift_correction_restores_the_mass(torch_cuda):
     _say("d2q17 fp32 drift correction")
     runs = {}

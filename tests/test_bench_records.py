@@ -35,3 +35,22 @@ def test_kernel_hash_ignores_comments_and_other_kernels(tmp_path, monkeypatch):
     assert bench.kernel_hash() == h0
     p.write_text(src[:cut].replace("const int u = t + 1;", "const int u = t + 2;") + src[cut:])
     assert bench.kernel_hash() != h0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU's throughput only: --gpus N > 1 exits with a message, before any
+    # device work
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one MI355X" in r.stderr
+
+
+def test_d2q17_workload_is_the_headline_lattice_periodic():
+    import lbsynth as ls
+    w, h = ls.D2Q17_WORKLOAD, ls.ROOFLINE
+    assert (w.Lx, w.Ly, w.T, w.V0, w.k, w.seed) == (h.Lx, h.Ly, h.T, h.V0, h.k, h.seed)
+    assert w.y_periodic and w.U == 0.0
+    assert bench.BYTES_PER_UPDATE_D2Q17_FP32 == 2 * 17 * 4

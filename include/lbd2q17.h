@@ -92,6 +92,11 @@ lb_status lb17_create(const lb_params* p, void* dev_ws, size_t ws_bytes, void* h
 lb_status lb17_init_lattice(lb17_handle* h, const double* n0, const double* ux0,
                             const double* uy0);
 
+/* Same, with the initial fields already in device memory (FP64, [Ly][Lx]);
+ * synchronises (the fields are checked on the host). */
+lb_status lb17_init_lattice_device(lb17_handle* h, const double* d_n0, const double* d_ux0,
+                                   const double* d_uy0);
+
 /* Enqueue nsteps >= 0 time steps (asynchronous). The moments of the last
  * step are kept for lb17_get_moments. */
 lb_status lb17_step_n(lb17_handle* h, int64_t nsteps);
@@ -100,6 +105,9 @@ lb_status lb17_step_n(lb17_handle* h, int64_t nsteps);
  * streaming, before collision); after lb17_init_lattice, the initial fields.
  * Host FP64 [Ly][Lx]; any may be NULL. Synchronises. */
 lb_status lb17_get_moments(lb17_handle* h, double* n, double* ux, double* uy);
+
+/* Same into device FP64 arrays (no synchronisation). */
+lb_status lb17_get_moments_device(lb17_handle* h, double* d_n, double* d_ux, double* d_uy);
 
 /* FP64 sums over the stored populations: out[0] mass, out[1..2] momentum,
  * out[3..4] min and max node density, out[5] non-finite nodes. Synchronises. */

@@ -293,6 +293,48 @@ lb_status lb17_init_lattice(lb17_handle* h, const double* n0, const double* ux0,
   return LB_OK;
 }
 
+lb_status lb17_init_lattice_device(lb17_handle* h, const double* d_n0, const double* d_ux0,
+                                   const double* d_uy0) {
+  if (!h) return fail(LB_EINVAL, "handle is NULL");
+  if (!d_n0) return fail(LB_EINVAL, "n0 is NULL");
+  const int64_t nn = nodes(h);
+  // stage the fields in the moment planes, then check them on the host
+  // (the bounds and the mean density)
+  HIPCHK(hipMemcpyAsync(h->mom, d_n0, nn * 8, hipMemcpyDeviceToDevice, h->st));
+  if (d_ux0) HIPCHK(hipMemcpyAsync(h->mom + nn, d_ux0, nn * 8, hipMemcpyDeviceToDevice, h->st));
+  else HIPCHK(hipMemsetAsync(h->mom + nn, 0, nn * 8, h->st));
+  if (d_uy0) HIPCHK(hipMemcpyAsync(h->mom + 2 * nn, d_uy0, nn * 8, hipMemcpyDeviceToDevice, h->st));
+  else HIPCHK(hipMemsetAsync(h->mom + 2 * nn, 0, nn * 8, h->st));
+  std::vector<double> n0(nn), u(2 * nn);
+  HIPCHK(hipMemcpyAsync(n0.data(), h->mom, nn * 8, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipMemcpyAsync(u.data(), h->mom + nn, 2 * nn * 8, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  double sum = 0.0;
+  for (int64_t k = 0; k < nn; ++k) {
+    if (!(n0[k] > 0.0 && n0[k] < 3.0)) return fail(LB_EINVAL, "n0[%lld] outside (0, 3)", (long long)k);
+    sum += n0[k];
+  }
+  for (int64_t k = 0; k < 2 * nn; ++k)
+    if (!std::isfinite(u[k])) return fail(LB_EINVAL, "initial velocity is not finite");
+  h->d.nbar = h->fp32 ? sum / (double)nn : 0.0;
+  h->parity = 0;
+  HIPCHK(d17k::launch_init17(h->fp32, h->d, 0, h->mom, h->mom + nn, h->mom + 2 * nn, h->st));
+  lb_status r = fresh_state(h, 0);
+  if (r != LB_OK) return r;
+  h->moments_valid = true;
+  return LB_OK;
+}
+
+lb_status lb17_get_moments_device(lb17_handle* h, double* d_n, double* d_ux, double* d_uy) {
+  if (!h) return fail(LB_EINVAL, "handle is NULL");
+  if (!h->moments_valid) return fail(LB_ESTATE, "no moments: init the lattice or take a step");
+  const int64_t nn = nodes(h);
+  if (d_n) HIPCHK(hipMemcpyAsync(d_n, h->mom, nn * 8, hipMemcpyDeviceToDevice, h->st));
+  if (d_ux) HIPCHK(hipMemcpyAsync(d_ux, h->mom + nn, nn * 8, hipMemcpyDeviceToDevice, h->st));
+  if (d_uy) HIPCHK(hipMemcpyAsync(d_uy, h->mom + 2 * nn, nn * 8, hipMemcpyDeviceToDevice, h->st));
+  return LB_OK;
+}
+
 lb_status lb17_step_n(lb17_handle* h, int64_t nsteps) {
   if (!h) return fail(LB_EINVAL, "handle is NULL");
   if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");

@@ -85,6 +85,8 @@ SIGNATURES = {
     "lb17_workspace_bytes": (ctypes.c_int, [_PP, ctypes.POINTER(ctypes.c_size_t)]),
     "lb17_create": (ctypes.c_int, [_PP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
     "lb17_init_lattice": (ctypes.c_int, [_VP, _DP, _DP, _DP]),
+    "lb17_init_lattice_device": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "lb17_get_moments_device": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "lb17_step_n": (ctypes.c_int, [_VP, ctypes.c_int64]),
     "lb17_get_moments": (ctypes.c_int, [_VP, _DP, _DP, _DP]),
     "lb17_reduce": (ctypes.c_int, [_VP, _DP]),
@@ -378,6 +380,13 @@ class Lattice17:
         return (self.Ly, self.Lx)
 
     def init(self, n0, ux0=None, uy0=None):
+        import torch
+        if isinstance(n0, torch.Tensor) and n0.is_cuda:
+            t = [None if a is None else a.to(torch.float64).contiguous() for a in (n0, ux0, uy0)]
+            self._keep = t
+            ptr = lambda a: None if a is None else ctypes.c_void_p(a.data_ptr())
+            _check(_lib.lb17_init_lattice_device(self._h, ptr(t[0]), ptr(t[1]), ptr(t[2])))
+            return self
         a = [_host(v, self.shape) for v in (n0, ux0, uy0)]
         _check(_lib.lb17_init_lattice(self._h, _dptr(a[0]), _dptr(a[1]), _dptr(a[2])))
         return self
@@ -390,6 +399,13 @@ class Lattice17:
         n, ux, uy = (np.empty(self.shape) for _ in range(3))
         _check(_lib.lb17_get_moments(self._h, _dptr(n), _dptr(ux), _dptr(uy)))
         return n, ux, uy
+
+    def moments_device(self):
+        import torch
+        out = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.workspace.device)
+        ptr = lambda k: ctypes.c_void_p(out[k].data_ptr())
+        _check(_lib.lb17_get_moments_device(self._h, ptr(0), ptr(1), ptr(2)))
+        return out
 
     def reduce(self):
         out = np.empty(6)

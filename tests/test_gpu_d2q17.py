@@ -198,6 +198,24 @@ def test_stochastic_rounding_stays_with_fp64(torch_cuda, case):
     assert err["sr"] * 10 < err[1]
 
 
+def test_device_init_and_moments_match_the_host_calls(torch_cuda):
+    _say("d2q17 device init")
+    import torch
+    from paper_1307_6703_amd import Lattice17
+    n0 = ls.noisy_density(160, 48, 5)
+    ux0 = 0.01 * np.sin(np.arange(160) / 7.0)[None, :].repeat(48, 0)
+    a = Lattice17(160, 48, fp32=True).init(n0, ux0)
+    b = Lattice17(160, 48, fp32=True).init(torch.from_numpy(n0).cuda(),
+                                           torch.from_numpy(ux0).cuda())
+    a.step(7)
+    b.step(7)
+    assert np.array_equal(a.populations(), b.populations())
+    m = b.moments_device()
+    torch.cuda.synchronize()
+    for x, y in zip(a.moments(), m.cpu().numpy()):
+        assert np.array_equal(x, y)
+
+
 def test_autotune_picks_a_shape_and_changes_no_bits(torch_cuda):
     _say("d2q17 autotune")
     g, _ = _pair(600, 200, fp32=True, oracle=False)

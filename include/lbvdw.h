@@ -103,7 +103,7 @@ typedef struct {
                              projection onto the Hermite polynomials of order
                              <= 2 (the space of Eq.(eqfunc) and
                              Eq.(forceterm)) before it relaxes, the step Sec. II
-                             names for tau != 1; one step per launch only    */
+                             names for tau != 1                               */
 } lb_params;
 
 typedef struct lb_handle lb_handle;

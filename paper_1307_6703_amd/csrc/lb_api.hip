@@ -66,7 +66,6 @@ lb_status set_tiles(lb_handle* h, int threads, int rows, int fuse = 1) {
   if (fuse == 2) {
     if (prec(h) != lbk::kFP32)
       return fail(LB_EINVAL, "two steps per launch need FP32 storage and arithmetic (fp32 = 1)");
-    if (h->p.collision != 0) return fail(LB_EINVAL, "two steps per launch need the BGK collision");
     if (!fused_threads_ok(threads))
       return fail(LB_EINVAL, "two steps per launch: threads must be 64, 128, 192 or 256 (got %d)", threads);
   } else if (threads != 64 && threads != 128 && threads != 256 && threads != 320 &&
@@ -133,7 +132,7 @@ lb_status step_impl(lb_handle* h, int64_t nsteps, bool moments_last) {
     if (moments_last && s + n == nsteps) flags |= lbk::kWriteMoments;
     if (h->pending_shift) flags |= lbk::kApplyShift;
     if (pair)
-      HIPCHK(lbk::launch_step2(h->threads, h->ddesc, h->dtiles, h->ntiles, h->parity,
+      HIPCHK(lbk::launch_step2(h->threads, h->p.collision != 0, h->ddesc, h->dtiles, h->ntiles, h->parity,
                                flags | (h->p.y_periodic ? lbk::kYPeriodic : lbk::kYWalls), h->st));
     else if (h->fuse == 2)
       HIPCHK(lbk::launch_step(prec(h), h->p.collision != 0, h->threads1, h->ddesc, h->dtiles1, h->ntiles1, h->parity,
@@ -243,7 +242,7 @@ lb_status lb_create(const lb_params* p, void* dev_ws, size_t ws_bytes, void* hip
   // nodes whose strips are mostly interior columns, else one step per launch;
   // 256-thread strips where their columns exceed Lx by at most 3% (wider
   // strips stream longer pieces of each row), else 128
-  if (prec_of(p) == lbk::kFP32 && p->collision == 0 && (int64_t)p->Lx * p->Ly >= ((int64_t)1 << 20) &&
+  if (prec_of(p) == lbk::kFP32 && (int64_t)p->Lx * p->Ly >= ((int64_t)1 << 20) &&
       p->Lx >= 256) {
     const int64_t cols256 = (int64_t)((p->Lx + 241) / 242) * 242;
     const int th = cols256 * 100 <= (int64_t)p->Lx * 103 ? 256 : 128;
@@ -472,7 +471,7 @@ lb_status lb_autotune(lb_handle* h, int32_t nsteps, int32_t* threads, int32_t* r
     for (int rw : rs)
       if (rw <= h->p.Ly) cand.push_back({t, rw, 1});
   }
-  if (prec(h) == lbk::kFP32 && h->p.collision == 0)
+  if (prec(h) == lbk::kFP32)
     for (int t : {64, 128, 192, 256}) {
       if (t > 128 && h->p.Lx + 14 <= t / 2) continue;
       std::vector<int> rs = {fused_default_rows(&h->p, t, 1), fused_default_rows(&h->p, t, 2), 32};

@@ -199,7 +199,6 @@ lb_status batch_tiles(lb_batch* b, int threads, int rows, int fuse = 1) {
   if (fuse == 2) {
     if (b->prec != lbk::kFP32)
       return fail(LB_EINVAL, "two steps per launch need FP32 storage and arithmetic (fp32 = 1)");
-    if (b->reg) return fail(LB_EINVAL, "two steps per launch need the BGK collision");
     if (!fused_threads_ok(threads))
       return fail(LB_EINVAL, "two steps per launch: threads must be 64, 128, 192 or 256 (got %d)", threads);
   } else if (threads != 64 && threads != 128 && threads != 256 && threads != 320 &&
@@ -261,7 +260,7 @@ lb_status enqueue_steps(lb_batch* b, int64_t n, bool moments_last, bool dry = fa
     if (b->pending_shift) flags |= lbk::kApplyShift;
     if (!dry) {
       if (pair)
-        HIPCHK(lbk::launch_step2(b->threads, b->ddesc, b->dtiles, b->ntiles, b->parity,
+        HIPCHK(lbk::launch_step2(b->threads, b->reg != 0, b->ddesc, b->dtiles, b->ntiles, b->parity,
                                  flags | b->yflags, b->st));
       else if (b->fuse == 2)
         HIPCHK(lbk::launch_step(b->prec, b->reg != 0, b->threads1, b->ddesc, b->dtiles1, b->ntiles1, b->parity,
@@ -595,7 +594,7 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t nsteps, int32_t* threads, int32
   for (int t : {128, 256, 512})
     for (int rw : {16, 32, 64, 128, 256})
       if (t != 512 || b->prec == lbk::kFP32) cand.push_back({t, rw, 1});
-  if (b->prec == lbk::kFP32 && !b->reg)
+  if (b->prec == lbk::kFP32)
     for (int t : {64, 128, 192, 256})
       for (int rw : {16, 32, 48, 64, 128, 256}) cand.push_back({t, rw, 2});
   hipEvent_t e0, e1;
@@ -728,7 +727,8 @@ lb_status lb_batch_step_subset(lb_batch* b, int64_t nsteps, const int32_t* mask)
       const int flags = (launch == launches - 1) ? lbk::kWriteMoments : 0;
       const int par = b->parity ^ (int)(launch & 1);
       if (kind == 2)
-        HIPCHK(lbk::launch_step2(th, b->ddesc, b->dsub, (int)t.size(), par, flags | b->yflags, b->st));
+        HIPCHK(lbk::launch_step2(th, b->reg != 0, b->ddesc, b->dsub, (int)t.size(), par,
+                                 flags | b->yflags, b->st));
       else
         HIPCHK(lbk::launch_step(b->prec, b->reg != 0, th, b->ddesc, b->dsub, (int)t.size(), par, flags, b->st));
     }

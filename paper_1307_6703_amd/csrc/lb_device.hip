@@ -424,7 +424,110 @@ __device__ __forceinline__ R slot_sum(const R v[9]) {
 // inside the walls (then the rows map as if periodic, which there is the
 // identity, and no wall rule applies: the same arithmetic on the same values
 // as the walls body, so the same bits); 0 read per lattice.
-template <int NT, bool MOM, int YB>
+// Regularised collision (Sec. II names the step that re-projects the
+// post-collision populations onto the Hermite space): the non-equilibrium
+// part h = g - geq is replaced by its projection onto the Hermite
+// polynomials of order <= 2 before it relaxes,
+//   g_i <- geq_i + (1 - omega) P[h]_i + F_i,
+//   P[h]_i = w_i [a0 + 3 a1.c_i + 9/2 a2 : (c_i c_i - I/3)],
+// a0 = sum h, a1 = sum h c, a2 = sum h (c c - I/3); geq and F as in collide,
+// formed separately here.
+template <typename R>
+struct CollReg {
+  R keep, oneT, s3;          // 1 - omega, 1 - T, 3 s
+  R wr0, wra, wrd;           // w^_i
+  R w0, wa, wd;              // w_i
+  R w0s, was, wds;           // w_i s
+};
+
+template <typename R>
+__device__ __forceinline__ CollReg<R> make_coll_reg(const Desc& d) {
+  CollReg<R> c;
+  const double s = 1.0 - 0.5 * d.omega;
+  c.keep = (R)(1.0 - d.omega);
+  c.oneT = (R)(1.0 - d.T);
+  c.s3 = (R)(3.0 * s);
+  c.wr0 = (R)rest_weight_hd(0, d.T);
+  c.wra = (R)rest_weight_hd(1, d.T);
+  c.wrd = (R)rest_weight_hd(5, d.T);
+  c.w0 = (R)(4.0 / 9.0);
+  c.wa = (R)(1.0 / 9.0);
+  c.wd = (R)(1.0 / 36.0);
+  c.w0s = (R)(4.0 / 9.0 * s);
+  c.was = (R)(1.0 / 9.0 * s);
+  c.wds = (R)(1.0 / 36.0 * s);
+  return c;
+}
+
+template <typename R>
+__device__ __forceinline__ void collide_reg(R g[9], const CollReg<R>& c, R n, R dn, R jx, R jy,
+                                            R rn, R Fx, R Fy, R dnx, R dny, R D) {
+  const R ux = jx * rn, uy = jy * rn;
+  const R usq = (R)1.5 * (ux * ux + uy * uy);
+  const R Xxx = (R)6 * ux * Fx + c.oneT * ((R)2 * ux * dnx + D);
+  const R Xyy = (R)6 * uy * Fy + c.oneT * ((R)2 * uy * dny + D);
+  const R Xxy = (R)3 * (ux * Fy + uy * Fx) + c.oneT * (ux * dny + uy * dnx);
+  const R trX = Xxx + Xyy;
+  // equilibrium deviations and forcing, by direction
+  R eq[9], fo[9];
+  eq[0] = c.wr0 * dn - c.w0 * (n * usq);
+  fo[0] = -c.w0s * ((R)0.5 * trX);
+  {
+    const R e = c.wra * dn + c.wa * (n * ((R)4.5 * ux * ux - usq)), a = (R)3 * c.wa * jx;
+    const R fs = c.was * (Xxx - (R)0.5 * Xyy), fa = c.wa * c.s3 * Fx;
+    eq[1] = e + a; eq[3] = e - a; fo[1] = fs + fa; fo[3] = fs - fa;
+  }
+  {
+    const R e = c.wra * dn + c.wa * (n * ((R)4.5 * uy * uy - usq)), a = (R)3 * c.wa * jy;
+    const R fs = c.was * (Xyy - (R)0.5 * Xxx), fa = c.wa * c.s3 * Fy;
+    eq[2] = e + a; eq[4] = e - a; fo[2] = fs + fa; fo[4] = fs - fa;
+  }
+  {
+    const R cu = ux + uy;
+    const R e = c.wrd * dn + c.wd * (n * ((R)4.5 * cu * cu - usq)), a = (R)3 * c.wd * (jx + jy);
+    const R fs = c.wds * (trX + (R)3 * Xxy), fa = c.wd * c.s3 * (Fx + Fy);
+    eq[5] = e + a; eq[7] = e - a; fo[5] = fs + fa; fo[7] = fs - fa;
+  }
+  {
+    const R cu = uy - ux;
+    const R e = c.wrd * dn + c.wd * (n * ((R)4.5 * cu * cu - usq)), a = (R)3 * c.wd * (jy - jx);
+    const R fs = c.wds * (trX - (R)3 * Xxy), fa = c.wd * c.s3 * (Fy - Fx);
+    eq[6] = e + a; eq[8] = e - a; fo[6] = fs + fa; fo[8] = fs - fa;
+  }
+  R h[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) h[i] = g[i] - eq[i];
+  const R a0 = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+  const R a1x = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
+  const R a1y = (h[2] - h[4]) + (h[5] - h[8]) + (h[6] - h[7]);
+  const R dg = (h[5] + h[6]) + (h[7] + h[8]);
+  const R a2xx = (h[1] + h[3]) + dg - a0 * (R)(1.0 / 3.0);
+  const R a2yy = (h[2] + h[4]) + dg - a0 * (R)(1.0 / 3.0);
+  const R a2xy = (h[5] - h[6]) + (h[7] - h[8]);
+  // P[h] by direction, times 1 - omega: w_i [a0 + 3 a1.c + 9/2 a2:(cc - I/3)]
+  const R k0 = c.keep * c.w0, ka = c.keep * c.wa, kd = c.keep * c.wd;
+  g[0] = eq[0] + k0 * (a0 - (R)1.5 * (a2xx + a2yy)) + fo[0];
+  {
+    const R s = a0 + (R)3 * a2xx - (R)1.5 * a2yy, t = (R)3 * a1x;
+    g[1] = eq[1] + ka * (s + t) + fo[1];
+    g[3] = eq[3] + ka * (s - t) + fo[3];
+  }
+  {
+    const R s = a0 + (R)3 * a2yy - (R)1.5 * a2xx, t = (R)3 * a1y;
+    g[2] = eq[2] + ka * (s + t) + fo[2];
+    g[4] = eq[4] + ka * (s - t) + fo[4];
+  }
+  {
+    const R s = a0 + (R)3 * (a2xx + a2yy), x9 = (R)9 * a2xy;
+    const R t5 = (R)3 * (a1x + a1y), t6 = (R)3 * (a1y - a1x);
+    g[5] = eq[5] + kd * (s + x9 + t5) + fo[5];
+    g[7] = eq[7] + kd * (s + x9 - t5) + fo[7];
+    g[6] = eq[6] + kd * (s - x9 + t6) + fo[6];
+    g[8] = eq[8] + kd * (s - x9 - t6) + fo[8];
+  }
+}
+
+template <int NT, bool MOM, int YB, bool REG>
 __device__ __forceinline__ void step2_tile(const Desc& __restrict__ d, const Tile& tile, int dir,
                                            int parity, int flags, float (&nR)[8][NT + 2],
                                            Pair<float> (&LP)[4][NT + 2], Mom<float> (&JR)[4][NT + 2],
@@ -440,6 +543,7 @@ __device__ __forceinline__ void step2_tile(const Desc& __restrict__ d, const Til
   const __amdgpu_buffer_rsrc_t Snone = make_rsrc(d.S[parity ^ 1], 0);
   const R* __restrict__ fext3 = (const R*)d.fext3;
   const Coll<R> cl = make_coll<R>(d);
+  const CollReg<R> clr = make_coll_reg<R>(d);
   const Sten<R> c = make_sten<R>(d, dir);
   R shift = (R)0;
   if ((flags & kApplyShift) && d.shift) shift = (R)(*d.shift);
@@ -662,7 +766,10 @@ __device__ __forceinline__ void step2_tile(const Desc& __restrict__ d, const Til
         const R rn1 = fast_rcp<R>(n1);
         const int wall1 = periodic ? 0 : (dd1 == 0 ? 1 : (dd1 == Ly - 1 ? 2 : 0));
         stage_wall<R>(g1, wall1, dn1, n1, Fx1, Fy1, c);
-        collide<R>(g1, cl, n1, dn1, m1.jx, m1.jy, rn1, Fx1, Fy1, dnx1, dny1, D1);
+        if constexpr (REG)
+          collide_reg<R>(g1, clr, n1, dn1, m1.jx, m1.jy, rn1, Fx1, Fy1, dnx1, dny1, D1);
+        else
+          collide<R>(g1, cl, n1, dn1, m1.jx, m1.jy, rn1, Fx1, Fy1, dnx1, dny1, D1);
         R* o = &O[(s + 2) & 3][0][0];
         constexpr int ps = NT + 2;
         o[0 * ps + u] = g1[1];
@@ -702,7 +809,10 @@ __device__ __forceinline__ void step2_tile(const Desc& __restrict__ d, const Til
           uy2 = m2.jy * rn2;
           const int wall2 = periodic ? 0 : (dd2 == 0 ? 1 : (dd2 == Ly - 1 ? 2 : 0));
           stage_wall<R>(g2, wall2, dn2, n2, Fx2, Fy2, c);
-          collide<R>(g2, cl, n2, dn2, m2.jx, m2.jy, rn2, Fx2, Fy2, dnx2, dny2, D2);
+          if constexpr (REG)
+            collide_reg<R>(g2, clr, n2, dn2, m2.jx, m2.jy, rn2, Fx2, Fy2, dnx2, dny2, D2);
+          else
+            collide<R>(g2, cl, n2, dn2, m2.jx, m2.jy, rn2, Fx2, Fy2, dnx2, dny2, D2);
         }
         // output rows lie in [0, Ly) (y0 .. y1-1 of the tile), periodic or not
         const __amdgpu_buffer_rsrc_t so = valid2 ? Sout : Snone;
@@ -728,7 +838,7 @@ __device__ __forceinline__ void step2_tile(const Desc& __restrict__ d, const Til
 // YB: 1 every lattice of the launch has walls (tiles whose pipeline stays at
 // least one row inside the walls take the wall-free body), 2 every lattice is
 // periodic in y, 0 read per lattice.
-template <int NT, bool MOM, int YB>
+template <int NT, bool MOM, int YB, bool REG>
 __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ descs,
                                                       const Tile* __restrict__ tiles, int ntiles,
                                                       int parity, int flags) {
@@ -757,42 +867,49 @@ __global__ __launch_bounds__(NT, 2) void step2_kernel(const Desc* __restrict__ d
   // [1, Ly - 2], so none is a wall or ghost row and their pulls read rows
   // 0 .. Ly - 1 as they are
   if (YB == 1 && NT == 256 && tile.y0 >= 8 && tile.y1 <= d.Ly - 8)
-    step2_tile<NT, MOM, 2>(d, tile, dir, parity, flags, nR, LP, JR, nR2, LP2, JR2, O);
+    step2_tile<NT, MOM, 2, REG>(d, tile, dir, parity, flags, nR, LP, JR, nR2, LP2, JR2, O);
   else
-    step2_tile<NT, MOM, YB>(d, tile, dir, parity, flags, nR, LP, JR, nR2, LP2, JR2, O);
+    step2_tile<NT, MOM, YB, REG>(d, tile, dir, parity, flags, nR, LP, JR, nR2, LP2, JR2, O);
 }
 
-template <int NT, int YB>
+template <int NT, int YB, bool REG>
 static void launch_step2_y(const Desc* dd, const Tile* dt, int ntiles, int parity, int flags,
                            hipStream_t st) {
   if (flags & kWriteMoments)
-    hipLaunchKernelGGL((step2_kernel<NT, true, YB>), dim3(ntiles), dim3(NT), 0, st, dd, dt,
+    hipLaunchKernelGGL((step2_kernel<NT, true, YB, REG>), dim3(ntiles), dim3(NT), 0, st, dd, dt,
                        ntiles, parity, flags);
   else
-    hipLaunchKernelGGL((step2_kernel<NT, false, YB>), dim3(ntiles), dim3(NT), 0, st, dd, dt,
+    hipLaunchKernelGGL((step2_kernel<NT, false, YB, REG>), dim3(ntiles), dim3(NT), 0, st, dd, dt,
                        ntiles, parity, flags);
 }
 
-template <int NT>
+template <int NT, bool REG>
 static hipError_t launch_step2_t(const Desc* dd, const Tile* dt, int ntiles, int parity,
                                  int flags, hipStream_t st) {
   if (flags & kYWalls)
-    launch_step2_y<NT, 1>(dd, dt, ntiles, parity, flags, st);
+    launch_step2_y<NT, 1, REG>(dd, dt, ntiles, parity, flags, st);
   else if (flags & kYPeriodic)
-    launch_step2_y<NT, 2>(dd, dt, ntiles, parity, flags, st);
+    launch_step2_y<NT, 2, REG>(dd, dt, ntiles, parity, flags, st);
   else
-    launch_step2_y<NT, 0>(dd, dt, ntiles, parity, flags, st);
+    launch_step2_y<NT, 0, REG>(dd, dt, ntiles, parity, flags, st);
   return hipGetLastError();
 }
 
-hipError_t launch_step2(int threads, const Desc* d_descs, const Tile* d_tiles, int ntiles,
-                        int parity, int flags, hipStream_t stream) {
-  if (ntiles <= 0) return hipSuccess;
-  if (threads == 64) return launch_step2_t<64>(d_descs, d_tiles, ntiles, parity, flags, stream);
-  if (threads == 128) return launch_step2_t<128>(d_descs, d_tiles, ntiles, parity, flags, stream);
-  if (threads == 192) return launch_step2_t<192>(d_descs, d_tiles, ntiles, parity, flags, stream);
-  if (threads == 256) return launch_step2_t<256>(d_descs, d_tiles, ntiles, parity, flags, stream);
+template <bool REG>
+static hipError_t launch_step2_r(int threads, const Desc* d_descs, const Tile* d_tiles,
+                                 int ntiles, int parity, int flags, hipStream_t stream) {
+  if (threads == 64) return launch_step2_t<64, REG>(d_descs, d_tiles, ntiles, parity, flags, stream);
+  if (threads == 128) return launch_step2_t<128, REG>(d_descs, d_tiles, ntiles, parity, flags, stream);
+  if (threads == 192) return launch_step2_t<192, REG>(d_descs, d_tiles, ntiles, parity, flags, stream);
+  if (threads == 256) return launch_step2_t<256, REG>(d_descs, d_tiles, ntiles, parity, flags, stream);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_step2(int threads, bool reg, const Desc* d_descs, const Tile* d_tiles,
+                        int ntiles, int parity, int flags, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  return reg ? launch_step2_r<true>(threads, d_descs, d_tiles, ntiles, parity, flags, stream)
+             : launch_step2_r<false>(threads, d_descs, d_tiles, ntiles, parity, flags, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -822,109 +939,6 @@ using lbrng::draws14;
 using lbrng::pcg4d;
 using lbrng::round_stochastic;
 using lbrng::U4;
-
-// Regularised collision (Sec. II names the step that re-projects the
-// post-collision populations onto the Hermite space): the non-equilibrium
-// part h = g - geq is replaced by its projection onto the Hermite
-// polynomials of order <= 2 before it relaxes,
-//   g_i <- geq_i + (1 - omega) P[h]_i + F_i,
-//   P[h]_i = w_i [a0 + 3 a1.c_i + 9/2 a2 : (c_i c_i - I/3)],
-// a0 = sum h, a1 = sum h c, a2 = sum h (c c - I/3); geq and F as in collide,
-// formed separately here.
-template <typename R>
-struct CollReg {
-  R keep, oneT, s3;          // 1 - omega, 1 - T, 3 s
-  R wr0, wra, wrd;           // w^_i
-  R w0, wa, wd;              // w_i
-  R w0s, was, wds;           // w_i s
-};
-
-template <typename R>
-__device__ __forceinline__ CollReg<R> make_coll_reg(const Desc& d) {
-  CollReg<R> c;
-  const double s = 1.0 - 0.5 * d.omega;
-  c.keep = (R)(1.0 - d.omega);
-  c.oneT = (R)(1.0 - d.T);
-  c.s3 = (R)(3.0 * s);
-  c.wr0 = (R)rest_weight_hd(0, d.T);
-  c.wra = (R)rest_weight_hd(1, d.T);
-  c.wrd = (R)rest_weight_hd(5, d.T);
-  c.w0 = (R)(4.0 / 9.0);
-  c.wa = (R)(1.0 / 9.0);
-  c.wd = (R)(1.0 / 36.0);
-  c.w0s = (R)(4.0 / 9.0 * s);
-  c.was = (R)(1.0 / 9.0 * s);
-  c.wds = (R)(1.0 / 36.0 * s);
-  return c;
-}
-
-template <typename R>
-__device__ __forceinline__ void collide_reg(R g[9], const CollReg<R>& c, R n, R dn, R jx, R jy,
-                                            R rn, R Fx, R Fy, R dnx, R dny, R D) {
-  const R ux = jx * rn, uy = jy * rn;
-  const R usq = (R)1.5 * (ux * ux + uy * uy);
-  const R Xxx = (R)6 * ux * Fx + c.oneT * ((R)2 * ux * dnx + D);
-  const R Xyy = (R)6 * uy * Fy + c.oneT * ((R)2 * uy * dny + D);
-  const R Xxy = (R)3 * (ux * Fy + uy * Fx) + c.oneT * (ux * dny + uy * dnx);
-  const R trX = Xxx + Xyy;
-  // equilibrium deviations and forcing, by direction
-  R eq[9], fo[9];
-  eq[0] = c.wr0 * dn - c.w0 * (n * usq);
-  fo[0] = -c.w0s * ((R)0.5 * trX);
-  {
-    const R e = c.wra * dn + c.wa * (n * ((R)4.5 * ux * ux - usq)), a = (R)3 * c.wa * jx;
-    const R fs = c.was * (Xxx - (R)0.5 * Xyy), fa = c.wa * c.s3 * Fx;
-    eq[1] = e + a; eq[3] = e - a; fo[1] = fs + fa; fo[3] = fs - fa;
-  }
-  {
-    const R e = c.wra * dn + c.wa * (n * ((R)4.5 * uy * uy - usq)), a = (R)3 * c.wa * jy;
-    const R fs = c.was * (Xyy - (R)0.5 * Xxx), fa = c.wa * c.s3 * Fy;
-    eq[2] = e + a; eq[4] = e - a; fo[2] = fs + fa; fo[4] = fs - fa;
-  }
-  {
-    const R cu = ux + uy;
-    const R e = c.wrd * dn + c.wd * (n * ((R)4.5 * cu * cu - usq)), a = (R)3 * c.wd * (jx + jy);
-    const R fs = c.wds * (trX + (R)3 * Xxy), fa = c.wd * c.s3 * (Fx + Fy);
-    eq[5] = e + a; eq[7] = e - a; fo[5] = fs + fa; fo[7] = fs - fa;
-  }
-  {
-    const R cu = uy - ux;
-    const R e = c.wrd * dn + c.wd * (n * ((R)4.5 * cu * cu - usq)), a = (R)3 * c.wd * (jy - jx);
-    const R fs = c.wds * (trX - (R)3 * Xxy), fa = c.wd * c.s3 * (Fy - Fx);
-    eq[6] = e + a; eq[8] = e - a; fo[6] = fs + fa; fo[8] = fs - fa;
-  }
-  R h[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) h[i] = g[i] - eq[i];
-  const R a0 = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
-  const R a1x = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
-  const R a1y = (h[2] - h[4]) + (h[5] - h[8]) + (h[6] - h[7]);
-  const R dg = (h[5] + h[6]) + (h[7] + h[8]);
-  const R a2xx = (h[1] + h[3]) + dg - a0 * (R)(1.0 / 3.0);
-  const R a2yy = (h[2] + h[4]) + dg - a0 * (R)(1.0 / 3.0);
-  const R a2xy = (h[5] - h[6]) + (h[7] - h[8]);
-  // P[h] by direction, times 1 - omega: w_i [a0 + 3 a1.c + 9/2 a2:(cc - I/3)]
-  const R k0 = c.keep * c.w0, ka = c.keep * c.wa, kd = c.keep * c.wd;
-  g[0] = eq[0] + k0 * (a0 - (R)1.5 * (a2xx + a2yy)) + fo[0];
-  {
-    const R s = a0 + (R)3 * a2xx - (R)1.5 * a2yy, t = (R)3 * a1x;
-    g[1] = eq[1] + ka * (s + t) + fo[1];
-    g[3] = eq[3] + ka * (s - t) + fo[3];
-  }
-  {
-    const R s = a0 + (R)3 * a2yy - (R)1.5 * a2xx, t = (R)3 * a1y;
-    g[2] = eq[2] + ka * (s + t) + fo[2];
-    g[4] = eq[4] + ka * (s - t) + fo[4];
-  }
-  {
-    const R s = a0 + (R)3 * (a2xx + a2yy), x9 = (R)9 * a2xy;
-    const R t5 = (R)3 * (a1x + a1y), t6 = (R)3 * (a1y - a1x);
-    g[5] = eq[5] + kd * (s + x9 + t5) + fo[5];
-    g[7] = eq[7] + kd * (s + x9 - t5) + fo[7];
-    g[6] = eq[6] + kd * (s - x9 + t6) + fo[6];
-    g[8] = eq[8] + kd * (s - x9 - t6) + fo[8];
-  }
-}
 
 // Rows of populations in flight ahead of stage A, and the waves per SIMD the
 // register budget is sized for (FP32; FP64 always sizes for one wave). Two

@@ -52,10 +52,11 @@ enum Prec : int { kFP64 = 0, kFP32 = 1, kFP32SR = 2 };
 // prec the kernel; reg the regularised collision (every listed lattice).
 hipError_t launch_step(int prec, bool reg, int threads, const Desc* d_descs, const Tile* d_tiles,
                        int ntiles, int parity, int flags, hipStream_t stream);
-// Two steps per launch (FP32 only; threads 64, 128, 192 or 256): tiles of
-// threads-14 columns, reads S[parity], writes S[parity ^ 1].
-hipError_t launch_step2(int threads, const Desc* d_descs, const Tile* d_tiles, int ntiles,
-                        int parity, int flags, hipStream_t stream);
+// Two steps per launch (FP32 only; threads 64, 128, 192 or 256; reg the
+// regularised collision): tiles of threads-14 columns, reads S[parity],
+// writes S[parity ^ 1].
+hipError_t launch_step2(int threads, bool reg, const Desc* d_descs, const Tile* d_tiles,
+                        int ntiles, int parity, int flags, hipStream_t stream);
 hipError_t launch_init(bool fp32, const Desc* d_desc, int parity, const double* d_n0,
                        const double* d_ux, const double* d_uy, int64_t nn, hipStream_t stream);
 // Per-block partial sums over S[parity] (nb = reduce_blocks(nn) blocks).

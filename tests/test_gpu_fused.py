@@ -32,12 +32,13 @@ def torch_cuda():
     return torch
 
 
-def _lattice(Lx, Ly, periodic, seed, check_every=0, drift=False, U=0.03, V0=0.1, k=2, T=0.95):
+def _lattice(Lx, Ly, periodic, seed, check_every=0, drift=False, U=0.03, V0=0.1, k=2, T=0.95,
+             tau=1.0, regularized=False):
     from paper_1307_6703_amd import Lattice
     N, Q = ls.table1_nq(T)
-    g = Lattice(Lx, Ly, T=T, tau=1.0, kappa=0.3, N=N, Q=Q, U=0.0 if periodic else U,
+    g = Lattice(Lx, Ly, T=T, tau=tau, kappa=0.3, N=N, Q=Q, U=0.0 if periodic else U,
                 fext=ls.potential_force(Lx, V0, k), y_periodic=periodic, fp32=True,
-                check_every=check_every, drift_correct=drift)
+                check_every=check_every, drift_correct=drift, regularized=regularized)
     g.init(ls.noisy_density(Lx, Ly, seed))
     return g
 
@@ -83,6 +84,55 @@ def test_fused_equals_one_step_bitwise(torch_cuda, Lx, Ly, periodic, launch, ste
     for x, y in zip(a.moments(), b.moments()):
         assert np.array_equal(x, y)
     assert np.array_equal(a.populations(), b.populations())
+
+
+# the regularised collision (Sec. II's re-projection) in both kernels, at
+# tau = 1 and at tau = 2 where the projection changes most
+REG_CASES = [
+    (300, 70, False, (128, 8), 41, 2.0),
+    (300, 70, True, (128, 9), 40, 2.0),
+    (600, 100, False, (256, 24), 41, 1.0),
+    (600, 40, True, (256, 16), 20, 2.0),
+    (101, 37, True, (64, 17), 20, 2.0),
+    (1, 9, False, (128, 8), 14, 1.0),
+]
+
+
+@pytest.mark.parametrize("Lx,Ly,periodic,launch,steps,tau", REG_CASES)
+def test_regularised_fused_equals_one_step_bitwise(torch_cuda, Lx, Ly, periodic, launch, steps,
+                                                   tau):
+    _say("regularised fused vs one-step", Lx, Ly, periodic, launch, steps, tau)
+    a = _lattice(Lx, Ly, periodic, seed=Lx + 5 * Ly, tau=tau, regularized=True)
+    b = _lattice(Lx, Ly, periodic, seed=Lx + 5 * Ly, tau=tau, regularized=True)
+    b.set_launch(*launch, steps_per_launch=2)
+    assert b.steps_per_launch() == 2
+    a.step(steps)
+    b.step(steps)
+    for x, y in zip(a.moments(), b.moments()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+def test_regularised_fused_matches_oracle(torch_cuda):
+    w = ls.PARITY_FP64
+    _say("regularised fused fp32 vs oracle", w.name)
+    N, Q = ls.table1_nq(w.T)
+    from paper_1307_6703_amd import Lattice
+    fext = ls.potential_force(w.Lx, w.V0, w.k)
+    n0 = ls.noisy_density(w.Lx, w.Ly, w.seed)
+    g = Lattice(w.Lx, w.Ly, T=w.T, tau=2.0, kappa=0.3, N=N, Q=Q, U=w.U, fext=fext, fp32=True,
+                check_every=100, drift_correct=True, regularized=True)
+    g.set_launch(128, 0, steps_per_launch=2)
+    g.init(n0)
+    o = OracleLB(Params(w.Lx, w.Ly, T=w.T, tau=2.0, kappa=0.3, N=N, Q=Q, U=w.U,
+                        regularized=True), n0, fext=fext)
+    g.step(200)
+    o.run(200, threads=8)
+    n, ux, uy = g.moments()
+    rel = (np.abs(n - o.n) / o.n).max()
+    du = max(np.abs(ux - o.ux).max(), np.abs(uy - o.uy).max())
+    _say(f"max rel |dn| {rel:.2e}, max |du| {du:.2e}")
+    assert rel <= 1e-4 and du <= 1e-4
 
 
 def test_fused_with_checks_and_drift_shift(torch_cuda):
@@ -156,18 +206,19 @@ def _batch_instances():
     return out
 
 
-@pytest.mark.parametrize("check_every,launch", [(20, (128, 33)), (7, (256, 17)), (0, (192, 65)),
-                                                (20, (64, 40))])
-def test_batch_fused_equals_one_step_batch(torch_cuda, check_every, launch):
+@pytest.mark.parametrize("check_every,launch,reg", [(20, (128, 33), False), (7, (256, 17), False),
+                                                    (0, (192, 65), False), (20, (64, 40), False),
+                                                    (7, (128, 24), True)])
+def test_batch_fused_equals_one_step_batch(torch_cuda, check_every, launch, reg):
     # graph runs of 64 steps (32 launches), eager steps up to the check grid,
     # single steps before checks that split a pair, subset steps
     from paper_1307_6703_amd import Batch
-    _say("batch fused vs one-step", check_every, launch)
+    _say("batch fused vs one-step", check_every, launch, reg)
     insts = _batch_instances()
     specs = [{k: v for k, v in d.items() if k != "seed"} for d in insts]
     drift = check_every > 0
-    a = Batch(specs, fp32=True, check_every=check_every, drift_correct=drift)
-    b = Batch(specs, fp32=True, check_every=check_every, drift_correct=drift)
+    a = Batch(specs, fp32=True, check_every=check_every, drift_correct=drift, regularized=reg)
+    b = Batch(specs, fp32=True, check_every=check_every, drift_correct=drift, regularized=reg)
     for i, d in enumerate(insts):
         a.init(i, ls.noisy_density(d["Lx"], d["Ly"], d["seed"]))
         b.init(i, ls.noisy_density(d["Lx"], d["Ly"], d["seed"]))

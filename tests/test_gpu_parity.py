@@ -352,7 +352,7 @@ def test_regularised_parity_ragged(torch_cuda, Lx, Ly, periodic, launch):
     assert dn <= TOL64 and dux <= TOL64 and duy <= TOL64
 
 
-def test_regularised_is_not_bgk_and_rejects_two_steps(torch_cuda):
+def test_regularised_is_not_bgk_and_runs_two_steps_in_fp32_only(torch_cuda):
     from paper_1307_6703_amd import LBError
     _say("regularised vs bgk")
     a, _ = _pair(128, 32, U=0.03, V0=0.1, k=2, tau=2.0)
@@ -361,7 +361,10 @@ def test_regularised_is_not_bgk_and_rejects_two_steps(torch_cuda):
     b.step(50)
     assert np.abs(a.moments()[0] - b.moments()[0]).max() > 1e-8
     c, _ = _pair(300, 64, fp32=True, regularized=True)
+    c.set_launch(128, 0, steps_per_launch=2)
+    assert c.steps_per_launch() == 2
+    d, _ = _pair(300, 64, fp32=False, regularized=True)
     with pytest.raises(LBError):
-        c.set_launch(128, 0, steps_per_launch=2)
-    for g in (a, b, c):
+        d.set_launch(128, 0, steps_per_launch=2)
+    for g in (a, b, c, d):
         g.close()

@@ -19,6 +19,8 @@
 
 #include "sg_internal.h"
 
+#include <type_traits>
+
 namespace sg {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -334,6 +336,13 @@ hipError_t launch_conv(int ci, int co, int mode, const ConvArgs& a, int grid, hi
 // and the epilogue are conv_kernel's (W X^T, FP32 accumulation, bias, SiLU,
 // the residual from the layer's input, bf16 rounding), so the stack gives
 // the same bits as four FWD_RES launches.
+//
+// Within a step a wave takes its subtiles one after the other and runs the
+// epilogue of subtile m between the products of subtile m + 1 (one output
+// value per step of k, scheduling fences every two steps), so that its SiLU
+// (two transcendental operations per value) runs on the vector unit while the
+// matrix cores work; the body is compiled per role (subtile count, layer 4 or
+// not) so that it holds no branch the scheduler cannot cross.
 // ---------------------------------------------------------------------------
 constexpr int SK_RW = SK_ST + 8;        // ring pixels per row
 constexpr int SK_PX = 56;               // LDS pixel stride (elements)
@@ -391,73 +400,132 @@ __global__ __launch_bounds__(SK_NT) void stack_kernel(StackArgs a) {
   bf16* const rin = &ring[L - 1][0][0];
   bf16* const rout = &ring[L < 4 ? L : 0][0][0];
   constexpr int SLOT = SK_RW * SK_PX;
-  for (int t = 0; t < a.H + 8; ++t) {
-    if (tid < SK_LD) *(uint4*)&ring[0][t & 3][lpx * SK_PX + lch * 8] = pre;
-    pre = uint4{0u, 0u, 0u, 0u};
-    if (tid < SK_LD && t + 1 < a.H) pre = *(const uint4*)(xin + (int64_t)(t + 1) * a.W * 48);
 
-    const int y = t - 2 * L;
-    if (y < 0 || y >= a.H) {
-      if (L < 4) {  // the padding row: zeros over the wave's pixels
+  // The march, compiled per role (NM subtiles; LAST: layer 4, which stores
+  // to memory) so that a step's body has no branch: the epilogue of subtile
+  // m is interleaved with the products of subtile m + 1.
+  auto march = [&](auto nmc, auto lastc) {
+    constexpr int NM = decltype(nmc)::value;
+    constexpr bool LAST = decltype(lastc)::value;
+    for (int t = 0; t < a.H + 8; ++t) {
+      if (tid < SK_LD) *(uint4*)&ring[0][t & 3][lpx * SK_PX + lch * 8] = pre;
+      pre = uint4{0u, 0u, 0u, 0u};
+      if (tid < SK_LD && t + 1 < a.H) pre = *(const uint4*)(xin + (int64_t)(t + 1) * a.W * 48);
+
+      const int y = t - 2 * L;
+      if (y < 0 || y >= a.H) {
+        if (!LAST) {  // the padding row: zeros over the wave's pixels
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          if (m >= nm) continue;
-          const int c = cs[m] + lm;
-          if (c < wmin[m]) continue;
-          uint2* o = (uint2*)&rout[(y & 3) * SLOT + c * SK_PX + lg * 12];
-          o[0] = uint2{0u, 0u};
-          o[1] = uint2{0u, 0u};
-          o[2] = uint2{0u, 0u};
+          for (int m = 0; m < NM; ++m) {
+            const int c = cs[m] + lm;
+            if (c < wmin[m]) continue;
+            uint2* o = (uint2*)&rout[(y & 3) * SLOT + c * SK_PX + lg * 12];
+            o[0] = uint2{0u, 0u};
+            o[1] = uint2{0u, 0u};
+            o[2] = uint2{0u, 0u};
+          }
         }
-      }
-    } else {
-      f32x4 acc[3][3];
-#pragma unroll
-      for (int m = 0; m < 3; ++m)
-#pragma unroll
-        for (int ns = 0; ns < 3; ++ns) acc[m][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kc = 0; kc < SK_NKC; ++kc) {
-        // this lane's 8 consecutive k = 8 j (one tap): j = 6 tap + ci0 / 8
-        const int j = 4 * kc + lg;
-        const bool kv = j < 54;
-        const int tap = kv ? (j * 43) >> 8 : 0;   // j / 6 for j < 56
-        const int ci0 = kv ? 8 * (j - 6 * tap) : 0;
-        const int ty = (tap * 11) >> 5;           // tap / 3 for tap < 9
-        const int dy = ty - 1, dx = tap - 3 * ty - 1;
-        const bf16* src = rin + ((y + dy) & 3) * SLOT + (lm + dx) * SK_PX + ci0;
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          if (m >= nm) continue;
+      } else {
+        auto ldx = [&](int m, int kc) {
+          // this lane's 8 consecutive k = 8 j (one tap): j = 6 tap + ci0 / 8
+          const int j = 4 * kc + lg;
+          const bool kv = j < 54;
+          const int tap = kv ? (j * 43) >> 8 : 0;   // j / 6 for j < 56
+          const int ci0 = kv ? 8 * (j - 6 * tap) : 0;
+          const int ty = (tap * 11) >> 5;           // tap / 3 for tap < 9
+          const int dy = ty - 1, dx = tap - 3 * ty - 1;
+          const bf16* src = rin + ((y + dy) & 3) * SLOT + (lm + dx) * SK_PX + ci0;
           bf16x8 xfr = *(const bf16x8*)&src[cs[m] * SK_PX];
           if (!kv) xfr = bf16x8{};
+          return xfr;
+        };
+        // products of subtile m into acc (input fragments two steps of k ahead)
+        auto products = [&](int m, f32x4* acc) {
 #pragma unroll
-          for (int ns = 0; ns < 3; ++ns)
-            acc[m][ns] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[ns][kc], xfr, acc[m][ns], 0, 0, 0);
+          for (int ns = 0; ns < 3; ++ns) acc[ns] = f32x4{0.f, 0.f, 0.f, 0.f};
+          bf16x8 xa = ldx(m, 0), xb = ldx(m, 1);
+#pragma unroll
+          for (int kc = 0; kc < SK_NKC; ++kc) {
+            bf16x8 xn = bf16x8{};
+            if (kc + 2 < SK_NKC) xn = ldx(m, kc + 2);
+#pragma unroll
+            for (int ns = 0; ns < 3; ++ns)
+              acc[ns] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[ns][kc], xa, acc[ns], 0, 0, 0);
+            xa = xb;
+            xb = xn;
+          }
+        };
+        // epilogue of subtile m: bias, SiLU, residual, bf16; pixels the
+        // overlapping fifth subtile shares with the fourth are written twice,
+        // with the same bits
+        auto epilogue = [&](int m, const f32x4* acc) {
+          const int c = cs[m] + lm;
+          const bf16* rrow = rin + (y & 3) * SLOT + c * SK_PX + lg * 4;
+#pragma unroll
+          for (int ns = 0; ns < 3; ++ns) {
+            const bf16x4 rr = *(const bf16x4*)&rrow[ns * 16];
+            const f32x4 bv = *(const f32x4*)&sbias[L - 1][ns * 16 + lg * 4];
+            bf16x4 yo;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) yo[r] = f2bf(bf2f(rr[r]) + silu(acc[ns][r] + bv[r]));
+            if (!LAST)
+              *(bf16x4*)&rout[(y & 3) * SLOT + c * SK_PX + ns * 16 + lg * 4] = yo;
+            else
+              *(bf16x4*)(a.y + (((int64_t)img * a.H + y) * a.W + x0 + c - 4) * 48 + ns * 16 + lg * 4) = yo;
+          }
+        };
+        f32x4 acc[2][3];
+        products(0, acc[0]);
+        // the products of subtile m + 1 with the epilogue of subtile m in
+        // between, one output value per step of k (12 per lane), the order
+        // fixed by scheduling fences so that the matrix cores and the vector
+        // unit work side by side
+#pragma unroll
+        for (int m = 0; m + 1 < NM; ++m) {
+          f32x4* pa = acc[(m + 1) & 1];
+          const f32x4* ea = acc[m & 1];
+          const int c = cs[m] + lm;
+          const bf16* rrow = rin + (y & 3) * SLOT + c * SK_PX + lg * 4;
+          bf16x4 rr, yo;
+#pragma unroll
+          for (int ns = 0; ns < 3; ++ns) pa[ns] = f32x4{0.f, 0.f, 0.f, 0.f};
+          bf16x8 xa = ldx(m + 1, 0), xb = ldx(m + 1, 1);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int kc = 0; kc < SK_NKC; ++kc) {
+            bf16x8 xn = bf16x8{};
+            if (kc + 2 < SK_NKC) xn = ldx(m + 1, kc + 2);
+#pragma unroll
+            for (int ns = 0; ns < 3; ++ns)
+              pa[ns] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[ns][kc], xa, pa[ns], 0, 0, 0);
+            xa = xb;
+            xb = xn;
+            if (kc < 12) {
+              const int ns = kc >> 2, r = kc & 3;
+              if (r == 0) rr = *(const bf16x4*)&rrow[ns * 16];
+              const float b = sbias[L - 1][ns * 16 + lg * 4 + r];
+              yo[r] = f2bf(bf2f(rr[r]) + silu(ea[ns][r] + b));
+              if (r == 3) {
+                if (!LAST)
+                  *(bf16x4*)&rout[(y & 3) * SLOT + c * SK_PX + ns * 16 + lg * 4] = yo;
+                else
+                  *(bf16x4*)(a.y + (((int64_t)img * a.H + y) * a.W + x0 + c - 4) * 48 + ns * 16 + lg * 4) = yo;
+              }
+            }
+            if (kc & 1) __builtin_amdgcn_sched_barrier(0);
+          }
         }
+        epilogue(NM - 1, acc[(NM - 1) & 1]);
       }
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        if (m >= nm) continue;
-        const int c = cs[m] + lm;
-        if (c < wmin[m]) continue;
-        const bf16* rrow = rin + (y & 3) * SLOT + c * SK_PX + lg * 4;
-#pragma unroll
-        for (int ns = 0; ns < 3; ++ns) {
-          const bf16x4 rr = *(const bf16x4*)&rrow[ns * 16];
-          const f32x4 bv = *(const f32x4*)&sbias[L - 1][ns * 16 + lg * 4];
-          bf16x4 yo;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) yo[r] = f2bf(bf2f(rr[r]) + silu(acc[m][ns][r] + bv[r]));
-          if (L < 4)
-            *(bf16x4*)&rout[(y & 3) * SLOT + c * SK_PX + ns * 16 + lg * 4] = yo;
-          else
-            *(bf16x4*)(a.y + (((int64_t)img * a.H + y) * a.W + x0 + c - 4) * 48 + ns * 16 + lg * 4) = yo;
-        }
-      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
+  };
+  if (L == 4)
+    march(std::integral_constant<int, 2>{}, std::integral_constant<bool, true>{});
+  else if (nm == 3)
+    march(std::integral_constant<int, 3>{}, std::integral_constant<bool, false>{});
+  else
+    march(std::integral_constant<int, 2>{}, std::integral_constant<bool, false>{});
 }
 
 hipError_t launch_stack(const StackArgs& a, hipStream_t st) {

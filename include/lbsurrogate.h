@@ -122,7 +122,10 @@ lb_status lbs_pack(const float* d_w, int32_t cir, int32_t cor, int32_t CI, int32
  *   3 backward:    g = conv + res (res may be NULL); z = g (may be NULL),
  *                  y = g SiLU'(zprev)   (x holds dL/dz of the layer above and
  *                  the weights are packed transposed)
- * bias: FP32 [co] (first / residual) or [nout] (output), may be NULL.
+ * bias: FP32 [co] (first / residual) or [nout] (output), may be NULL; the
+ * backward mode takes NULL (a bias would be added to conv). The products
+ * accumulate in FP32 starting from the bias; in mode 1 the residual is added
+ * in the rounding of SiLU's product (one fused multiply-add).
  * The kernel is persistent: each workgroup walks 8-row x 64-column tiles
  * (stride: the grid). blocks caps the grid (0: one workgroup per tile, at
  * most as many as fit on the device at once; 1 <= blocks <= 4096 forces a

@@ -40,6 +40,8 @@ __device__ __forceinline__ float sigmoid(float z) {
   return __builtin_amdgcn_rcpf(1.0f + __expf(-z));
 }
 __device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
+// r + SiLU(z) with one rounding (the residual layers)
+__device__ __forceinline__ float silu_res(float z, float r) { return __builtin_fmaf(z, sigmoid(z), r); }
 __device__ __forceinline__ float silu_grad(float z) {
   const float s = sigmoid(z);
   return s * (1.0f + z * (1.0f - s));
@@ -162,11 +164,12 @@ __global__ __launch_bounds__(CNT) void conv_kernel(ConvArgs a) {
     // D = W X^T: the weights are the A operand (rows: output channels), the
     // input pixels the B operand, so lane (lm, lg) ends with channels
     // 16 ns + 4 lg .. +3 of pixel 16 ms + lm of the wave's row
+    // (the accumulators start from the bias)
     f32x4 acc[4][NS];
 #pragma unroll
     for (int ms = 0; ms < 4; ++ms)
 #pragma unroll
-      for (int ns = 0; ns < NS; ++ns) acc[ms][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int ns = 0; ns < NS; ++ns) acc[ms][ns] = f32x4{bv[ns][0], bv[ns][1], bv[ns][2], bv[ns][3]};
 
 #pragma unroll
     for (int kc = 0; kc < KP / 32; ++kc) {
@@ -205,9 +208,9 @@ __global__ __launch_bounds__(CNT) void conv_kernel(ConvArgs a) {
               const int xx = x0 + ms * 16 + lm;
               if (xx >= a.W) continue;
               float* p = a.yf + (((int64_t)img * a.H + h) * a.W + xx) * 3;
-              p[0] = acc[ms][0][0] + bv[0][0];
-              p[1] = acc[ms][0][1] + bv[0][1];
-              p[2] = acc[ms][0][2] + bv[0][2];
+              p[0] = acc[ms][0][0];
+              p[1] = acc[ms][0][1];
+              p[2] = acc[ms][0][2];
             }
           }
         } else {
@@ -221,7 +224,7 @@ __global__ __launch_bounds__(CNT) void conv_kernel(ConvArgs a) {
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const int co = ns * 16 + lg * 4 + r;
-                if (co < a.nout) a.yf[q * a.nout + co] = acc[ms][ns][r] + bv[ns][r];
+                if (co < a.nout) a.yf[q * a.nout + co] = acc[ms][ns][r];
               }
           }
         }
@@ -259,12 +262,12 @@ __global__ __launch_bounds__(CNT) void conv_kernel(ConvArgs a) {
           bf16x4 yo, zo;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const float v = acc[ms][ns][r] + bv[ns][r];
+            const float v = acc[ms][ns][r];
             if (MODE == FWD_FIRST) {
               yo[r] = f2bf(silu(v));
               zo[r] = f2bf(v);
             } else if (MODE == FWD_RES) {
-              yo[r] = f2bf(bf2f(rr[ms][ns][r]) + silu(v));
+              yo[r] = f2bf(silu_res(v, bf2f(rr[ms][ns][r])));
               zo[r] = f2bf(v);
             } else {  // BWD: v = dL/dh of this layer's input (+ the residual path)
               const float g = v + bf2f(rr[ms][ns][r]);
@@ -442,7 +445,7 @@ __global__ __launch_bounds__(SK_NT) void stack_kernel(StackArgs a) {
         // products of subtile m into acc (input fragments two steps of k ahead)
         auto products = [&](int m, f32x4* acc) {
 #pragma unroll
-          for (int ns = 0; ns < 3; ++ns) acc[ns] = f32x4{0.f, 0.f, 0.f, 0.f};
+          for (int ns = 0; ns < 3; ++ns) acc[ns] = *(const f32x4*)&sbias[L - 1][ns * 16 + lg * 4];
           bf16x8 xa = ldx(m, 0), xb = ldx(m, 1);
 #pragma unroll
           for (int kc = 0; kc < SK_NKC; ++kc) {
@@ -464,10 +467,9 @@ __global__ __launch_bounds__(SK_NT) void stack_kernel(StackArgs a) {
 #pragma unroll
           for (int ns = 0; ns < 3; ++ns) {
             const bf16x4 rr = *(const bf16x4*)&rrow[ns * 16];
-            const f32x4 bv = *(const f32x4*)&sbias[L - 1][ns * 16 + lg * 4];
             bf16x4 yo;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) yo[r] = f2bf(bf2f(rr[r]) + silu(acc[ns][r] + bv[r]));
+            for (int r = 0; r < 4; ++r) yo[r] = f2bf(silu_res(acc[ns][r], bf2f(rr[r])));
             if (!LAST)
               *(bf16x4*)&rout[(y & 3) * SLOT + c * SK_PX + ns * 16 + lg * 4] = yo;
             else
@@ -488,7 +490,7 @@ __global__ __launch_bounds__(SK_NT) void stack_kernel(StackArgs a) {
           const bf16* rrow = rin + (y & 3) * SLOT + c * SK_PX + lg * 4;
           bf16x4 rr, yo;
 #pragma unroll
-          for (int ns = 0; ns < 3; ++ns) pa[ns] = f32x4{0.f, 0.f, 0.f, 0.f};
+          for (int ns = 0; ns < 3; ++ns) pa[ns] = *(const f32x4*)&sbias[L - 1][ns * 16 + lg * 4];
           bf16x8 xa = ldx(m + 1, 0), xb = ldx(m + 1, 1);
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -503,8 +505,7 @@ __global__ __launch_bounds__(SK_NT) void stack_kernel(StackArgs a) {
             if (kc < 12) {
               const int ns = kc >> 2, r = kc & 3;
               if (r == 0) rr = *(const bf16x4*)&rrow[ns * 16];
-              const float b = sbias[L - 1][ns * 16 + lg * 4 + r];
-              yo[r] = f2bf(bf2f(rr[r]) + silu(ea[ns][r] + b));
+              yo[r] = f2bf(silu_res(ea[ns][r], bf2f(rr[r])));
               if (r == 3) {
                 if (!LAST)
                   *(bf16x4*)&rout[(y & 3) * SLOT + c * SK_PX + ns * 16 + lg * 4] = yo;

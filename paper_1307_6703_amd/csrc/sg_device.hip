@@ -114,8 +114,11 @@ __device__ __forceinline__ void conv_load_tile(uint4* pre, const bf16* x, const 
   }
 }
 
+// The first layer (8 input channels) is memory work: held to 128 VGPRs (four
+// waves per SIMD) so that two workgroups share a CU and keep twice the loads
+// in flight.
 template <int CI, int CO, int MODE>
-__global__ __launch_bounds__(CNT) void conv_kernel(ConvArgs a) {
+__global__ __launch_bounds__(CNT, CI == 8 && MODE == FWD_FIRST ? 4 : 1) void conv_kernel(ConvArgs a) {
   using S = ConvShape<CI, CO>;
   constexpr int KP = S::KP, NS = S::NS, PX = S::PX, WS = S::WS, TCOLS = S::TCOLS;
   constexpr int K = S::K;

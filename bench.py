@@ -494,7 +494,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": ("step2_kernel<%d>" if spl == 2 else "step_kernel<float, float, %d>") % threads,
+                     # template arguments as the trace names them: strip threads, moments
+                     # store, y boundary (1 walls, 2 periodic), regularised collision
+                     "kernel": ("step2_kernel<%d, false, %d, false>" % (threads, 2 if w.y_periodic else 1)
+                                if spl == 2 else "step_kernel<float, float, %d, false, false>" % threads),
                      "us_per_launch": round(k_ms * 1e3, 2),
                      "launches_timed": k_steps // spl,
                      "node_updates_per_launch": w.nodes * spl,

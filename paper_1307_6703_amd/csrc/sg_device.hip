@@ -64,7 +64,10 @@ __host__ __device__ constexpr int kpad() { return (9 * CI + 31) / 32 * 32; }
 template <int CI, int CO>
 struct ConvShape {
   static constexpr int K = 9 * CI, KP = kpad<CI>(), NS = CO / 16;
-  static constexpr int PX = CI + 8;   // LDS pixel stride (elements): conflict-free 16-byte reads
+  // LDS pixel stride (elements): padded for conflict-free 16-byte reads, except
+  // in the output layer (48 -> 16), whose unpadded tile (78 KB with the
+  // weights) lets two workgroups share a CU
+  static constexpr int PX = (CI == 48 && CO == 16) ? CI : CI + 8;
   static constexpr int WS = KP + 8;   // LDS weight row stride
   static constexpr int TCOLS = TW + 2, TROWS = TR + 2;
   static constexpr int CH = CI / 8;   // 16-byte chunks per input pixel
@@ -114,11 +117,12 @@ __device__ __forceinline__ void conv_load_tile(uint4* pre, const bf16* x, const 
   }
 }
 
-// The first layer (8 input channels) is memory work: held to 128 VGPRs (four
-// waves per SIMD) so that two workgroups share a CU and keep twice the loads
-// in flight.
+// The first and the output layer (8 input channels; 16 output channels) are
+// memory work: held to 128 VGPRs (four waves per SIMD) so that two workgroups
+// share a CU and keep twice the loads in flight.
 template <int CI, int CO, int MODE>
-__global__ __launch_bounds__(CNT, CI == 8 && MODE == FWD_FIRST ? 4 : 1) void conv_kernel(ConvArgs a) {
+__global__ __launch_bounds__(CNT, (CI == 8 && MODE == FWD_FIRST) || (CO == 16 && MODE == FWD_OUT) ? 4 : 1)
+void conv_kernel(ConvArgs a) {
   using S = ConvShape<CI, CO>;
   constexpr int KP = S::KP, NS = S::NS, PX = S::PX, WS = S::WS, TCOLS = S::TCOLS;
   constexpr int K = S::K;

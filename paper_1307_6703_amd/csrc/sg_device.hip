@@ -343,9 +343,9 @@ hipError_t launch_conv(int ci, int co, int mode, const ConvArgs& a, int grid, hi
 // the fourth; layer 4: 64 pixels in 2 + 2). The roles are dealt so that
 // waves w and w + 4 (the same SIMD when waves go to the SIMDs in turn) pair
 // a 3-subtile part with a 2-subtile one. The product, its k order
-// and the epilogue are conv_kernel's (W X^T, FP32 accumulation, bias, SiLU,
-// the residual from the layer's input, bf16 rounding), so the stack gives
-// the same bits as four FWD_RES launches.
+// and the epilogue are conv_kernel's (W X^T, FP32 accumulation starting from
+// the bias, SiLU with the residual from the layer's input added in one FMA,
+// bf16 rounding), so the stack gives the same bits as four FWD_RES launches.
 //
 // Within a step a wave takes its subtiles one after the other and runs the
 // epilogue of subtile m between the products of subtile m + 1 (one output
@@ -465,9 +465,9 @@ __global__ __launch_bounds__(SK_NT) void stack_kernel(StackArgs a) {
             xb = xn;
           }
         };
-        // epilogue of subtile m: bias, SiLU, residual, bf16; pixels the
-        // overlapping fifth subtile shares with the fourth are written twice,
-        // with the same bits
+        // epilogue of subtile m (the bias is in the accumulators): SiLU and
+        // residual, bf16; pixels the overlapping fifth subtile shares with the
+        // fourth are written twice, with the same bits
         auto epilogue = [&](int m, const f32x4* acc) {
           const int c = cs[m] + lm;
           const bf16* rrow = rin + (y & 3) * SLOT + c * SK_PX + lg * 4;

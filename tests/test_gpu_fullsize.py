@@ -112,3 +112,44 @@ def test_full_size_100_steps_on_exact_windows(fp32, tol, x0):
         assert rel.max() <= tol and du <= tol
     else:
         assert np.abs(n[:, gx] - on).max() <= tol and du <= tol
+
+
+_REG_WINDOWS = {}
+
+
+@pytest.mark.parametrize("x0", [4000])
+def test_full_size_regularised_two_step_on_exact_window(x0):
+    """The regularised collision on the full lattice in its default launch
+    (two steps per launch in FP32), 100 steps at tau = 2 (at tau = 1 the
+    projection has no effect), against an exact oracle window."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1307_6703_amd import Lattice
+    w = ls.ROOFLINE
+    tau = 2.0
+    n0, fext = w.n0(), w.fext()
+    if x0 not in _REG_WINDOWS:
+        cols = np.arange(x0 - WINDOW_HALF, x0 + WINDOW_HALF) % w.Lx
+        _say(f"regularised oracle window of {cols.size} columns at x0 = {x0}, {WINDOW_STEPS} steps")
+        o = OracleLB(Params(cols.size, w.Ly, T=w.T, tau=tau, kappa=w.kappa, N=w.N, Q=w.Q, U=w.U,
+                            regularized=True),
+                     np.ascontiguousarray(n0[:, cols]), fext=np.ascontiguousarray(fext[cols]))
+        o.run(WINDOW_STEPS)
+        _REG_WINDOWS[x0] = (cols, o)
+    cols, o = _REG_WINDOWS[x0]
+    _say("full size regularised", w.name, WINDOW_STEPS, "steps")
+    g = Lattice(w.Lx, w.Ly, T=w.T, tau=tau, kappa=w.kappa, N=w.N, Q=w.Q, U=w.U, fext=fext,
+                fp32=True, check_every=100, drift_correct=True, regularized=True)
+    assert g.steps_per_launch() == 2
+    g.init(n0).step(WINDOW_STEPS)
+    n, ux, uy = g.moments()
+    _say(f"launch {g.get_launch()}")
+    g.close()
+    keep = slice(WINDOW_HALF - WINDOW_KEEP, WINDOW_HALF + WINDOW_KEEP)
+    gx = cols[keep]
+    on, oux, ouy = o.n[:, keep], o.ux[:, keep], o.uy[:, keep]
+    rel = np.abs(n[:, gx] - on) / on
+    du = max(np.abs(ux[:, gx] - oux).max(), np.abs(uy[:, gx] - ouy).max())
+    _say(f"columns {gx[0]}..{gx[-1]}: max rel |dn| {rel.max():.2e}, max |du| {du:.2e}")
+    assert rel.max() <= 1e-4 and du <= 1e-4

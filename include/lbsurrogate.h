@@ -123,7 +123,7 @@ lb_status lbs_pack(const float* d_w, int32_t cir, int32_t cor, int32_t CI, int32
  *                  y = g SiLU'(zprev)   (x holds dL/dz of the layer above and
  *                  the weights are packed transposed)
  * bias: FP32 [co] (first / residual) or [nout] (output), may be NULL; the
- * backward mode takes NULL (a bias would be added to conv). The products
+ * backward mode takes none (LB_EINVAL otherwise). The products
  * accumulate in FP32 starting from the bias; in mode 1 the residual is added
  * in the rounding of SiLU's product (one fused multiply-add).
  * The kernel is persistent: each workgroup walks 8-row x 64-column tiles

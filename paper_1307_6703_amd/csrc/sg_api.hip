@@ -440,6 +440,7 @@ lb_status lbs_conv(int32_t mode, int32_t ci, int32_t co, const void* d_x, const 
   }
   if (mode == sg::FWD_RES && !d_res) return fail(LB_EINVAL, "residual mode needs res");
   if (mode == sg::BWD && !d_zprev) return fail(LB_EINVAL, "backward mode needs zprev");
+  if (mode == sg::BWD && d_bias) return fail(LB_EINVAL, "backward mode takes no bias");
   return conv(mode, ci, co, d_x, d_wpack, d_bias, d_res, d_zprev, d_y, d_z, d_yf, nout, B, H, W,
               (hipStream_t)hip_stream, blocks);
 }

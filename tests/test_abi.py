@@ -137,6 +137,11 @@ def test_surrogate_sizes_and_validation(lib):
     assert st == lbvdw.LB_EINVAL and "channel pair" in lib.lb_last_error().decode()
     st = lib.lbs_conv(7, 8, 48, None, None, None, None, None, None, None, None, 0, 1, 4, 4, 0, None)
     assert st == lbvdw.LB_EINVAL and "mode" in lib.lb_last_error().decode()
+    # a bias in the backward mode is refused on the host (placeholder pointers,
+    # never dereferenced: every check before it passes, none launches)
+    fake = ctypes.c_void_p(1 << 20)
+    st = lib.lbs_conv(3, 16, 48, fake, fake, fake, None, fake, fake, None, None, 0, 1, 4, 4, 0, None)
+    assert st == lbvdw.LB_EINVAL and "no bias" in lib.lb_last_error().decode()
     st = lib.lbs_wgrad(16, 48, 16, 48, None, None, 1, 4, 4, 1.0, None, 1, None, None, None)
     assert st == lbvdw.LB_EINVAL
     assert lib.lbs_create(1, 4, 4, 0, None, 0, None, None) == lbvdw.LB_EINVAL

@@ -244,7 +244,8 @@ lb_status lb_batch_set_launch(lb_batch* b, int32_t threads, int32_t rows);
 
 /* Two time steps per launch (fp32 = 1 only; LB_EINVAL otherwise).
  * A workgroup of threads (64, 128, 192 or 256; 0: 128) runs the step of
- * Eq.(evoleq) twice over a strip of threads - 14 columns and a y-chunk of
+ * Eq.(evoleq), with either collision (lb_params.collision), twice over a
+ * strip of threads - 14 columns and a y-chunk of
  * rows (0: a default height), keeping the first step's populations in LDS,
  * so the populations cross HBM once per two steps. Every node runs the same
  * arithmetic as with one step per launch, so results are the same bits.

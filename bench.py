@@ -233,8 +233,8 @@ def mode_bench(w, n0_dev, fext, prec: int, steps: int, check_every: int):
             "launch": {"threads": threads, "rows": rows, "workgroups": blocks, "steps_per_launch": 1},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "kernel": ("step_kernel<float, double, %d>" if prec == 2 else
-                                    "step_kernel<double, double, %d>") % threads,
+                         "kernel": ("step_kernel<float, double, %d, false, false>" if prec == 2 else
+                                    "step_kernel<double, double, %d, false, false>") % threads,
                          "us_per_launch": round(k_ms * 1e3, 2), "bytes_per_update": bpu},
             "nmin": red["nmin"], "nmax": red["nmax"]}
 
